@@ -1,0 +1,172 @@
+#!/usr/bin/env python
+"""Throughput of the ph-FT-AFQMC slice path on one MI355X: walker*slices per second.
+
+One step = one whole imaginary-time path (tau = 0 .. beta, all n slices) for every
+walker of the workload: per slice the force bias, the shifted propagator, the
+stabilised Green's function, ln det and the phaseless weight; QR stabilisation and
+the local energy at every stabilisation boundary and at slice n; then the weighted
+energy means.  Inputs (fields) are resident in HBM before the timed region.  Both
+precisions run on the same seeded fields; the mixed path's energy error is measured
+against the FP64 path on every walker, and `value` is the mixed throughput when that
+error is within 1e-6, else the FP64 throughput.  The FP64 oracle is timed on the
+host cores on a bounded sample of the same workload (`cpu_baseline`).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synthinputs as si  # noqa: E402
+
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+MIXED_E_TOL = 1e-6
+
+
+def _oracle_worker(args):
+    name, sidx, walker, n_run = args
+    from threadpoolctl import threadpool_limits
+    from oracle import ueg, path, energy
+    sd = si.WORKLOADS[name]["systems"][sidx]
+    s = ueg.UEGSystem(sd["n_elec"], sd["rs"], sd["theta"], sd["nmax2"], sd["dtau"], stab_every=sd["stab_every"])
+    z = si.walker_fields(si.system_seed(name, sidx), walker, s.n_slices, s.NQ)
+    with threadpool_limits(1):
+        t = time.time()
+        path.run_walker(s, z, energy_fn=energy.local_energy, stop_after=n_run)
+        return time.time() - t, min(n_run, s.n_slices)
+
+
+def cpu_baseline(name, seconds_target=12.0):
+    """Oracle throughput on the host: one walker per process, one BLAS thread each."""
+    from concurrent.futures import ProcessPoolExecutor
+    from oracle import ueg
+    sd = si.WORKLOADS[name]["systems"][0]
+    s = ueg.UEGSystem(sd["n_elec"], sd["rs"], sd["theta"], sd["nmax2"], sd["dtau"], stab_every=sd["stab_every"])
+    nproc = max(1, min(os.cpu_count() or 1, 16, sd["walkers"]))
+    # calibrate the slice count so that each process works for about seconds_target
+    dt1, n1 = _oracle_worker((name, 0, 0, 2))
+    n_run = int(max(2, min(s.n_slices, seconds_target / max(dt1 / n1, 1e-6))))
+    t = time.time()
+    with ProcessPoolExecutor(max_workers=nproc) as ex:
+        res = list(ex.map(_oracle_worker, [(name, 0, w, n_run) for w in range(nproc)]))
+    wall = time.time() - t
+    ws = sum(r[1] for r in res)
+    return {"value": ws / wall, "unit": "walker*slices/s", "cores": nproc, "kind": "oracle",
+            "sample": "%d walkers x first %d of %d slices of %s (one process and one BLAS thread per walker)"
+                      % (nproc, n_run, s.n_slices, name)}
+
+
+def run_precision(F, torch, systems, fields, steps, warmup):
+    ctx = F.Context(systems)
+    infos = [ctx.info(i) for i in range(len(systems))]
+    for _ in range(warmup):
+        ctx.reset()
+        ctx.propagate(fields)
+        for i in range(len(systems)):
+            ctx.energy(i)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.reset()
+        ctx.propagate(fields)
+        for i in range(len(systems)):
+            ctx.energy(i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile(False)
+    ws = sum(inf["n_walkers"] * inf["n_slices"] for inf in infos)
+    out = {"seconds": t1 - t0, "walker_slices_per_s": ws * steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
+           "profile_ms_per_step": {k: v[0] / steps for k, v in prof.items()},
+           "launches_per_step": {k: v[1] // steps for k, v in prof.items()}}
+    gemm_ms, gemm_n = prof["gemm"]
+    flops = sum(8.0 * inf["M"] ** 3 * inf["n_walkers"] * inf["n_slices"] for inf in infos) / (len(systems))
+    # algorithmic flops of one propagator GEMM launch: 8 M^3 per walker (one system)
+    inf0 = infos[0]
+    per_launch = 8.0 * inf0["M"] ** 3 * inf0["n_walkers"]
+    out["gemm_avg_ms"] = gemm_ms / max(gemm_n, 1)
+    out["gemm_tflops"] = per_launch / (out["gemm_avg_ms"] * 1e-3) / 1e12
+    energies = [ctx.energy(i)["local"].cpu().numpy() for i in range(len(systems))]
+    status = [ctx.energy(i)["status"].cpu().numpy() for i in range(len(systems))]
+    return ctx, out, energies, status
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ueg_n66_m171")
+    ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (walkers would shard "
+              "across GPUs with no per-slice communication); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2012_12228_amd as F
+    F.load_library()
+    wl = si.WORKLOADS[args.workload]
+    # field shapes (n slices, N_Q) from the library's own tables
+    fields = []
+    for i, sd in enumerate(wl["systems"]):
+        probe = F.Context([dict(sd, walkers=1)])
+        inf = probe.info()
+        probe.close()
+        f = si.fields(si.system_seed(args.workload, i), sd["walkers"], inf["n_slices"], inf["n_q"])
+        fields.append(torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    results = {}
+    precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    energies = {}
+    for p in precs:
+        systems = [dict(sd, precision=0 if p == "fp64" else 1) for sd in wl["systems"]]
+        ctx, out, en, st = run_precision(F, torch, systems, fields, args.steps, args.warmup)
+        results[p], energies[p] = out, (en, st)
+        del ctx
+        torch.cuda.empty_cache()
+    err = None
+    if "fp64" in energies and "mixed" in energies:
+        errs = []
+        for (a, sa), (b, sb) in zip(zip(*energies["fp64"]), zip(*energies["mixed"])):
+            ok = (sa == 0) & (sb == 0)
+            e12a, e12b = a[ok, 0] + a[ok, 1], b[ok, 0] + b[ok, 1]
+            errs.append(np.max(np.abs(e12b - e12a) / np.abs(e12a)))
+        err = float(max(errs))
+        results["mixed"]["max_rel_err_E1E2_vs_fp64"] = err
+    use = "mixed" if ("mixed" in results and err is not None and err <= MIXED_E_TOL) else precs[0]
+    if args.precision == "mixed":
+        use = "mixed"
+    r = results[use]
+    sd0 = wl["systems"][0]
+    prec_key = "f32" if use == "mixed" else "f64"
+    achieved = r["gemm_tflops"]
+    line = {
+        "metric": "walker*slices/s incl. stabilised G+energy, FP64 vs mixed at <=1e-6 rel error",
+        "value": r["walker_slices_per_s"], "unit": "walker*slices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64-fp32mfma+f64" if use == "mixed" else "f64",
+        "data": "synthetic (seeded N(0,1) auxiliary fields, free-electron trial)",
+        "config": {"workload": args.workload, "systems": [
+            {k: v for k, v in sd.items()} for sd in wl["systems"]], "precision_reported": use},
+        "roofline": {"bound": "mfma", "kernel": "propagator complex GEMM (%s MFMA)" % prec_key,
+                     "achieved": achieved, "peak": PEAK_TFLOPS[prec_key], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS[prec_key], "traffic": None,
+                     "avg_launch_ms": r["gemm_avg_ms"]},
+        "fp64": results.get("fp64"), "mixed": results.get("mixed"),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

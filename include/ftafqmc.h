@@ -1,0 +1,170 @@
+/*
+ * ftafqmc.h -- C ABI of the MI355X library for the imaginary-time slice path of
+ * phaseless finite-temperature AFQMC (ph-FT-AFQMC) on the uniform electron gas
+ * in a plane-wave basis (Lee, Morales, Malone, arXiv:2012.12228).
+ *
+ * What the library computes (per walker, batched over walkers):
+ *   - the slice propagator B = e^{-dtau/2 (H_1 - mu N)} e^{sqrt(dtau)(x - xbar).v}
+ *     e^{-dtau/2 (H_1 - mu N)} (Sec. "Finite-Temperature AFQMC", eq. B; the HS
+ *     operators of Sec. "Uniform Electron Gas": v = i A(Q)/sqrt2, i B(Q)/sqrt2);
+ *   - the optimal force bias xbar = -sqrt(dtau) <v> from P = I - G^T (Sec.
+ *     "Phaseless approximation");
+ *   - the constrained product A(tau_k) = B_T^{n-k} B_k ... B_1 (eq. Abrenda) kept
+ *     as a stratified Q D T factorisation (Sec. "Numerical Stabilization") and the
+ *     Green's function G = (I + A)^{-1} (eq. green) with ln det(I + A);
+ *   - the phaseless weight w <- |I| max(0, cos theta) (eq. import, eq. phimport,
+ *     eq. theta) with S = det(I + A_{k+1})^2 / det(I + A_k)^2;
+ *   - the local energy E_M + E_1 + E_2 with Hartree and exchange parts (Sec.
+ *     "Uniform Electron Gas", Gamma_Q and Lambda_Q) and the electron number.
+ *
+ * Conventions shared by every entry point:
+ *   - Spin-restricted: one M x M block per walker serves both spins; det(I + A)
+ *     enters squared and one-body expectation values carry a factor 2.
+ *   - Basis order: plane waves K = 2 pi n / L, integer n with |n|^2 <= nmax2,
+ *     sorted by |n|^2, then n_x, n_y, n_z ascending.  Momentum transfers Q are
+ *     all distinct nonzero K_i - K_j in the same order; query() reports N_Q.
+ *   - Fields: complex128 per walker, slice and momentum transfer, row-major
+ *     [W][n_slices][N_Q]; Re = field of A(Q), Im = field of B(Q), each meant to
+ *     be iid N(0,1) (the HS transform's Gaussian fields).
+ *   - Matrices handed out are row-major [W][M][M] with G_ij = <c_i c_j^+>.
+ *   - Memory: every device pointer is owned by the caller.  The library never
+ *     allocates device memory: all per-walker state and constant tables live in
+ *     one caller-provided device workspace of ftafqmc_workspace_bytes() bytes,
+ *     which must stay valid and untouched until ftafqmc_destroy().  The handle
+ *     itself is host memory owned by the library.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Every call only enqueues work on it; results are ready when the stream is.
+ *   - Errors: functions return an ftafqmc_status; nothing throws or aborts.
+ *     ftafqmc_last_error() gives a message.  Numerical failure of one walker
+ *     (non-finite G, failed stabilisation) is reported in that walker's status
+ *     word, not as a call error.
+ *   - Threads: a handle must not be used from two threads at once.
+ */
+#ifndef FTAFQMC_H
+#define FTAFQMC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ftafqmc_ctx* ftafqmc_t;
+
+typedef enum {
+  FTAFQMC_OK = 0,
+  FTAFQMC_E_ARG = -1,         /* invalid argument (sizes, NULL pointer, parameter range) */
+  FTAFQMC_E_HIP = -2,         /* a HIP runtime call failed */
+  FTAFQMC_E_NUMERIC = -3,     /* every walker of a system failed numerically */
+  FTAFQMC_E_STATE = -4,       /* call not valid in the handle's current state */
+  FTAFQMC_E_UNSUPPORTED = -5  /* requested feature not built */
+} ftafqmc_status;
+
+/* precision of the propagator GEMM chain */
+enum { FTAFQMC_FP64 = 0, FTAFQMC_MIXED = 1 };
+/* per-walker status word */
+enum { FTAFQMC_WALKER_ALIVE = 0, FTAFQMC_WALKER_KILLED = 1, FTAFQMC_WALKER_NUMERIC = 2 };
+/* dtype codes for ftafqmc_greens */
+enum { FTAFQMC_C128 = 0, FTAFQMC_C64 = 1 };
+
+/* One UEG system (Sec. "Computational Details"): N, r_s, Theta = T/T_F, basis
+ * cutoff, time step; plus the walker batch and the stabilisation interval. */
+typedef struct {
+  int n_elec;      /* N-bar: even, >= 2 (N/2 electrons per spin) */
+  double rs;       /* Wigner-Seitz radius, > 0; box L = (4 pi N / 3)^(1/3) r_s */
+  double theta;    /* reduced temperature T/T_F, > 0; k_B T_F = (9 pi/4)^(2/3) / (2 r_s^2) (eq. fermiT) */
+  int nmax2;       /* plane waves with integer |n|^2 <= nmax2, >= 1 */
+  double dtau;     /* nominal time step; n = round(beta/dtau) slices, dtau_eff = beta/n */
+  int stab_every;  /* QR stabilisation every stab_every slices (and at slice n), >= 1 */
+  int n_walkers;   /* >= 1 */
+  double mu;       /* interacting chemical potential; NaN selects mu_T of the trial */
+  double kscale;   /* lambda in H_1 = lambda T + h (1 = the physical Hamiltonian) */
+  int precision;   /* FTAFQMC_FP64 or FTAFQMC_MIXED */
+  int flags;       /* reserved, 0 */
+} ftafqmc_params;
+
+/* Derived sizes and constants of one system (host-side values). */
+typedef struct {
+  int M;            /* plane waves */
+  int n_q;          /* momentum transfers (both signs) */
+  int n_slices;     /* n */
+  int n_walkers;
+  int slice;        /* slices done so far (0..n) */
+  int n_measure;    /* energy records so far (one per stabilisation boundary and at slice n) */
+  int ld;           /* padded leading dimension used internally */
+  double beta, dtau, L, omega, mu_T, mu, e_madelung;
+} ftafqmc_info;
+
+/* Bytes of device workspace needed for the n_sys systems listed in p[0..n_sys-1]
+ * (n_sys > 1 batches walkers of different systems in one handle).  Host-only. */
+int ftafqmc_workspace_bytes(const ftafqmc_params* p, int n_sys, size_t* bytes);
+
+/* Build the plane-wave tables (basis, momentum transfers, Coulomb kernel, the
+ * one-body remainder h_K of the sum-of-squares form, the trial chemical
+ * potential mu_T with 2 sum_K f(eps_K - mu_T) = N) on the host, upload them into
+ * d_workspace on `stream`, and set every walker to tau = 0: A_0 = B_T^n, weight 1,
+ * G_0 = (I + B_T^n)^{-1}.  d_workspace: device memory of ws_bytes >= the size
+ * from ftafqmc_workspace_bytes, 256-byte aligned.  On success *out is a new handle. */
+int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size_t ws_bytes,
+                     void* stream, ftafqmc_t* out);
+
+/* Sizes and constants of system `sys` (host-side; does not synchronise). */
+int ftafqmc_query(ftafqmc_t h, int sys, ftafqmc_info* out);
+
+/* Put every walker of every system back to tau = 0 (enqueued on stream). */
+int ftafqmc_reset(ftafqmc_t h, void* stream);
+
+/* Advance every walker of every system by n_slices slices (clamped at each
+ * system's n).  d_fields[s]: device pointer to system s's whole-path fields,
+ * complex128 [W_s][n_s][N_Q,s]; slice k of the path reads d_fields[s][w][k][:].
+ * Per slice: force bias from the current G, shifted propagator, stabilisation when
+ * the slice count reaches a multiple of stab_every or n, the new G and ln det,
+ * the phaseless weight update; the local energy is recorded at every
+ * stabilisation boundary and at slice n (see ftafqmc_records). */
+int ftafqmc_propagate(ftafqmc_t h, const void* const* d_fields, int n_slices, void* stream);
+
+/* Copy the current per-walker Green's function of system `sys` into d_G:
+ * row-major [W][M][M], dtype FTAFQMC_C128 (double2) or FTAFQMC_C64 (float2). */
+int ftafqmc_greens(ftafqmc_t h, int sys, void* d_G, int dtype, void* stream);
+
+/* Local energy of every walker of system `sys` at the current slice, from the
+ * current G: d_local [W][4] complex128 = (E_1, E_2, E = E_M + E_1 + E_2, N);
+ * d_mean [4] complex128 = weighted means sum_w w O_w / sum_w w over live walkers
+ * (NaN if none is alive); d_logw [W] double = ln w (-inf when killed);
+ * d_status [W] int = FTAFQMC_WALKER_*.  Any output pointer may be NULL. */
+int ftafqmc_energy(ftafqmc_t h, int sys, void* d_local, void* d_mean, double* d_logw,
+                   int* d_status, void* stream);
+
+/* Energy records taken during propagation: d_trace [n_rec][W][4] complex128 as in
+ * ftafqmc_energy, d_logw [n_rec][W] and d_slice [n_rec] (host int array, the slice
+ * of each record).  n_rec = info.n_measure.  Any pointer may be NULL. */
+int ftafqmc_records(ftafqmc_t h, int sys, void* d_trace, double* d_logw, int* h_slice,
+                    void* stream);
+
+/* Adjoint of the weighted mean energy and electron number at the current slice
+ * with respect to mu and the kinetic scale lambda, for fixed shifted fields
+ * (mode 0 = FROZEN_FIELDS).  d_out [4] double = (d<E>/dmu, d<N>/dmu,
+ * d<E>/dlambda, d<N>/dlambda).  Returns FTAFQMC_E_UNSUPPORTED for other modes. */
+int ftafqmc_backward(ftafqmc_t h, int sys, int mode, double* d_out, void* stream);
+
+/* Kernel-class timing with HIP events recorded on the caller's stream around every
+ * launch (instrumentation).  enable = 1 starts recording; enable = 0 stops, waits for
+ * the recorded events and writes, per class, the summed milliseconds into
+ * h_ms[FTAFQMC_PROF_CLASSES] and the launch counts into h_count (host arrays, may be
+ * NULL).  Classes: the propagator GEMMs, the Green's-function elimination, the
+ * transposes around it, the weight/force-bias kernel, the coefficient/V gather,
+ * the stabilisation, the energy. */
+enum { FTAFQMC_PROF_GEMM = 0, FTAFQMC_PROF_ELIM = 1, FTAFQMC_PROF_GREENS = 2, FTAFQMC_PROF_WEIGHT = 3,
+       FTAFQMC_PROF_COEF = 4, FTAFQMC_PROF_STAB = 5, FTAFQMC_PROF_ENERGY = 6, FTAFQMC_PROF_CLASSES = 7 };
+int ftafqmc_profile(ftafqmc_t h, int enable, double* h_ms, long long* h_count);
+
+/* Message of the last error on this handle ("" if none); valid until the next call. */
+const char* ftafqmc_last_error(ftafqmc_t h);
+
+/* Release the handle (host memory only; the caller frees the workspace). */
+void ftafqmc_destroy(ftafqmc_t h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FTAFQMC_H */

@@ -172,8 +172,10 @@ def wrap_angle(x):
 ALIVE, KILLED, NUMERIC = 0, 1, 2
 
 
-def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False):
+def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, stop_after=None):
     """Propagate one walker from tau = 0 to tau = beta with fields z[k, q].
+
+    stop_after: end the path after that many slices (a bounded sample for timing).
 
     z: complex [n_slices, NQ]; Re z = field of A(Q), Im z = field of B(Q).
     Measures the local energy (energy_fn(sys, G)) after slice k+1 when
@@ -191,7 +193,7 @@ def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False):
     theta_all = np.zeros(n)
     lnI_all = np.zeros(n)
     records, greens = [], []
-    for k in range(n):
+    for k in range(n if stop_after is None else min(n, int(stop_after))):
         P = np.eye(M) - G.T
         xbA, xbB = force_bias(sys, P)
         xA, xB = z[k].real, z[k].imag

@@ -1,0 +1,247 @@
+"""Python binding of libftafqmc: ph-FT-AFQMC slice propagation for the uniform electron gas on MI355X.
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+libftafqmc.so (built by paper_2012_12228_amd/build.py).  torch supplies device
+memory (the workspace and all inputs/outputs) and the stream.  The functions
+carry the names of the C ABI declared in include/ftafqmc.h; `Context` bundles
+them for one handle.  There is no fallback: without the built library every
+call raises.
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libftafqmc.so")
+
+FTAFQMC_FP64, FTAFQMC_MIXED = 0, 1
+FTAFQMC_C128, FTAFQMC_C64 = 0, 1
+WALKER_ALIVE, WALKER_KILLED, WALKER_NUMERIC = 0, 1, 2
+FROZEN_FIELDS = 0
+STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NUMERIC", -4: "E_STATE", -5: "E_UNSUPPORTED"}
+
+ABI_SYMBOLS = ["ftafqmc_workspace_bytes", "ftafqmc_init_ueg", "ftafqmc_query", "ftafqmc_reset",
+               "ftafqmc_propagate", "ftafqmc_greens", "ftafqmc_energy", "ftafqmc_records",
+               "ftafqmc_backward", "ftafqmc_profile", "ftafqmc_last_error", "ftafqmc_destroy"]
+PROF_CLASSES = ["gemm", "elim", "greens_transpose", "weight_forcebias", "coef_gather", "stabilise", "energy"]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_elec", ctypes.c_int), ("rs", ctypes.c_double), ("theta", ctypes.c_double),
+                ("nmax2", ctypes.c_int), ("dtau", ctypes.c_double), ("stab_every", ctypes.c_int),
+                ("n_walkers", ctypes.c_int), ("mu", ctypes.c_double), ("kscale", ctypes.c_double),
+                ("precision", ctypes.c_int), ("flags", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int), ("n_q", ctypes.c_int), ("n_slices", ctypes.c_int),
+                ("n_walkers", ctypes.c_int), ("slice", ctypes.c_int), ("n_measure", ctypes.c_int),
+                ("ld", ctypes.c_int), ("beta", ctypes.c_double), ("dtau", ctypes.c_double),
+                ("L", ctypes.c_double), ("omega", ctypes.c_double), ("mu_T", ctypes.c_double),
+                ("mu", ctypes.c_double), ("e_madelung", ctypes.c_double)]
+
+
+_lib_handle = None
+
+
+def load_library():
+    """Load libftafqmc.so (torch must be imported first so that one HIP runtime serves both)."""
+    global _lib_handle
+    if _lib_handle is not None:
+        return _lib_handle
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libftafqmc.so is not built: run `python paper_2012_12228_amd/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ip, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    lib.ftafqmc_workspace_bytes.argtypes = [ctypes.POINTER(Params), ip, ctypes.POINTER(sz)]
+    lib.ftafqmc_init_ueg.argtypes = [ctypes.POINTER(Params), ip, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.ftafqmc_query.argtypes = [vp, ip, ctypes.POINTER(Info)]
+    lib.ftafqmc_reset.argtypes = [vp, vp]
+    lib.ftafqmc_propagate.argtypes = [vp, ctypes.POINTER(vp), ip, vp]
+    lib.ftafqmc_greens.argtypes = [vp, ip, vp, ip, vp]
+    lib.ftafqmc_energy.argtypes = [vp, ip, vp, vp, vp, vp, vp]
+    lib.ftafqmc_records.argtypes = [vp, ip, vp, vp, ctypes.POINTER(ctypes.c_int), vp]
+    lib.ftafqmc_backward.argtypes = [vp, ip, ip, vp, vp]
+    lib.ftafqmc_profile.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
+    lib.ftafqmc_last_error.argtypes = [vp]
+    lib.ftafqmc_last_error.restype = ctypes.c_char_p
+    lib.ftafqmc_destroy.argtypes = [vp]
+    lib.ftafqmc_destroy.restype = None
+    for name in ABI_SYMBOLS[:-2]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib_handle = lib
+    return lib
+
+
+def _params(sysdef):
+    mu = sysdef.get("mu")
+    return Params(int(sysdef["n_elec"]), float(sysdef["rs"]), float(sysdef["theta"]), int(sysdef["nmax2"]),
+                  float(sysdef["dtau"]), int(sysdef.get("stab_every", 10)), int(sysdef["walkers"]),
+                  float("nan") if mu is None else float(mu), float(sysdef.get("kscale", 1.0)),
+                  int(sysdef.get("precision", FTAFQMC_FP64)), int(sysdef.get("flags", 0)))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check(rc, handle=None):
+    if rc != 0:
+        msg = ""
+        if handle:
+            msg = load_library().ftafqmc_last_error(handle).decode()
+        raise RuntimeError("ftafqmc call failed: %s %s" % (STATUS.get(rc, rc), msg))
+
+
+# ------------------------------------------------------------ C ABI names ---
+def ftafqmc_workspace_bytes(systems):
+    arr = (Params * len(systems))(*[_params(s) for s in systems])
+    n = ctypes.c_size_t(0)
+    _check(load_library().ftafqmc_workspace_bytes(arr, len(systems), ctypes.byref(n)))
+    return n.value
+
+
+def ftafqmc_init_ueg(systems, workspace, device):
+    arr = (Params * len(systems))(*[_params(s) for s in systems])
+    h = ctypes.c_void_p(0)
+    _check(load_library().ftafqmc_init_ueg(arr, len(systems), _ptr(workspace), workspace.numel(),
+                                           _stream(device), ctypes.byref(h)))
+    return h
+
+
+def ftafqmc_query(handle, sys=0):
+    info = Info()
+    _check(load_library().ftafqmc_query(handle, sys, ctypes.byref(info)), handle)
+    return {f: getattr(info, f) for f, _ in Info._fields_}
+
+
+def ftafqmc_reset(handle, device):
+    _check(load_library().ftafqmc_reset(handle, _stream(device)), handle)
+
+
+def ftafqmc_propagate(handle, fields, n_slices, device):
+    for f in fields:
+        if f.dtype != torch.complex128 or not f.is_contiguous() or f.device.type != "cuda":
+            raise ValueError("fields must be contiguous complex128 CUDA tensors")
+    ptrs = (ctypes.c_void_p * len(fields))(*[f.data_ptr() for f in fields])
+    _check(load_library().ftafqmc_propagate(handle, ptrs, int(n_slices), _stream(device)), handle)
+
+
+def ftafqmc_greens(handle, sys, out, device):
+    code = FTAFQMC_C128 if out.dtype == torch.complex128 else FTAFQMC_C64
+    _check(load_library().ftafqmc_greens(handle, sys, _ptr(out), code, _stream(device)), handle)
+    return out
+
+
+def ftafqmc_energy(handle, sys, local, mean, logw, status, device):
+    _check(load_library().ftafqmc_energy(handle, sys, _ptr(local), _ptr(mean), _ptr(logw), _ptr(status),
+                                         _stream(device)), handle)
+
+
+def ftafqmc_records(handle, sys, trace, logw, n_rec, device):
+    slices = (ctypes.c_int * max(1, n_rec))()
+    _check(load_library().ftafqmc_records(handle, sys, _ptr(trace), _ptr(logw), slices, _stream(device)), handle)
+    return [slices[i] for i in range(n_rec)]
+
+
+def ftafqmc_backward(handle, sys, mode, out, device):
+    _check(load_library().ftafqmc_backward(handle, sys, mode, _ptr(out), _stream(device)), handle)
+    return out
+
+
+def ftafqmc_profile(handle, enable):
+    """enable=True starts event timing; enable=False stops and returns {class: (ms, launches)}."""
+    n = len(PROF_CLASSES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_longlong * n)()
+    _check(load_library().ftafqmc_profile(handle, 1 if enable else 0, ms, cnt), handle)
+    if enable:
+        return None
+    return {PROF_CLASSES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+
+def ftafqmc_destroy(handle):
+    load_library().ftafqmc_destroy(handle)
+
+
+# ------------------------------------------------------------- convenience ---
+class Context:
+    """One library handle over one or more UEG systems, with its torch workspace."""
+
+    def __init__(self, systems, device="cuda:0"):
+        if isinstance(systems, dict):
+            systems = [systems]
+        self.systems = [dict(s) for s in systems]
+        self.device = torch.device(device)
+        load_library()
+        nbytes = ftafqmc_workspace_bytes(self.systems)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.workspace = self.workspace[off:off + nbytes]
+        self.handle = ftafqmc_init_ueg(self.systems, self.workspace, self.device)
+        self.infos = [ftafqmc_query(self.handle, i) for i in range(len(self.systems))]
+
+    def info(self, sys=0):
+        return ftafqmc_query(self.handle, sys)
+
+    def reset(self):
+        ftafqmc_reset(self.handle, self.device)
+
+    def propagate(self, fields, n_slices=None):
+        if isinstance(fields, torch.Tensor):
+            fields = [fields]
+        for i, f in enumerate(fields):
+            inf = self.infos[i]
+            want = (inf["n_walkers"], inf["n_slices"], inf["n_q"])
+            if tuple(f.shape) != want:
+                raise ValueError("fields of system %d must have shape %s" % (i, want))
+        if n_slices is None:
+            n_slices = max(inf["n_slices"] for inf in self.infos)
+        ftafqmc_propagate(self.handle, fields, n_slices, self.device)
+
+    def greens(self, sys=0, dtype=torch.complex128):
+        inf = self.infos[sys]
+        out = torch.empty((inf["n_walkers"], inf["M"], inf["M"]), dtype=dtype, device=self.device)
+        return ftafqmc_greens(self.handle, sys, out, self.device)
+
+    def energy(self, sys=0):
+        W = self.infos[sys]["n_walkers"]
+        local = torch.empty((W, 4), dtype=torch.complex128, device=self.device)
+        mean = torch.empty(4, dtype=torch.complex128, device=self.device)
+        logw = torch.empty(W, dtype=torch.float64, device=self.device)
+        status = torch.empty(W, dtype=torch.int32, device=self.device)
+        ftafqmc_energy(self.handle, sys, local, mean, logw, status, self.device)
+        return dict(local=local, mean=mean, logw=logw, status=status)
+
+    def records(self, sys=0):
+        inf = self.info(sys)
+        n, W = inf["n_measure"], inf["n_walkers"]
+        trace = torch.empty((max(n, 1), W, 4), dtype=torch.complex128, device=self.device)
+        logw = torch.empty((max(n, 1), W), dtype=torch.float64, device=self.device)
+        slices = ftafqmc_records(self.handle, sys, trace, logw, n, self.device)
+        return dict(slices=slices, trace=trace[:n], logw=logw[:n])
+
+    def profile(self, enable):
+        return ftafqmc_profile(self.handle, enable)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ftafqmc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def walker_slices_per_second(systems_info, seconds):
+    """Throughput W * n summed over systems."""
+    return sum(i["n_walkers"] * i["n_slices"] for i in systems_info) / seconds

@@ -1,0 +1,188 @@
+// Batched complex GEMM on the CDNA4 matrix cores for the slice propagator.
+//
+// C_w = alpha * op(A_w) op(B_w) + cI I + c1 P1_w + c2 P2_w + c3 P3_w, scaled as
+// diag(rs) C diag(cs), with an optional second output C2_w from the same product.
+// The epilogue forms the Paterson-Stockmeyer blocks of the Taylor series of e^V
+// and the half-step kinetic factors of the symmetric Trotter propagator (eq. B)
+// without extra passes over memory.
+//
+// Tiling: 64 x 64 output tile per 256-thread workgroup (2 x 2 waves, each wave
+// 2 x 2 blocks of 16 x 16), K staged through LDS 16 at a time, double-buffered.
+// Complex products use four real MFMAs: re += a.re b.re - a.im b.im,
+// im += a.re b.im + a.im b.re.  FP64 path: v_mfma_f64_16x16x4f64; mixed path:
+// v_mfma_f32_16x16x4f32 with complex64 operands and FP32 accumulation.
+// Matrices are [W][ld][ld] (or any lda/ldb/ldc) with zero padding beyond M;
+// every load is bounds-guarded against M, every store against Mpad.
+#include "common.h"
+#include "kernels.h"
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
+
+template <typename ACC> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4v acc_t;
+  static FT_DEV acc_t mma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  // output register v of lane l holds row 4v + l/16, column l%16 of the 16x16 block
+  static FT_DEV int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+  typedef f4v acc_t;
+  static FT_DEV acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  // output register v of lane l holds row 4(l/16) + v, column l%16
+  static FT_DEV int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+template <typename T> FT_DEV double2 ld_c(const T* p) { return to_d2(*p); }
+
+template <typename TA, typename TB, typename TC, typename ACC>
+__global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
+  typedef typename cplx_of<ACC>::type cacc;
+  typedef typename Mfma<ACC>::acc_t acc_t;
+  __shared__ cacc As[2][BK][BM + PAD];
+  __shared__ cacc Bs[2][BK][BN + PAD];
+
+  int w, tile;
+  if (!xcd_walker_tile(blockIdx.x, p.W, p.tiles * p.tiles, &w, &tile)) return;
+  const int tm = tile / p.tiles, tn = tile - tm * p.tiles;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int M = p.M;
+
+  const TA* A = (const TA*)p.A + (long long)w * p.sA;
+  const TB* B = (const TB*)p.B + (long long)w * p.sB;
+
+  acc_t accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { accR[i][j][v] = 0; accI[i][j][v] = 0; }
+
+  cacc ra[4], rb[4];
+  // global -> registers for k-tile kt
+  auto load_tile = [&](int kt) {
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int gm, gk;
+      if (p.opA == 0) { gm = m0 + (t >> 2); gk = k0 + ((t & 3) << 2) + e; }
+      else            { gk = k0 + (t >> 4); gm = m0 + ((t & 15) << 2) + e; }
+      double2 v = make_double2(0.0, 0.0);
+      if (gm < M && gk < M) {
+        v = p.opA == 0 ? ld_c(A + (long long)gm * p.lda + gk) : cconj(ld_c(A + (long long)gk * p.lda + gm));
+      }
+      ra[e] = cvt<ACC>(v);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int gk, gn;
+      if (p.opB == 0) { gk = k0 + (t >> 4); gn = n0 + ((t & 15) << 2) + e; }
+      else            { gn = n0 + (t >> 2); gk = k0 + ((t & 3) << 2) + e; }
+      double2 v = make_double2(0.0, 0.0);
+      if (gn < M && gk < M) {
+        v = p.opB == 0 ? ld_c(B + (long long)gk * p.ldb + gn) : cconj(ld_c(B + (long long)gn * p.ldb + gk));
+      }
+      rb[e] = cvt<ACC>(v);
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (p.opA == 0) As[buf][((t & 3) << 2) + e][t >> 2] = ra[e];
+      else            As[buf][t >> 4][((t & 15) << 2) + e] = ra[e];
+      if (p.opB == 0) Bs[buf][t >> 4][((t & 15) << 2) + e] = rb[e];
+      else            Bs[buf][((t & 3) << 2) + e][t >> 2] = rb[e];
+    }
+  };
+
+  const int nk = (M + BK - 1) / BK;
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+  const int li = lane & 15, lk = lane >> 4;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load_tile(kt + 1);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      cacc a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[buf][ks + lk][wr * 32 + i * 16 + li];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[buf][ks + lk][wc * 32 + j * 16 + li];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const ACC nai = -a[i].y;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          accR[i][j] = Mfma<ACC>::mma(a[i].x, b[j].x, accR[i][j]);
+          accR[i][j] = Mfma<ACC>::mma(nai, b[j].y, accR[i][j]);
+          accI[i][j] = Mfma<ACC>::mma(a[i].x, b[j].y, accI[i][j]);
+          accI[i][j] = Mfma<ACC>::mma(a[i].y, b[j].x, accI[i][j]);
+        }
+      }
+    }
+    if (kt + 1 < nk) store_tile(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue
+  TC* C = (TC*)p.C + (long long)w * p.sC;
+  TC* C2 = p.C2 ? (TC*)p.C2 + (long long)w * p.sC : nullptr;
+  const TC* P1 = p.P1 ? (const TC*)p.P1 + (long long)w * p.sP : nullptr;
+  const TC* P2 = p.P2 ? (const TC*)p.P2 + (long long)w * p.sP : nullptr;
+  const TC* P3 = p.P3 ? (const TC*)p.P3 + (long long)w * p.sP : nullptr;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = m0 + wr * 32 + i * 16 + Mfma<ACC>::row(lane, v);
+        const int gj = n0 + wc * 32 + j * 16 + li;
+        if (gi >= p.Mpad || gj >= p.Mpad) continue;
+        double2 out = make_double2(0.0, 0.0), out2 = make_double2(0.0, 0.0);
+        if (gi < M && gj < M) {
+          const double2 acc = make_double2((double)accR[i][j][v], (double)accI[i][j][v]);
+          out = cscale(acc, p.alpha);
+          out2 = cscale(acc, p.beta2);
+          if (gi == gj) { out.x += p.cI; out2.x += p.dI; }
+          const long long off = (long long)gi * p.ldp + gj;
+          if (P1) { double2 q = ld_c(P1 + off); out = cadd(out, cscale(q, p.c1)); out2 = cadd(out2, cscale(q, p.d1)); }
+          if (P2) { double2 q = ld_c(P2 + off); out = cadd(out, cscale(q, p.c2)); out2 = cadd(out2, cscale(q, p.d2)); }
+          if (P3) { double2 q = ld_c(P3 + off); out = cadd(out, cscale(q, p.c3)); out2 = cadd(out2, cscale(q, p.d3)); }
+          if (p.rs) out = cscale(out, p.rs[gi]);
+          if (p.cs) out = cscale(out, p.cs[gj]);
+        }
+        store_c(C + (long long)gi * p.ldc + gj, out);
+        if (C2) store_c(C2 + (long long)gi * p.ldc + gj, out2);
+      }
+}
+
+}  // namespace
+
+int gemm_tiles(int Mpad) { return (Mpad + BM - 1) / BM; }
+
+hipError_t launch_zgemm(const GemmParams& p0, int prec, hipStream_t s) {
+  GemmParams p = p0;
+  p.tiles = gemm_tiles(p.Mpad);
+  const int blocks = ((p.W + 7) / 8) * 8 * p.tiles * p.tiles;
+  if (blocks == 0) return hipSuccess;
+  switch (prec) {
+    case GEMM_Z64:   // complex128 in and out, FP64 MFMA
+      zgemm_kernel<double2, double2, double2, double><<<blocks, 256, 0, s>>>(p); break;
+    case GEMM_C32:   // complex64 in and out, FP32 MFMA
+      zgemm_kernel<float2, float2, float2, float><<<blocks, 256, 0, s>>>(p); break;
+    case GEMM_C32_Z64B:  // complex64 A, complex128 B (rounded to complex64), complex128 out
+      zgemm_kernel<float2, double2, double2, float><<<blocks, 256, 0, s>>>(p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}

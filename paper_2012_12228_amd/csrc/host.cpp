@@ -1,0 +1,559 @@
+// Host side of the library: UEG tables, workspace layout, slice orchestration and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ftafqmc.h"
+#include "kernels.h"
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+constexpr double MADELUNG = 2.837297;  // Sec. "Uniform Electron Gas"
+constexpr int MAX_M = 512;             // the elimination keeps a panel row per thread, two per thread at most
+constexpr int MAX_NQ = 8192;           // the shifted coefficients of one walker are staged in LDS
+
+typedef std::array<int, 3> iv3;
+
+bool iv_less(const iv3& a, const iv3& b) {
+  const int na = a[0] * a[0] + a[1] * a[1] + a[2] * a[2], nb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+  if (na != nb) return na < nb;
+  return a < b;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct HostSys {
+  ftafqmc_params p;
+  int M = 0, NQ = 0, n = 0, ld = 0, rmax = 0, gdim = 0, gc0 = 0, nrec_max = 0;
+  double L = 0, omega = 0, TF = 0, beta = 0, dtau = 0, muT = 0, mu = 0, EM = 0;
+  std::vector<iv3> nvec, qvec;
+  std::vector<int> idx, neg, qptr, qpair, flat;
+  std::vector<double> vq, sq, eps, hK, kh, lnbt;
+  std::vector<short> grid;
+  size_t off_begin = 0, bytes = 0;
+  SysDev dev;
+  double2* mean = nullptr;
+  int k = 0, nrec = 0;
+  std::vector<int> rec_slice;
+};
+
+// Logistic 1/(1+e^x) without overflow.
+double fermi(double x) { return x > 0 ? std::exp(-x) / (1.0 + std::exp(-x)) : 1.0 / (1.0 + std::exp(x)); }
+
+std::string build_tables(HostSys& s, const ftafqmc_params& p) {
+  s.p = p;
+  if (p.n_elec < 2 || (p.n_elec & 1)) return "n_elec must be even and >= 2";
+  if (!(p.rs > 0) || !(p.theta > 0) || !(p.dtau > 0)) return "rs, theta and dtau must be positive";
+  if (p.nmax2 < 1) return "nmax2 must be >= 1";
+  if (p.stab_every < 1) return "stab_every must be >= 1";
+  if (p.n_walkers < 1) return "n_walkers must be >= 1";
+  if (p.precision != FTAFQMC_FP64 && p.precision != FTAFQMC_MIXED) return "unknown precision";
+  if (!std::isfinite(p.kscale)) return "kscale must be finite";
+  // box, temperature, slices (Sec. "Computational Details", eq. fermiT)
+  s.L = std::cbrt(4.0 * PI * p.n_elec / 3.0) * p.rs;
+  s.omega = s.L * s.L * s.L;
+  s.TF = 0.5 * std::pow(9.0 * PI / 4.0, 2.0 / 3.0) / (p.rs * p.rs);
+  s.beta = 1.0 / (p.theta * s.TF);
+  s.n = std::max(1, (int)std::lround(s.beta / p.dtau));
+  s.dtau = s.beta / s.n;
+  // basis
+  s.rmax = (int)std::floor(std::sqrt((double)p.nmax2));
+  while ((s.rmax + 1) * (s.rmax + 1) <= p.nmax2) ++s.rmax;
+  for (int a = -s.rmax; a <= s.rmax; ++a)
+    for (int b = -s.rmax; b <= s.rmax; ++b)
+      for (int c = -s.rmax; c <= s.rmax; ++c)
+        if (a * a + b * b + c * c <= p.nmax2) s.nvec.push_back({a, b, c});
+  std::sort(s.nvec.begin(), s.nvec.end(), iv_less);
+  s.M = (int)s.nvec.size();
+  if (s.M > MAX_M) return "basis larger than the supported maximum of 512 plane waves";
+  s.ld = (s.M + 15) / 16 * 16;
+  const double k0 = 2.0 * PI / s.L;
+  s.eps.assign(s.ld, 0.0);
+  for (int i = 0; i < s.M; ++i) {
+    const iv3& v = s.nvec[i];
+    s.eps[i] = 0.5 * k0 * k0 * (double)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  }
+  // momentum transfers
+  std::map<iv3, int, bool (*)(const iv3&, const iv3&)> qmap(iv_less);
+  for (int i = 0; i < s.M; ++i)
+    for (int j = 0; j < s.M; ++j)
+      if (i != j) qmap.emplace(iv3{s.nvec[i][0] - s.nvec[j][0], s.nvec[i][1] - s.nvec[j][1], s.nvec[i][2] - s.nvec[j][2]}, 0);
+  for (auto& kv : qmap) { kv.second = (int)s.qvec.size(); s.qvec.push_back(kv.first); }
+  s.NQ = (int)s.qvec.size();
+  if (s.NQ > MAX_NQ) return "too many momentum transfers";
+  s.idx.assign((size_t)s.M * s.M, -1);
+  for (int i = 0; i < s.M; ++i)
+    for (int j = 0; j < s.M; ++j)
+      if (i != j)
+        s.idx[(size_t)i * s.M + j] = qmap.at(iv3{s.nvec[i][0] - s.nvec[j][0], s.nvec[i][1] - s.nvec[j][1], s.nvec[i][2] - s.nvec[j][2]});
+  s.neg.resize(s.NQ);
+  s.vq.resize(s.NQ);
+  s.sq.resize(s.NQ);
+  for (int q = 0; q < s.NQ; ++q) {
+    const iv3& v = s.qvec[q];
+    s.neg[q] = qmap.at(iv3{-v[0], -v[1], -v[2]});
+    const double q2 = k0 * k0 * (double)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    s.vq[q] = 4.0 * PI / (s.omega * q2);
+    s.sq[q] = std::sqrt(PI * s.dtau / (s.omega * q2));
+  }
+  // one-body remainder of the sum-of-squares form: h_K = -(1/2) sum_{K' != K} v(K - K')
+  s.hK.assign(s.M, 0.0);
+  for (int i = 0; i < s.M; ++i) {
+    double a = 0.0;
+    for (int j = 0; j < s.M; ++j)
+      if (j != i) a += s.vq[s.idx[(size_t)i * s.M + j]];
+    s.hK[i] = -0.5 * a;
+  }
+  // trial chemical potential: 2 sum_K f(eps_K - mu_T) = N by bisection
+  {
+    auto count = [&](double mu) { double c = 0; for (int i = 0; i < s.M; ++i) c += 2.0 * fermi(s.beta * (s.eps[i] - mu)); return c; };
+    double lo = s.eps[0] - 60.0 / s.beta, hi = s.eps[s.M - 1] + 60.0 / s.beta;
+    if (!(count(lo) < p.n_elec && p.n_elec < count(hi))) return "electron number not reachable in this basis";
+    for (int it = 0; it < 400; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (count(mid) < p.n_elec) lo = mid; else hi = mid;
+      if (hi - lo <= 4e-16 * std::max(1.0, std::fabs(mid))) break;
+    }
+    s.muT = 0.5 * (lo + hi);
+  }
+  s.mu = std::isnan(p.mu) ? s.muT : p.mu;
+  s.EM = -MADELUNG * p.n_elec / (2.0 * s.L);
+  s.kh.assign(s.ld, 0.0);
+  s.lnbt.assign(s.ld, 0.0);
+  for (int i = 0; i < s.M; ++i) {
+    s.kh[i] = std::exp(-0.5 * s.dtau * (p.kscale * s.eps[i] + s.hK[i] - s.mu));
+    s.lnbt[i] = -s.dtau * (s.eps[i] - s.muT);
+  }
+  // pairs of each Q as flat indices of G_{r p} (K_p - K_r = Q)
+  s.qptr.assign(s.NQ + 1, 0);
+  for (int i = 0; i < s.M; ++i)
+    for (int j = 0; j < s.M; ++j)
+      if (i != j) s.qptr[s.idx[(size_t)i * s.M + j] + 1]++;
+  for (int q = 0; q < s.NQ; ++q) s.qptr[q + 1] += s.qptr[q];
+  s.qpair.assign(s.qptr[s.NQ], 0);
+  {
+    std::vector<int> fill(s.qptr.begin(), s.qptr.end() - 1);
+    for (int pidx = 0; pidx < s.M; ++pidx)
+      for (int r = 0; r < s.M; ++r)
+        if (pidx != r) s.qpair[fill[s.idx[(size_t)pidx * s.M + r]]++] = r * s.ld + pidx;
+  }
+  // lookup grid for K_b - K_a + K_d
+  const int R = 3 * s.rmax;
+  s.gdim = 2 * R + 1;
+  s.gc0 = R * (s.gdim * s.gdim + s.gdim + 1);
+  s.grid.assign((size_t)s.gdim * s.gdim * s.gdim, (short)-1);
+  s.flat.resize(s.M);
+  for (int i = 0; i < s.M; ++i) {
+    const iv3& v = s.nvec[i];
+    s.flat[i] = v[0] * s.gdim * s.gdim + v[1] * s.gdim + v[2];
+    s.grid[(size_t)(s.flat[i] + s.gc0)] = (short)i;
+  }
+  s.nrec_max = s.n / p.stab_every + 2;
+  return "";
+}
+
+// Lay out (or only size, when base == nullptr) one system's slice of the workspace.
+size_t layout(HostSys& s, char* base, size_t off) {
+  const int W = s.p.n_walkers, ld = s.ld, M = s.M, NQ = s.NQ;
+  const size_t mat = (size_t)ld * ld;
+  const size_t velem = s.p.precision == FTAFQMC_MIXED ? sizeof(float2) : sizeof(double2);
+  auto take = [&](size_t bytes) -> char* { char* r = base ? base + off : nullptr; off = align256(off + bytes); return r; };
+  SysDev& d = s.dev;
+  s.off_begin = off;
+  d.idx = (const int*)take(sizeof(int) * M * M);
+  d.neg = (const int*)take(sizeof(int) * NQ);
+  d.vq = (const double*)take(sizeof(double) * NQ);
+  d.sq = (const double*)take(sizeof(double) * NQ);
+  d.eps = (const double*)take(sizeof(double) * ld);
+  d.kh = (const double*)take(sizeof(double) * ld);
+  d.lnbt = (const double*)take(sizeof(double) * ld);
+  d.qptr = (const int*)take(sizeof(int) * (NQ + 1));
+  d.qpair = (const int*)take(sizeof(int) * (size_t)M * (M - 1));
+  d.grid = (const short*)take(sizeof(short) * s.grid.size());
+  d.flat = (const int*)take(sizeof(int) * M);
+  d.Y = (double2*)take(sizeof(double2) * mat * W);
+  d.Ti = (double2*)take(sizeof(double2) * mat * W);
+  d.G = (double2*)take(sizeof(double2) * mat * W);
+  d.Ynew = (double2*)take(sizeof(double2) * mat * W);
+  d.aug = (double2*)take(sizeof(double2) * 2 * mat * W);
+  d.V = take(velem * mat * W);
+  d.V2 = take(velem * mat * W);
+  d.V3 = take(velem * mat * W);
+  d.V4 = take(velem * mat * W);
+  d.E0 = take(sizeof(double2) * mat * W);
+  d.E1 = take(sizeof(double2) * mat * W);
+  d.D = (double*)take(sizeof(double) * ld * W);
+  d.Dpi = (double*)take(sizeof(double) * ld * W);
+  d.perm = (int*)take(sizeof(int) * ld * W);
+  d.r = (double2*)take(sizeof(double2) * (size_t)NQ * W);
+  d.expo = (double2*)take(sizeof(double2) * W);
+  d.ell = (double2*)take(sizeof(double2) * W);
+  d.lndetT = (double2*)take(sizeof(double2) * W);
+  d.lndetX = (double2*)take(sizeof(double2) * W);
+  d.logw = (double*)take(sizeof(double) * W);
+  d.status = (int*)take(sizeof(int) * W);
+  d.slice_lnS = (double2*)take(sizeof(double2) * (size_t)W * s.n);
+  d.slice_theta = (double*)take(sizeof(double) * (size_t)W * s.n);
+  d.exch = (double2*)take(sizeof(double2) * (size_t)ld * W);
+  d.local = (double2*)take(sizeof(double2) * 4 * W);
+  d.rec_E = (double2*)take(sizeof(double2) * 4 * (size_t)W * s.nrec_max);
+  d.rec_logw = (double*)take(sizeof(double) * (size_t)W * s.nrec_max);
+  d.rec_status = (int*)take(sizeof(int) * (size_t)W * s.nrec_max);
+  d.scratch = (double*)take(sizeof(double) * (size_t)ld * W);
+  s.mean = (double2*)take(sizeof(double2) * 4);
+  s.bytes = off - s.off_begin;
+  d.M = M; d.ld = ld; d.NQ = NQ; d.W = W; d.n = s.n; d.grid_dim = s.gdim; d.grid_c0 = s.gc0;
+  d.dtau = s.dtau; d.kscale = s.p.kscale; d.e_madelung = s.EM;
+  d.mat_stride = (long long)mat;
+  d.aug_stride = (long long)2 * mat;
+  return off;
+}
+
+}  // namespace
+
+struct ProfEvent { int cls; hipEvent_t a, b; };
+
+struct ftafqmc_ctx {
+  std::vector<HostSys> sys;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::string err;
+  bool prof = false;
+  std::vector<ProfEvent> events;
+  int set(int code, const std::string& m) { err = m; return code; }
+};
+
+namespace {
+
+#define HIPCHK(call)                                                             \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) return h->set(FTAFQMC_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Launch f on st; with profiling on, bracket it with two events of class cls.
+template <typename F> hipError_t timed(ftafqmc_ctx* h, int cls, hipStream_t st, F f) {
+  if (!h->prof) return f();
+  ProfEvent ev{cls, nullptr, nullptr};
+  hipError_t e = hipEventCreate(&ev.a);
+  if (e == hipSuccess) e = hipEventCreate(&ev.b);
+  if (e == hipSuccess) e = hipEventRecord(ev.a, st);
+  if (e != hipSuccess) return e;
+  e = f();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(ev.b, st);
+  h->events.push_back(ev);
+  return e;
+}
+
+double sum_ln_lb(const HostSys& s, int k) {
+  double a = 0.0;
+  for (int i = 0; i < s.M; ++i) a += -std::max(0.0, (double)(s.n - k) * s.lnbt[i]);
+  return a;
+}
+
+GemmParams gp_base(const HostSys& s) {
+  GemmParams g;
+  std::memset(&g, 0, sizeof(g));
+  g.sA = g.sB = g.sC = g.sP = s.dev.mat_stride;
+  g.lda = g.ldb = g.ldc = g.ldp = s.ld;
+  g.M = s.M; g.Mpad = s.ld; g.W = s.p.n_walkers;
+  g.alpha = 1.0;
+  return g;
+}
+
+double inv_fact(int j) { double f = 1.0; for (int i = 2; i <= j; ++i) f *= i; return 1.0 / f; }
+
+// Y <- K e^V K Y with e^V by Paterson-Stockmeyer (blocks of 4): degree 16 in FP64
+// (6 products), degree 12 in mixed precision (5 products); one more to apply.
+int apply_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
+  SysDev& d = s.dev;
+  const bool mixed = s.p.precision == FTAFQMC_MIXED;
+  const int prec = mixed ? GEMM_C32 : GEMM_Z64;
+  const int deg = mixed ? 12 : 16;
+  GemmParams g = gp_base(s);
+  g.A = d.V; g.B = d.V; g.C = d.V2;
+  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));                       // V^2
+  g.A = d.V2; g.B = d.V; g.C = d.V3;
+  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));                       // V^3
+  // V^4 and the top Horner block a_deg V^4 + sum_{r<4} a_{deg-4+r} V^r
+  g.A = d.V2; g.B = d.V2; g.C = d.V4; g.C2 = d.E0;
+  g.P1 = d.V; g.P2 = d.V2; g.P3 = d.V3;
+  g.beta2 = inv_fact(deg); g.dI = inv_fact(deg - 4); g.d1 = inv_fact(deg - 3); g.d2 = inv_fact(deg - 2); g.d3 = inv_fact(deg - 1);
+  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));
+  void* cur = d.E0;
+  void* nxt = d.E1;
+  for (int top = deg - 8; top >= 0; top -= 4) {
+    GemmParams e = gp_base(s);
+    e.A = cur; e.B = d.V4; e.C = nxt;
+    e.P1 = d.V; e.P2 = d.V2; e.P3 = d.V3;
+    e.cI = inv_fact(top); e.c1 = inv_fact(top + 1); e.c2 = inv_fact(top + 2); e.c3 = inv_fact(top + 3);
+    if (top == 0) { e.rs = d.kh; e.cs = d.kh; }            // K e^V K
+    HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(e, prec, st); }));
+    std::swap(cur, nxt);
+  }
+  GemmParams a = gp_base(s);
+  a.A = cur; a.B = d.Y; a.C = d.Ynew;
+  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(a, mixed ? GEMM_C32_Z64B : GEMM_Z64, st); }));
+  std::swap(d.Y, d.Ynew);
+  return FTAFQMC_OK;
+}
+
+// Pre-pivoted QR of Y diag(D) by one Cholesky-QR pass; updates Y, D and Ti = T^{-1}.
+int stabilise(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
+  SysDev& d = s.dev;
+  HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_perm(d, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_gather(d, st); }));
+  GemmParams g = gp_base(s);
+  g.A = d.E0; g.B = d.E0; g.C = d.aug; g.opA = 1;
+  g.sC = d.aug_stride; g.ldc = 2 * s.ld;
+  HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));  // S = E0^H E0 into the left block
+  ElimParams e;
+  e.aug = d.aug; e.stride = d.aug_stride; e.lda = 2 * s.ld; e.M = s.M; e.rhs_off = s.ld; e.nrhs = s.M;
+  e.W = d.W; e.pivot = 0; e.backsub = 0; e.lndet = nullptr; e.status = d.status;
+  HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_elim(e, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_finish_a(d, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_build_ti(d, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_elim(e, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_finish_b(d, st); }));
+  return FTAFQMC_OK;
+}
+
+// G_k, ln det(I + A_k), the weight update of the slice that ended at k, r_Q of G_k.
+int greens(ftafqmc_ctx* h, HostSys& s, int k, int init, hipStream_t st) {
+  SysDev& d = s.dev;
+  HIPCHK(timed(h, FTAFQMC_PROF_GREENS, st, [&] { return launch_greens_form(d, k, st); }));
+  ElimParams e;
+  e.aug = d.aug; e.stride = d.aug_stride; e.lda = 2 * s.ld; e.M = s.M; e.rhs_off = s.ld; e.nrhs = s.M;
+  e.W = d.W; e.pivot = 1; e.backsub = 1; e.lndet = d.lndetX; e.status = d.status;
+  HIPCHK(timed(h, FTAFQMC_PROF_ELIM, st, [&] { return launch_elim(e, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_GREENS, st, [&] { return launch_greens_post(d, k, st); }));
+  const double slb = sum_ln_lb(s, k);
+  HIPCHK(timed(h, FTAFQMC_PROF_WEIGHT, st, [&] { return launch_weight(d, k, slb, init, st); }));
+  return FTAFQMC_OK;
+}
+
+int reset_sys(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
+  HIPCHK(launch_init_state(s.dev, st));
+  int rc = greens(h, s, 0, 1, st);
+  if (rc) return rc;
+  s.k = 0;
+  s.nrec = 0;
+  s.rec_slice.clear();
+  return FTAFQMC_OK;
+}
+
+int step(ftafqmc_ctx* h, HostSys& s, const double2* fields, hipStream_t st) {
+  const int k = s.k;
+  const int mixed = s.p.precision == FTAFQMC_MIXED;
+  HIPCHK(timed(h, FTAFQMC_PROF_COEF, st, [&] { return launch_coef_v(s.dev, fields, k, mixed, st); }));
+  int rc = apply_propagator(h, s, st);
+  if (rc) return rc;
+  const bool boundary = ((k + 1) % s.p.stab_every == 0) || (k + 1 == s.n);
+  if (boundary) { rc = stabilise(h, s, st); if (rc) return rc; }
+  rc = greens(h, s, k + 1, 0, st);
+  if (rc) return rc;
+  if (boundary) {
+    const int rec = s.nrec;
+    HIPCHK(timed(h, FTAFQMC_PROF_ENERGY, st, [&] { return launch_energy(s.dev, rec, st); }));
+    s.rec_slice.push_back(k + 1);
+    ++s.nrec;
+  }
+  s.k = k + 1;
+  return FTAFQMC_OK;
+}
+
+int check_handle(ftafqmc_ctx* h, int sys) {
+  if (!h) return FTAFQMC_E_ARG;
+  if (sys < 0 || sys >= (int)h->sys.size()) return h->set(FTAFQMC_E_ARG, "system index out of range");
+  return FTAFQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ftafqmc_workspace_bytes(const ftafqmc_params* p, int n_sys, size_t* bytes) {
+  if (!p || n_sys < 1 || !bytes) return FTAFQMC_E_ARG;
+  size_t off = 0;
+  for (int i = 0; i < n_sys; ++i) {
+    HostSys s;
+    if (!build_tables(s, p[i]).empty()) return FTAFQMC_E_ARG;
+    off = layout(s, nullptr, off);
+  }
+  *bytes = off;
+  return FTAFQMC_OK;
+}
+
+int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size_t ws_bytes, void* stream,
+                     ftafqmc_t* out) {
+  if (!p || n_sys < 1 || !out || !d_workspace) return FTAFQMC_E_ARG;
+  if (((uintptr_t)d_workspace) & 255) return FTAFQMC_E_ARG;
+  ftafqmc_ctx* h = new (std::nothrow) ftafqmc_ctx();
+  if (!h) return FTAFQMC_E_ARG;
+  h->sys.resize(n_sys);
+  size_t off = 0;
+  for (int i = 0; i < n_sys; ++i) {
+    std::string m = build_tables(h->sys[i], p[i]);
+    if (!m.empty()) { delete h; return FTAFQMC_E_ARG; }
+    off = layout(h->sys[i], nullptr, off);
+  }
+  if (off > ws_bytes) { delete h; return FTAFQMC_E_ARG; }
+  h->ws = (char*)d_workspace;
+  h->ws_bytes = ws_bytes;
+  hipStream_t st = (hipStream_t)stream;
+  off = 0;
+  for (int i = 0; i < n_sys; ++i) {
+    HostSys& s = h->sys[i];
+    off = layout(s, h->ws, off);
+    const SysDev& d = s.dev;
+    auto up = [&](const void* dst, const void* src, size_t n) {
+      return hipMemcpyAsync((void*)dst, src, n, hipMemcpyHostToDevice, st);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(d.idx, s.idx.data(), sizeof(int) * s.idx.size());
+    if (e == hipSuccess) e = up(d.neg, s.neg.data(), sizeof(int) * s.NQ);
+    if (e == hipSuccess) e = up(d.vq, s.vq.data(), sizeof(double) * s.NQ);
+    if (e == hipSuccess) e = up(d.sq, s.sq.data(), sizeof(double) * s.NQ);
+    if (e == hipSuccess) e = up(d.eps, s.eps.data(), sizeof(double) * s.ld);
+    if (e == hipSuccess) e = up(d.kh, s.kh.data(), sizeof(double) * s.ld);
+    if (e == hipSuccess) e = up(d.lnbt, s.lnbt.data(), sizeof(double) * s.ld);
+    if (e == hipSuccess) e = up(d.qptr, s.qptr.data(), sizeof(int) * (s.NQ + 1));
+    if (e == hipSuccess) e = up(d.qpair, s.qpair.data(), sizeof(int) * s.qpair.size());
+    if (e == hipSuccess) e = up(d.grid, s.grid.data(), sizeof(short) * s.grid.size());
+    if (e == hipSuccess) e = up(d.flat, s.flat.data(), sizeof(int) * s.M);
+    // the host tables are no longer needed once the copies have completed
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) { delete h; return FTAFQMC_E_HIP; }
+    if (reset_sys(h, s, st) != FTAFQMC_OK) { delete h; return FTAFQMC_E_HIP; }
+  }
+  *out = h;
+  return FTAFQMC_OK;
+}
+
+int ftafqmc_query(ftafqmc_t h, int sys, ftafqmc_info* out) {
+  int rc = check_handle(h, sys);
+  if (rc) return rc;
+  if (!out) return h->set(FTAFQMC_E_ARG, "null output");
+  const HostSys& s = h->sys[sys];
+  out->M = s.M; out->n_q = s.NQ; out->n_slices = s.n; out->n_walkers = s.p.n_walkers;
+  out->slice = s.k; out->n_measure = s.nrec; out->ld = s.ld;
+  out->beta = s.beta; out->dtau = s.dtau; out->L = s.L; out->omega = s.omega;
+  out->mu_T = s.muT; out->mu = s.mu; out->e_madelung = s.EM;
+  return FTAFQMC_OK;
+}
+
+int ftafqmc_reset(ftafqmc_t h, void* stream) {
+  if (!h) return FTAFQMC_E_ARG;
+  for (auto& s : h->sys) {
+    int rc = reset_sys(h, s, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return FTAFQMC_OK;
+}
+
+int ftafqmc_propagate(ftafqmc_t h, const void* const* d_fields, int n_slices, void* stream) {
+  if (!h) return FTAFQMC_E_ARG;
+  if (!d_fields || n_slices < 0) return h->set(FTAFQMC_E_ARG, "bad fields or slice count");
+  for (size_t i = 0; i < h->sys.size(); ++i)
+    if (!d_fields[i]) return h->set(FTAFQMC_E_ARG, "null fields pointer");
+  hipStream_t st = (hipStream_t)stream;
+  for (int j = 0; j < n_slices; ++j) {
+    bool any = false;
+    for (size_t i = 0; i < h->sys.size(); ++i) {
+      HostSys& s = h->sys[i];
+      if (s.k >= s.n) continue;
+      any = true;
+      int rc = step(h, s, (const double2*)d_fields[i], st);
+      if (rc) return rc;
+    }
+    if (!any) break;
+  }
+  return FTAFQMC_OK;
+}
+
+int ftafqmc_greens(ftafqmc_t h, int sys, void* d_G, int dtype, void* stream) {
+  int rc = check_handle(h, sys);
+  if (rc) return rc;
+  if (!d_G || (dtype != FTAFQMC_C128 && dtype != FTAFQMC_C64)) return h->set(FTAFQMC_E_ARG, "bad output");
+  HIPCHK(launch_copy_greens(h->sys[sys].dev, d_G, dtype, (hipStream_t)stream));
+  return FTAFQMC_OK;
+}
+
+int ftafqmc_energy(ftafqmc_t h, int sys, void* d_local, void* d_mean, double* d_logw, int* d_status,
+                   void* stream) {
+  int rc = check_handle(h, sys);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  HostSys& s = h->sys[sys];
+  HIPCHK(launch_energy(s.dev, -1, st));
+  HIPCHK(launch_energy_mean(s.dev, s.dev.local, s.dev.logw, s.dev.status, s.mean, st));
+  HIPCHK(launch_copy_state(s.dev, (double2*)d_local, d_logw, d_status, st));
+  if (d_mean) HIPCHK(hipMemcpyAsync(d_mean, s.mean, 4 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  return FTAFQMC_OK;
+}
+
+int ftafqmc_records(ftafqmc_t h, int sys, void* d_trace, double* d_logw, int* h_slice, void* stream) {
+  int rc = check_handle(h, sys);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  HostSys& s = h->sys[sys];
+  const size_t W = s.p.n_walkers;
+  if (d_trace && s.nrec)
+    HIPCHK(hipMemcpyAsync(d_trace, s.dev.rec_E, sizeof(double2) * 4 * W * s.nrec, hipMemcpyDeviceToDevice, st));
+  if (d_logw && s.nrec)
+    HIPCHK(hipMemcpyAsync(d_logw, s.dev.rec_logw, sizeof(double) * W * s.nrec, hipMemcpyDeviceToDevice, st));
+  if (h_slice)
+    for (int i = 0; i < s.nrec; ++i) h_slice[i] = s.rec_slice[i];
+  return FTAFQMC_OK;
+}
+
+int ftafqmc_backward(ftafqmc_t h, int sys, int mode, double* d_out, void* stream) {
+  int rc = check_handle(h, sys);
+  if (rc) return rc;
+  (void)mode; (void)d_out; (void)stream;
+  return h->set(FTAFQMC_E_UNSUPPORTED, "backward not built yet");
+}
+
+int ftafqmc_profile(ftafqmc_t h, int enable, double* h_ms, long long* h_count) {
+  if (!h) return FTAFQMC_E_ARG;
+  if (enable) {
+    h->prof = true;
+    return FTAFQMC_OK;
+  }
+  h->prof = false;
+  if (h_ms) for (int c = 0; c < FTAFQMC_PROF_CLASSES; ++c) h_ms[c] = 0.0;
+  if (h_count) for (int c = 0; c < FTAFQMC_PROF_CLASSES; ++c) h_count[c] = 0;
+  int rc = FTAFQMC_OK;
+  for (auto& ev : h->events) {
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(ev.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.a, ev.b);
+    if (e != hipSuccess) rc = h->set(FTAFQMC_E_HIP, std::string("profile events: ") + hipGetErrorString(e));
+    if (h_ms && ev.cls >= 0 && ev.cls < FTAFQMC_PROF_CLASSES) h_ms[ev.cls] += ms;
+    if (h_count && ev.cls >= 0 && ev.cls < FTAFQMC_PROF_CLASSES) h_count[ev.cls] += 1;
+    (void)hipEventDestroy(ev.a);
+    (void)hipEventDestroy(ev.b);
+  }
+  h->events.clear();
+  return rc;
+}
+
+const char* ftafqmc_last_error(ftafqmc_t h) { return h ? h->err.c_str() : "null handle"; }
+
+void ftafqmc_destroy(ftafqmc_t h) {
+  if (!h) return;
+  for (auto& ev : h->events) { (void)hipEventDestroy(ev.a); (void)hipEventDestroy(ev.b); }
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,593 @@
+// Slice-path kernels other than the GEMMs and the elimination.
+//
+// Notation: per walker the sampled product is R_k = Y diag(D) T with Ti = T^{-1}; the
+// constrained product is A_k = L_k R_k with the diagonal trial block
+// L_k = B_T^{n-k} (eq. Abrenda).  Scale splitting: L = L_s / L_b and D = D_s / D_b
+// with L_b = 1/max(1,|L|), D_b = 1/max(1,|D|) (Sec. "Numerical Stabilization"), so
+//   I + A = L_b^{-1} X D_b^{-1} T,   X = L_b Ti D_b + L_s Y D_s,
+//   G = (I + A)^{-1} = (Ti D_b) X^{-1} L_b,
+//   ln det(I + A) = ln det X + ln det T - sum ln L_b - sum ln D_b.
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int TT = 32;  // transpose tile
+constexpr double PI = 3.14159265358979323846;
+
+FT_DEV double2 zero2() { return make_double2(0.0, 0.0); }
+
+// ------------------------------------------------------------------ init ---
+__global__ __launch_bounds__(NT) void init_state_kernel(SysDev s) {
+  const long long total = (long long)s.W * s.mat_stride;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < total; e += (long long)gridDim.x * NT) {
+    const long long loc = e % s.mat_stride;
+    const int i = (int)(loc / s.ld), j = (int)(loc % s.ld);
+    const double2 v = (i == j && i < s.M) ? make_double2(1.0, 0.0) : zero2();
+    s.Y[e] = v;
+    s.Ti[e] = v;
+  }
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < (long long)s.W * s.ld; e += (long long)gridDim.x * NT)
+    s.D[e] = ((int)(e % s.ld) < s.M) ? 1.0 : 0.0;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < s.W; e += (long long)gridDim.x * NT) {
+    s.lndetT[e] = zero2();
+    s.logw[e] = 0.0;
+    s.status[e] = 0;
+    s.expo[e] = zero2();
+  }
+}
+
+// ------------------------------------------------- force-bias shifted V ---
+// c_Q = i s_Q (z_Q + conj z_{-Q}) - 2 dtau v_Q r_{-Q}: the coefficient of rho(Q) in
+// sqrt(dtau) (x - xbar).v with xbar_A = -2i s_Q (r_Q + r_{-Q}), xbar_B = 2 s_Q (r_Q - r_{-Q}),
+// r_Q = <rho(Q)> per spin; the weight exponent is sum_Q [x.xbar - xbar.xbar/2].
+template <typename TV>
+__global__ __launch_bounds__(NT) void coef_v_kernel(SysDev s, const double2* fields, int k, TV* V) {
+  extern __shared__ double2 csh[];
+  __shared__ double red[8];
+  const int w = blockIdx.x;
+  if (w >= s.W) return;
+  const double2* z = fields + ((long long)w * s.n + k) * s.NQ;
+  const double2* r = s.r + (long long)w * s.NQ;
+  double2 ex = zero2();
+  for (int q = threadIdx.x; q < s.NQ; q += NT) {
+    const int nq = s.neg[q];
+    const double2 zq = z[q], zn = z[nq], rq = r[q], rn = r[nq];
+    const double sqv = s.sq[q], vqv = s.vq[q];
+    // i s (z_q + conj z_-q)
+    const double2 u = make_double2(zq.x + zn.x, zq.y - zn.y);
+    double2 c = make_double2(-sqv * u.y, sqv * u.x);
+    c.x -= 2.0 * s.dtau * vqv * rn.x;
+    c.y -= 2.0 * s.dtau * vqv * rn.y;
+    csh[q] = c;
+    // xbar_A = -2i s (r_q + r_-q), xbar_B = 2 s (r_q - r_-q)
+    const double2 sp = make_double2(rq.x + rn.x, rq.y + rn.y), sm = make_double2(rq.x - rn.x, rq.y - rn.y);
+    const double2 xa = make_double2(2.0 * sqv * sp.y, -2.0 * sqv * sp.x);
+    const double2 xb = make_double2(2.0 * sqv * sm.x, 2.0 * sqv * sm.y);
+    const double2 xa2 = cmul(xa, xa), xb2 = cmul(xb, xb);
+    ex.x += zq.x * xa.x + zq.y * xb.x - 0.5 * (xa2.x + xb2.x);
+    ex.y += zq.x * xa.y + zq.y * xb.y - 0.5 * (xa2.y + xb2.y);
+  }
+  ex = block_csum_256(ex, red);
+  if (threadIdx.x == 0) s.expo[w] = ex;
+  __syncthreads();
+  TV* Vw = V + (long long)w * s.mat_stride;
+  const int ld = s.ld, M = s.M;
+  for (int e = threadIdx.x; e < ld * ld; e += NT) {
+    const int i = e / ld, j = e - i * ld;
+    double2 v = zero2();
+    if (i < M && j < M && i != j) v = csh[s.idx[i * M + j]];
+    store_c(Vw + e, v);
+  }
+}
+
+// ------------------------------------------------------ Green's function ---
+FT_DEV void split_L(const SysDev& s, int i, int k, double* lb, double* ls) {
+  const double lnl = (double)(s.n - k) * s.lnbt[i];
+  *lb = exp(-fmax(lnl, 0.0));
+  *ls = exp(fmin(lnl, 0.0));
+}
+FT_DEV void split_D(double d, double* db, double* ds) {
+  const double a = fabs(d);
+  if (a > 1.0) { *db = 1.0 / a; *ds = d / a; }
+  else { *db = 1.0; *ds = d; }
+}
+
+// aug[i][j] = X[j][i], aug[i][ld + j] = (Ti D_b)[j][i]  (transposed through LDS)
+__global__ __launch_bounds__(NT) void greens_form_kernel(SysDev s, int k) {
+  __shared__ double2 tX[TT][TT + 1];
+  __shared__ double2 tU[TT][TT + 1];
+  const int nt = (s.ld + TT - 1) / TT;
+  int w, tile;
+  if (!xcd_walker_tile(blockIdx.x, s.W, nt * nt, &w, &tile)) return;
+  const int ti = tile / nt, tj = tile - ti * nt;   // aug rows ti*TT.., aug cols tj*TT..
+  const double2* Y = s.Y + (long long)w * s.mat_stride;
+  const double2* Ti = s.Ti + (long long)w * s.mat_stride;
+  const double* D = s.D + (long long)w * s.ld;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int yy = ty; yy < TT; yy += 8) {
+    const int row = tj * TT + yy, col = ti * TT + tx;   // element (row=j, col=i) of Y and Ti
+    double2 x = zero2(), u = zero2();
+    if (row < s.M && col < s.M) {
+      double lb, ls, db, ds;
+      split_L(s, row, k, &lb, &ls);
+      split_D(D[col], &db, &ds);
+      const double2 tv = Ti[(long long)row * s.ld + col], yv = Y[(long long)row * s.ld + col];
+      u = cscale(tv, db);
+      x = make_double2(lb * u.x + ls * ds * yv.x, lb * u.y + ls * ds * yv.y);
+    }
+    tX[yy][tx] = x;
+    tU[yy][tx] = u;
+  }
+  __syncthreads();
+  double2* aug = s.aug + (long long)w * s.aug_stride;
+  for (int yy = ty; yy < TT; yy += 8) {
+    const int i = ti * TT + yy, j = tj * TT + tx;
+    if (i < s.ld && j < s.ld) {
+      aug[(long long)i * 2 * s.ld + j] = tX[tx][yy];
+      aug[(long long)i * 2 * s.ld + s.ld + j] = tU[tx][yy];
+    }
+  }
+}
+
+// G[i][j] = H[j][i] L_b[j] with H = aug right block (= X^{-T} (Ti D_b)^T)
+__global__ __launch_bounds__(NT) void greens_post_kernel(SysDev s, int k) {
+  __shared__ double2 tH[TT][TT + 1];
+  const int nt = (s.ld + TT - 1) / TT;
+  int w, tile;
+  if (!xcd_walker_tile(blockIdx.x, s.W, nt * nt, &w, &tile)) return;
+  const int ti = tile / nt, tj = tile - ti * nt;   // G rows ti.., cols tj..
+  const double2* aug = s.aug + (long long)w * s.aug_stride;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < TT; yy += 8) {
+    const int row = tj * TT + yy, col = ti * TT + tx;   // H[row=j][col=i]
+    double2 h = zero2();
+    if (row < s.M && col < s.M) {
+      double lb, ls;
+      split_L(s, row, k, &lb, &ls);
+      h = cscale(aug[(long long)row * 2 * s.ld + s.ld + col], lb);
+    }
+    tH[yy][tx] = h;
+  }
+  __syncthreads();
+  double2* G = s.G + (long long)w * s.mat_stride;
+  for (int yy = ty; yy < TT; yy += 8) {
+    const int i = ti * TT + yy, j = tj * TT + tx;
+    if (i < s.ld && j < s.ld) G[(long long)i * s.ld + j] = tH[tx][yy];
+  }
+}
+
+// r_Q = sum over pairs K_p - K_r = Q of P_pr = -G_rp; ln det(I + A_k); phaseless weight.
+__global__ __launch_bounds__(NT) void weight_kernel(SysDev s, int k, double sum_lnLb, int init) {
+  __shared__ double red[8];
+  const int w = blockIdx.x;
+  if (w >= s.W) return;
+  const double2* G = s.G + (long long)w * s.mat_stride;
+  double2* r = s.r + (long long)w * s.NQ;
+  double bad = 0.0;
+  for (int q = threadIdx.x; q < s.NQ; q += NT) {
+    double2 acc = zero2();
+    for (int e = s.qptr[q]; e < s.qptr[q + 1]; ++e) acc = csub(acc, G[s.qpair[e]]);
+    r[q] = acc;
+    if (!isfinite(acc.x) || !isfinite(acc.y)) bad = 1.0;
+  }
+  double sdb = 0.0;
+  const double* D = s.D + (long long)w * s.ld;
+  for (int i = threadIdx.x; i < s.M; i += NT) sdb += log(fmax(fabs(D[i]), 1.0));   // -ln D_b
+  sdb = block_sum_256(sdb, red);
+  bad = block_sum_256(bad, red);
+  if (threadIdx.x != 0) return;
+  const double2 lx = s.lndetX[w], lt = s.lndetT[w];
+  // ln det(I + A) = ln det X + ln det T - sum ln L_b - sum ln D_b
+  const double2 ell = make_double2(lx.x + lt.x - sum_lnLb + sdb, lx.y + lt.y);
+  int st = s.status[w];
+  if (init) {
+    s.ell[w] = ell;
+    if (!(isfinite(ell.x) && isfinite(ell.y)) || bad > 0.0) s.status[w] = 2;
+    return;
+  }
+  const double2 old = s.ell[w];
+  s.ell[w] = ell;
+  // S = det(I + A_{k+1})^2 / det(I + A_k)^2 ; theta = arg S in (-pi, pi]
+  const double2 lnS = make_double2(2.0 * (ell.x - old.x), 2.0 * (ell.y - old.y));
+  double th = remainder(lnS.y, 2.0 * PI);
+  if (th <= -PI) th += 2.0 * PI;
+  const double lnI = lnS.x + s.expo[w].x;
+  s.slice_lnS[(long long)w * s.n + (k - 1)] = lnS;
+  s.slice_theta[(long long)w * s.n + (k - 1)] = th;
+  if (st == 0) {
+    const double cth = cos(th);
+    if (!(isfinite(lnI) && isfinite(ell.x) && isfinite(ell.y)) || bad > 0.0) { s.status[w] = 2; s.logw[w] = -INFINITY; }
+    else if (cth <= 0.0) { s.status[w] = 1; s.logw[w] = -INFINITY; }
+    else s.logw[w] += lnI + log(cth);
+  }
+}
+
+// ------------------------------------------------------- stabilisation ---
+// Pre-pivoting: order the columns of Y diag(D) by decreasing norm.
+__global__ __launch_bounds__(NT) void stab_perm_kernel(SysDev s) {
+  extern __shared__ double nrm[];           // [M]
+  __shared__ int parity_sh;
+  const int w = blockIdx.x;
+  if (w >= s.W) return;
+  const double2* Y = s.Y + (long long)w * s.mat_stride;
+  const double* D = s.D + (long long)w * s.ld;
+  const int M = s.M, ld = s.ld;
+  for (int j = threadIdx.x; j < M; j += NT) {
+    double a = 0.0;
+    for (int i = 0; i < M; ++i) a += cabs2(Y[(long long)i * ld + j]);
+    const double v = sqrt(a) * fabs(D[j]);
+    nrm[j] = (v == v) ? v : -1.0;   // a NaN norm ranks last, so ranks stay a permutation
+  }
+  __syncthreads();
+  int* perm = s.perm + (long long)w * ld;
+  double* Dpi = s.Dpi + (long long)w * ld;
+  for (int j = threadIdx.x; j < M; j += NT) {
+    const double v = nrm[j];
+    int rank = 0;
+    for (int i = 0; i < M; ++i) {
+      const double u = nrm[i];
+      rank += (u > v || (u == v && i < j)) ? 1 : 0;
+    }
+    perm[rank] = j;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < M; j += NT) Dpi[j] = D[perm[j]];
+  if (threadIdx.x == 0) {
+    // parity by counting cycles; visited flags reuse the norm array
+    int par = 0;
+    for (int i = 0; i < M; ++i) nrm[i] = 0.0;
+    for (int i = 0; i < M; ++i) {
+      if (nrm[i] != 0.0) continue;
+      int j = i, len = 0;
+      while (j >= 0 && j < M && nrm[j] == 0.0) { nrm[j] = 1.0; j = perm[j]; ++len; }
+      par += len - 1;
+    }
+    parity_sh = par & 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && parity_sh) s.lndetT[w].y += PI;
+}
+
+// E0 = Y[:, perm]; aug right block = E0^H
+__global__ __launch_bounds__(NT) void stab_gather_kernel(SysDev s) {
+  __shared__ double2 tile_sh[TT][TT + 1];
+  const int nt = (s.ld + TT - 1) / TT;
+  int w, tile;
+  if (!xcd_walker_tile(blockIdx.x, s.W, nt * nt, &w, &tile)) return;
+  const int ti = tile / nt, tj = tile - ti * nt;   // E0 rows ti.., cols tj..
+  const double2* Y = s.Y + (long long)w * s.mat_stride;
+  const int* perm = s.perm + (long long)w * s.ld;
+  double2* E0 = (double2*)s.E0 + (long long)w * s.mat_stride;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < TT; yy += 8) {
+    const int i = ti * TT + yy, j = tj * TT + tx;
+    double2 v = zero2();
+    if (i < s.M && j < s.M) v = Y[(long long)i * s.ld + perm[j]];
+    if (i < s.ld && j < s.ld) E0[(long long)i * s.ld + j] = v;
+    tile_sh[yy][tx] = v;
+  }
+  __syncthreads();
+  double2* aug = s.aug + (long long)w * s.aug_stride;
+  for (int yy = ty; yy < TT; yy += 8) {
+    const int j = tj * TT + yy, i = ti * TT + tx;    // aug[j][ld + i] = conj(E0[i][j])
+    if (i < s.ld && j < s.ld) aug[(long long)j * 2 * s.ld + s.ld + i] = cconj(tile_sh[tx][yy]);
+  }
+}
+
+// After the Cholesky elimination of [S | E0^H]: U = aug left (S = L D L^H, U = D L^H),
+// aug right = L'^{-1} E0^H with L' unit lower.  R1 = D^{-1/2} U, Q^H = D^{-1/2} (aug right).
+// Writes Y = Q, D_new = sqrt(d) D_pi, and Ru = D_new^{-1} R1 D_pi (unit upper) into E1.
+__global__ __launch_bounds__(NT) void stab_finish_a_kernel(SysDev s) {
+  __shared__ double2 tile_sh[TT][TT + 1];
+  const int nt = (s.ld + TT - 1) / TT;
+  int w, tile;
+  if (!xcd_walker_tile(blockIdx.x, s.W, nt * nt, &w, &tile)) return;
+  const int ti = tile / nt, tj = tile - ti * nt;   // aug rows ti.., cols tj..
+  const double2* aug = s.aug + (long long)w * s.aug_stride;
+  const double* Dpi = s.Dpi + (long long)w * s.ld;
+  double2* Ru = (double2*)s.E1 + (long long)w * s.mat_stride;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int ld2 = 2 * s.ld;
+  for (int yy = ty; yy < TT; yy += 8) {
+    const int i = ti * TT + yy, j = tj * TT + tx;
+    double2 q = zero2(), ru = zero2();
+    if (i < s.M && j < s.M) {
+      const double d = aug[(long long)i * ld2 + i].x;
+      const double sd = sqrt(d);
+      q = cscale(aug[(long long)i * ld2 + s.ld + j], 1.0 / sd);
+      if (j == i) ru = make_double2(1.0, 0.0);
+      else if (j > i) ru = cscale(aug[(long long)i * ld2 + j], Dpi[j] / (d * Dpi[i]));
+    }
+    if (i < s.ld && j < s.ld) Ru[(long long)i * s.ld + j] = ru;
+    tile_sh[yy][tx] = q;
+  }
+  __syncthreads();
+  double2* Y = s.Y + (long long)w * s.mat_stride;
+  for (int yy = ty; yy < TT; yy += 8) {
+    const int j = tj * TT + yy, i = ti * TT + tx;   // Y[j][i] = conj(Q^H[i][j])
+    if (i < s.ld && j < s.ld) Y[(long long)j * s.ld + i] = cconj(tile_sh[tx][yy]);
+  }
+}
+
+__global__ __launch_bounds__(NT) void stab_newd_kernel(SysDev s) {
+  const int w = blockIdx.x;
+  if (w >= s.W) return;
+  const double2* aug = s.aug + (long long)w * s.aug_stride;
+  const double* Dpi = s.Dpi + (long long)w * s.ld;
+  double* D = s.D + (long long)w * s.ld;
+  int bad = 0;
+  for (int i = threadIdx.x; i < s.ld; i += NT) {
+    double v = 0.0;
+    if (i < s.M) {
+      const double d = aug[(long long)i * 2 * s.ld + i].x;
+      if (!(d > 0.0) || !isfinite(d)) bad = 1;
+      v = sqrt(d) * Dpi[i];
+    }
+    D[i] = v;
+  }
+  if (bad) s.status[w] = 2;   // Cholesky breakdown: the partial product was too ill-conditioned
+}
+
+// aug = [Ru^T | (Ti[:, perm])^T]
+__global__ __launch_bounds__(NT) void stab_build_ti_kernel(SysDev s) {
+  __shared__ double2 tR[TT][TT + 1];
+  __shared__ double2 tT[TT][TT + 1];
+  const int nt = (s.ld + TT - 1) / TT;
+  int w, tile;
+  if (!xcd_walker_tile(blockIdx.x, s.W, nt * nt, &w, &tile)) return;
+  const int ti = tile / nt, tj = tile - ti * nt;   // aug rows ti.., cols tj..
+  const double2* Ru = (const double2*)s.E1 + (long long)w * s.mat_stride;
+  const double2* Ti = s.Ti + (long long)w * s.mat_stride;
+  const int* perm = s.perm + (long long)w * s.ld;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < TT; yy += 8) {
+    const int row = tj * TT + yy, col = ti * TT + tx;   // source element (row=j, col=i)
+    double2 a = zero2(), b = zero2();
+    if (row < s.M && col < s.M) {
+      a = Ru[(long long)row * s.ld + col];
+      b = Ti[(long long)row * s.ld + perm[col]];
+    }
+    tR[yy][tx] = a;
+    tT[yy][tx] = b;
+  }
+  __syncthreads();
+  double2* aug = s.aug + (long long)w * s.aug_stride;
+  for (int yy = ty; yy < TT; yy += 8) {
+    const int i = ti * TT + yy, j = tj * TT + tx;
+    if (i < s.ld && j < s.ld) {
+      aug[(long long)i * 2 * s.ld + j] = tR[tx][yy];
+      aug[(long long)i * 2 * s.ld + s.ld + j] = tT[tx][yy];
+    }
+  }
+}
+
+// Ti[i][j] = aug[j][ld + i]
+__global__ __launch_bounds__(NT) void stab_finish_b_kernel(SysDev s) {
+  __shared__ double2 tile_sh[TT][TT + 1];
+  const int nt = (s.ld + TT - 1) / TT;
+  int w, tile;
+  if (!xcd_walker_tile(blockIdx.x, s.W, nt * nt, &w, &tile)) return;
+  const int ti = tile / nt, tj = tile - ti * nt;   // Ti rows ti.., cols tj..
+  const double2* aug = s.aug + (long long)w * s.aug_stride;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < TT; yy += 8) {
+    const int row = tj * TT + yy, col = ti * TT + tx;   // aug[row=j][ld + col=i]
+    double2 v = zero2();
+    if (row < s.M && col < s.M) v = aug[(long long)row * 2 * s.ld + s.ld + col];
+    tile_sh[yy][tx] = v;
+  }
+  __syncthreads();
+  double2* Ti = s.Ti + (long long)w * s.mat_stride;
+  for (int yy = ty; yy < TT; yy += 8) {
+    const int i = ti * TT + yy, j = tj * TT + tx;
+    if (i < s.ld && j < s.ld) Ti[(long long)i * s.ld + j] = tile_sh[tx][yy];
+  }
+}
+
+// ---------------------------------------------------------------- energy ---
+// Exchange: sum_Q v_Q Lambda_Q = sum_{a != d} v(K_a - K_d) sum_b P_ab P_cd with
+// K_c = K_b - (K_a - K_d), P = I - G^T.  One workgroup per (walker, a).
+__global__ __launch_bounds__(NT) void exchange_kernel(SysDev s) {
+  extern __shared__ char dyn[];
+  double2* pcol = (double2*)dyn;                    // [M]: P_ab = delta_ab - G_ba
+  short* grid = (short*)(pcol + s.M);               // [grid_dim^3]
+  __shared__ double red[8];
+  int w, a;
+  if (!xcd_walker_tile(blockIdx.x, s.W, s.M, &w, &a)) return;
+  const double2* G = s.G + (long long)w * s.mat_stride;
+  const int M = s.M, ld = s.ld;
+  const int g3 = s.grid_dim * s.grid_dim * s.grid_dim;
+  for (int e = threadIdx.x; e < g3; e += NT) grid[e] = s.grid[e];
+  for (int b = threadIdx.x; b < M; b += NT) {
+    double2 v = cscale(G[(long long)b * ld + a], -1.0);
+    if (b == a) v.x += 1.0;
+    pcol[b] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double2 acc = zero2();
+  for (int d = wid; d < M; d += 4) {
+    if (d == a) continue;
+    const double v = s.vq[s.idx[a * M + d]];
+    const double2* Gd = G + (long long)d * ld;
+    // grid index of K_b - K_a + K_d is flat[b] + flat[d] - flat[a] + grid_c0
+    const int off = s.flat[d] - s.flat[a] + s.grid_c0;
+    double2 part = zero2();
+    for (int b = lane; b < M; b += 64) {
+      const int c = grid[s.flat[b] + off];
+      if (c >= 0) {
+        double2 pcd = cscale(Gd[c], -1.0);      // P_cd = delta_cd - G_dc
+        if (c == d) pcd.x += 1.0;
+        const double2 pr = cmul(pcol[b], pcd);
+        part.x += pr.x;
+        part.y += pr.y;
+      }
+    }
+    acc.x += v * part.x;
+    acc.y += v * part.y;
+  }
+  acc = block_csum_256(acc, red);
+  if (threadIdx.x == 0) s.exch[(long long)w * ld + a] = acc;
+}
+
+// E1 = 2 lambda sum eps P_KK, N = 2 sum P_KK, Hartree = (1/2) sum v_Q 4 r_Q r_-Q,
+// E2 = Hartree - sum_Q v_Q Lambda_Q, E = E1 + E2 + E_M.
+__global__ __launch_bounds__(NT) void energy_finish_kernel(SysDev s, int rec) {
+  __shared__ double red[8];
+  const int w = blockIdx.x;
+  if (w >= s.W) return;
+  const double2* G = s.G + (long long)w * s.mat_stride;
+  const double2* r = s.r + (long long)w * s.NQ;
+  double2 e1 = zero2(), nn = zero2(), hart = zero2(), ex = zero2();
+  for (int i = threadIdx.x; i < s.M; i += NT) {
+    const double2 g = G[(long long)i * s.ld + i];
+    const double2 pkk = make_double2(1.0 - g.x, -g.y);
+    e1 = cadd(e1, cscale(pkk, s.eps[i]));
+    nn = cadd(nn, pkk);
+    ex = cadd(ex, s.exch[(long long)w * s.ld + i]);
+  }
+  for (int q = threadIdx.x; q < s.NQ; q += NT) hart = cadd(hart, cscale(cmul(r[q], r[s.neg[q]]), s.vq[q]));
+  e1 = block_csum_256(e1, red);
+  nn = block_csum_256(nn, red);
+  hart = block_csum_256(hart, red);
+  ex = block_csum_256(ex, red);
+  if (threadIdx.x != 0) return;
+  const double2 E1 = cscale(e1, 2.0 * s.kscale);
+  const double2 N = cscale(nn, 2.0);
+  const double2 E2 = csub(cscale(hart, 2.0), ex);
+  const double2 E = make_double2(E1.x + E2.x + s.e_madelung, E1.y + E2.y);
+  double2* out = s.local + (long long)w * 4;
+  out[0] = E1; out[1] = E2; out[2] = E; out[3] = N;
+  if (rec >= 0) {
+    double2* ro = s.rec_E + ((long long)rec * s.W + w) * 4;
+    ro[0] = E1; ro[1] = E2; ro[2] = E; ro[3] = N;
+    s.rec_logw[(long long)rec * s.W + w] = s.logw[w];
+    s.rec_status[(long long)rec * s.W + w] = s.status[w];
+  }
+}
+
+// weighted means over live walkers: sum_w e^{logw - max} O_w / sum_w e^{logw - max}
+__global__ __launch_bounds__(NT) void energy_mean_kernel(const double2* local, const double* logw,
+                                                         const int* status, int W, double2* mean) {
+  __shared__ double red[8];
+  double mx = -INFINITY;
+  for (int w = threadIdx.x; w < W; w += NT)
+    if (status[w] == 0 && isfinite(logw[w])) mx = fmax(mx, logw[w]);
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  __shared__ double mxs[4];
+  if ((threadIdx.x & 63) == 0) mxs[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  mx = fmax(fmax(mxs[0], mxs[1]), fmax(mxs[2], mxs[3]));
+  __syncthreads();
+  double ws = 0.0;
+  double2 acc[4] = {zero2(), zero2(), zero2(), zero2()};
+  for (int w = threadIdx.x; w < W; w += NT) {
+    if (status[w] == 0 && isfinite(logw[w])) {
+      const double f = exp(logw[w] - mx);
+      ws += f;
+      for (int c = 0; c < 4; ++c) acc[c] = cadd(acc[c], cscale(local[(long long)w * 4 + c], f));
+    }
+  }
+  ws = block_sum_256(ws, red);
+  for (int c = 0; c < 4; ++c) acc[c] = block_csum_256(acc[c], red);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 4; ++c)
+      mean[c] = ws > 0.0 ? cscale(acc[c], 1.0 / ws) : make_double2(NAN, NAN);
+}
+
+template <typename TO>
+__global__ __launch_bounds__(NT) void copy_greens_kernel(SysDev s, TO* out) {
+  const long long total = (long long)s.W * s.M * s.M;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < total; e += (long long)gridDim.x * NT) {
+    const long long w = e / ((long long)s.M * s.M);
+    const int loc = (int)(e - w * s.M * s.M);
+    const int i = loc / s.M, j = loc - i * s.M;
+    store_c(out + e, s.G[w * s.mat_stride + (long long)i * s.ld + j]);
+  }
+}
+
+__global__ __launch_bounds__(NT) void copy_state_kernel(SysDev s, double2* local, double* logw, int* status) {
+  for (int w = blockIdx.x * NT + threadIdx.x; w < s.W; w += gridDim.x * NT) {
+    if (local)
+      for (int c = 0; c < 4; ++c) local[(long long)w * 4 + c] = s.local[(long long)w * 4 + c];
+    if (logw) logw[w] = s.logw[w];
+    if (status) status[w] = s.status[w];
+  }
+}
+
+int tiles_blocks(const SysDev& s, int per_walker) { return ((s.W + 7) / 8) * 8 * per_walker; }
+int tt_tiles(const SysDev& s) { const int nt = (s.ld + TT - 1) / TT; return nt * nt; }
+
+}  // namespace
+
+hipError_t launch_init_state(const SysDev& s, hipStream_t st) {
+  init_state_kernel<<<1024, NT, 0, st>>>(s);
+  return hipGetLastError();
+}
+hipError_t launch_coef_v(const SysDev& s, const double2* fields, int k, int mixed, hipStream_t st) {
+  const size_t shm = (size_t)s.NQ * sizeof(double2);
+  if (mixed) coef_v_kernel<float2><<<s.W, NT, shm, st>>>(s, fields, k, (float2*)s.V);
+  else coef_v_kernel<double2><<<s.W, NT, shm, st>>>(s, fields, k, (double2*)s.V);
+  return hipGetLastError();
+}
+hipError_t launch_greens_form(const SysDev& s, int k, hipStream_t st) {
+  greens_form_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s, k);
+  return hipGetLastError();
+}
+hipError_t launch_greens_post(const SysDev& s, int k, hipStream_t st) {
+  greens_post_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s, k);
+  return hipGetLastError();
+}
+hipError_t launch_weight(const SysDev& s, int k, double sum_lnLb, int init, hipStream_t st) {
+  weight_kernel<<<s.W, NT, 0, st>>>(s, k, sum_lnLb, init);
+  return hipGetLastError();
+}
+hipError_t launch_stab_perm(const SysDev& s, hipStream_t st) {
+  stab_perm_kernel<<<s.W, NT, (size_t)s.M * sizeof(double), st>>>(s);
+  return hipGetLastError();
+}
+hipError_t launch_stab_gather(const SysDev& s, hipStream_t st) {
+  stab_gather_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s);
+  return hipGetLastError();
+}
+hipError_t launch_stab_finish_a(const SysDev& s, hipStream_t st) {
+  stab_finish_a_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  stab_newd_kernel<<<s.W, NT, 0, st>>>(s);
+  return hipGetLastError();
+}
+hipError_t launch_stab_build_ti(const SysDev& s, hipStream_t st) {
+  stab_build_ti_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s);
+  return hipGetLastError();
+}
+hipError_t launch_stab_finish_b(const SysDev& s, hipStream_t st) {
+  stab_finish_b_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s);
+  return hipGetLastError();
+}
+hipError_t launch_energy(const SysDev& s, int rec, hipStream_t st) {
+  const size_t shm = (size_t)s.M * sizeof(double2) +
+                     (size_t)s.grid_dim * s.grid_dim * s.grid_dim * sizeof(short) + 16;
+  exchange_kernel<<<tiles_blocks(s, s.M), NT, shm, st>>>(s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  energy_finish_kernel<<<s.W, NT, 0, st>>>(s, rec);
+  return hipGetLastError();
+}
+hipError_t launch_energy_mean(const SysDev& s, const double2* local, const double* logw, const int* status,
+                              double2* mean, hipStream_t st) {
+  energy_mean_kernel<<<1, NT, 0, st>>>(local, logw, status, s.W, mean);
+  return hipGetLastError();
+}
+hipError_t launch_copy_greens(const SysDev& s, void* out, int dtype, hipStream_t st) {
+  if (dtype == 0) copy_greens_kernel<double2><<<1024, NT, 0, st>>>(s, (double2*)out);
+  else copy_greens_kernel<float2><<<1024, NT, 0, st>>>(s, (float2*)out);
+  return hipGetLastError();
+}
+hipError_t launch_copy_state(const SysDev& s, double2* local_out, double* logw_out, int* status_out,
+                             hipStream_t st) {
+  copy_state_kernel<<<(s.W + NT - 1) / NT, NT, 0, st>>>(s, local_out, logw_out, status_out);
+  return hipGetLastError();
+}

@@ -36,6 +36,11 @@ WORKLOADS = {
 }
 
 
+def system_seed(workload, system_index):
+    """Seed of one system of a workload: the workload seed plus 1000 per system index."""
+    return int(WORKLOADS[workload]["seed"]) + 1000 * int(system_index)
+
+
 def walker_rng(seed, walker):
     """The generator of one walker: PCG64 seeded by the pair (seed, walker)."""
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(walker)])))

@@ -1,0 +1,70 @@
+"""Write stored oracle outputs for sampled walkers of the large workloads.
+
+Calls only oracle/ and the seeded input generator.  For each workload and each
+sampled walker it runs the FP64 oracle over the whole path and keeps, at every
+energy record (each stabilisation boundary and the last slice): E_1, E_2, E, N,
+ln w and the status; plus the final Green's function's diagonal and first rows.
+Usage: python tests/golden/make_oracle_golden.py [workload ...]
+"""
+import os
+import sys
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import ueg, path, energy  # noqa: E402
+import synthinputs as si  # noqa: E402
+
+SAMPLES = {
+    "ueg_n66_m171": {0: [0, 255]},
+    "ueg_n38_m123": {0: [0, 127]},
+    "ueg_uneven4": {0: [0, 170], 1: [0, 170], 2: [0, 84], 3: [0, 84]},
+    "ueg_n114_m485": {0: [0, 511]},
+}
+G_ROWS = 8
+
+
+def one(args):
+    name, sidx, w = args
+    from threadpoolctl import threadpool_limits
+    wl = si.WORKLOADS[name]
+    sd = wl["systems"][sidx]
+    s = ueg.UEGSystem(sd["n_elec"], sd["rs"], sd["theta"], sd["nmax2"], sd["dtau"], stab_every=sd["stab_every"])
+    z = si.walker_fields(si.system_seed(name, sidx), w, s.n_slices, s.NQ)
+    with threadpool_limits(2):
+        out = path.run_walker(s, z, energy_fn=energy.local_energy)
+    recs = out["records"]
+    return dict(
+        system=sidx, walker=w,
+        slices=np.array([r["slice"] for r in recs]),
+        E=np.array([[r["E1"], r["E2"], r["E"], r["N"]] for r in recs]),
+        logw=np.array([r["logw"] for r in recs]),
+        status=np.array([r["status"] for r in recs]),
+        G_diag=np.diagonal(out["G"]).copy(),
+        G_rows=out["G"][:G_ROWS].copy(),
+    )
+
+
+def main(names):
+    jobs = [(n, sidx, w) for n in names for sidx, ws in SAMPLES[n].items() for w in ws]
+    with ProcessPoolExecutor(max_workers=min(4, len(jobs))) as ex:
+        results = list(ex.map(one, jobs))
+    for n in names:
+        arrays = {}
+        for (jn, sidx, w), r in zip(jobs, results):
+            if jn != n:
+                continue
+            key = "s%d_w%d" % (sidx, w)
+            for k, v in r.items():
+                if k not in ("system", "walker"):
+                    arrays[key + "_" + k] = v
+        fn = os.path.join(HERE, "oracle_%s.npz" % n)
+        np.savez_compressed(fn, **arrays)
+        print("wrote", fn, os.path.getsize(fn), "bytes")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or list(SAMPLES))

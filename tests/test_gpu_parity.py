@@ -1,0 +1,269 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on identical seeded fields.
+
+Tolerances (written here, derived in the design notes):
+  FP64 path   -- relative 1e-10 for G (max-norm), E_1, E_2, E, N; ln w to 1e-10 * max(1, |ln w|);
+                 status words identical.
+  mixed path  -- complex64 propagator GEMMs with FP32 accumulation, FP64 everything else:
+                 E_1 + E_2 relative 1e-6, N relative 1e-6, G relative 1e-5, ln w relative 1e-5.
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ueg, path, energy  # noqa: E402
+import synthinputs as si  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+FP64_REL = 1e-10
+MIX_E12, MIX_N, MIX_G, MIX_LOGW = 1e-6, 1e-6, 1e-5, 1e-5
+
+
+def _F():
+    import paper_2012_12228_amd as F
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F.load_library()
+    return F
+
+
+def oracle_system(sd):
+    return ueg.UEGSystem(sd["n_elec"], sd["rs"], sd["theta"], sd["nmax2"], sd["dtau"],
+                         stab_every=sd.get("stab_every", 10), mu=sd.get("mu"), kscale=sd.get("kscale", 1.0))
+
+
+def gpu_run(F, systems, fields_list, n_slices=None):
+    ctx = F.Context(systems)
+    fds = [torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in fields_list]
+    ctx.propagate(fds, n_slices)
+    torch.cuda.synchronize()
+    return ctx, fds
+
+
+def relc(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def rel_mat(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def check_walker(rec_gpu, logw_gpu, G_gpu, ref, mixed=False, label=""):
+    """rec_gpu [n_rec][4] complex, logw_gpu [n_rec]; ref: oracle output dict."""
+    recs = ref["records"]
+    assert len(recs) == rec_gpu.shape[0], label
+    for j, r in enumerate(recs):
+        e1, e2, e, nn = rec_gpu[j]
+        if mixed:
+            assert relc(e1 + e2, r["E1"] + r["E2"]) < MIX_E12, (label, j)
+            assert relc(nn, r["N"]) < MIX_N, (label, j)
+        else:
+            for got, want in ((e1, r["E1"]), (e2, r["E2"]), (e, r["E"]), (nn, r["N"])):
+                assert relc(got, want) < FP64_REL, (label, j, got, want)
+        if np.isfinite(r["logw"]):
+            tol = (MIX_LOGW if mixed else FP64_REL) * max(1.0, abs(r["logw"]))
+            assert abs(logw_gpu[j] - r["logw"]) < tol, (label, j, logw_gpu[j], r["logw"])
+        else:
+            assert logw_gpu[j] == -np.inf, (label, j)
+    if G_gpu is not None:
+        assert rel_mat(G_gpu, ref["G"]) < (MIX_G if mixed else FP64_REL), label
+
+
+# --------------------------------------------------------------- small ---
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_m19_all_walkers_full_path(precision):
+    F = _F()
+    wl = si.WORKLOADS["ueg_n14_m19"]
+    sd = dict(wl["systems"][0], precision=precision)
+    s = oracle_system(sd)
+    W = sd["walkers"]
+    flds = si.fields(si.system_seed("ueg_n14_m19", 0), W, s.n_slices, s.NQ)
+    ctx, _ = gpu_run(F, [sd], [flds])
+    inf = ctx.info()
+    assert (inf["M"], inf["n_q"], inf["n_slices"]) == (s.M, s.NQ, s.n_slices)
+    assert inf["mu_T"] == pytest.approx(s.mu_T, rel=1e-13)
+    rec = ctx.records()
+    trace = rec["trace"].cpu().numpy()
+    logw = rec["logw"].cpu().numpy()
+    G = ctx.greens().cpu().numpy()
+    for w in range(W):
+        ref = path.run_walker(s, flds[w], energy_fn=energy.local_energy)
+        check_walker(trace[:, w], logw[:, w], G[w], ref, mixed=precision == 1, label="walker %d" % w)
+    assert rec["slices"] == [r["slice"] for r in ref["records"]]
+
+
+def test_ragged_m57_every_slice_stabilised_and_kscale_mu():
+    """M=57 (ragged against 16/64 tiles), stabilisation every slice, lambda != 1, explicit mu."""
+    F = _F()
+    sd = dict(n_elec=38, rs=1.0, theta=0.25, nmax2=5, dtau=0.05, stab_every=1, walkers=5,
+              kscale=0.85, mu=1.2)
+    s = oracle_system(sd)
+    flds = si.fields(77, sd["walkers"], s.n_slices, s.NQ)
+    ctx, _ = gpu_run(F, [sd], [flds])
+    rec = ctx.records()
+    G = ctx.greens().cpu().numpy()
+    for w in range(sd["walkers"]):
+        ref = path.run_walker(s, flds[w], energy_fn=energy.local_energy)
+        check_walker(rec["trace"].cpu().numpy()[:, w], rec["logw"].cpu().numpy()[:, w], G[w], ref, label=w)
+
+
+def test_single_walker_stabilised_only_at_the_end():
+    F = _F()
+    sd = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=1000, walkers=1)
+    s = oracle_system(sd)
+    flds = si.fields(5, 1, s.n_slices, s.NQ)
+    ctx, _ = gpu_run(F, [sd], [flds])
+    rec = ctx.records()
+    assert rec["slices"] == [s.n_slices]
+    ref = path.run_walker(s, flds[0], energy_fn=energy.local_energy)
+    check_walker(rec["trace"].cpu().numpy()[:, 0], rec["logw"].cpu().numpy()[:, 0], ctx.greens().cpu().numpy()[0], ref)
+
+
+def test_zero_fields_closed_form():
+    F = _F()
+    sd = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5, walkers=3)
+    s = oracle_system(sd)
+    ctx, _ = gpu_run(F, [sd], [np.zeros((3, s.n_slices, s.NQ), complex)])
+    lev = s.eps + s.hK - s.mu
+    occ = 1 / (1 + np.exp(s.beta * lev))
+    G = ctx.greens().cpu().numpy()
+    for w in range(3):
+        assert np.abs(G[w] - np.diag(1 - occ)).max() < 1e-13
+    e = ctx.energy()
+    ell_n = np.sum(np.log1p(np.exp(-s.beta * lev)))
+    ell_0 = np.sum(np.log1p(np.exp(-s.beta * (s.eps - s.mu_T))))
+    assert np.allclose(e["logw"].cpu().numpy(), 2 * (ell_n - ell_0), rtol=1e-12)
+    assert e["mean"].cpu().numpy()[3].real == pytest.approx(2 * occ.sum(), rel=1e-12)
+
+
+def test_slicewise_calls_clamp_and_match_one_call():
+    F = _F()
+    sd = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5, walkers=4)
+    s = oracle_system(sd)
+    flds = si.fields(9, 4, s.n_slices, s.NQ)
+    a, fa = gpu_run(F, [sd], [flds])
+    b = F.Context([sd])
+    fb = torch.from_numpy(flds).cuda()
+    b.propagate([fb], 0)
+    assert b.info()["slice"] == 0
+    for _ in range(s.n_slices + 3):
+        b.propagate([fb], 1)
+    torch.cuda.synchronize()
+    assert b.info()["slice"] == s.n_slices
+    assert torch.equal(a.greens(), b.greens())
+    b.reset()
+    b.propagate([fb])
+    torch.cuda.synchronize()
+    assert torch.equal(a.greens(), b.greens())
+    assert b.info()["n_measure"] == a.info()["n_measure"]
+
+
+def test_bitwise_reproducible():
+    F = _F()
+    sd = dict(si.WORKLOADS["ueg_n14_m19"]["systems"][0], walkers=16)
+    s = oracle_system(sd)
+    flds = si.fields(3, 16, s.n_slices, s.NQ)
+    a, _ = gpu_run(F, [sd], [flds])
+    b, _ = gpu_run(F, [sd], [flds])
+    assert torch.equal(a.greens(), b.greens())
+    assert torch.equal(a.records()["trace"], b.records()["trace"])
+
+
+def test_phaseless_kills_match_oracle():
+    F = _F()
+    sd = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5, walkers=24)
+    s = oracle_system(sd)
+    flds = 6.0 * si.fields(4242, 24, s.n_slices, s.NQ)
+    ctx, _ = gpu_run(F, [sd], [flds])
+    st = ctx.energy()["status"].cpu().numpy()
+    refs = [path.run_walker(s, flds[w]) for w in range(24)]
+    want = np.array([r["status"] for r in refs])
+    assert (want == path.KILLED).any()
+    assert np.array_equal(st, want)
+    lw = ctx.energy()["logw"].cpu().numpy()
+    assert np.all(np.isinf(lw[want == path.KILLED]))
+    assert np.all(np.isfinite(ctx.greens().cpu().numpy()))
+
+
+def test_nan_fields_flag_only_that_walker():
+    F = _F()
+    sd = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5, walkers=4)
+    s = oracle_system(sd)
+    flds = si.fields(21, 4, s.n_slices, s.NQ)
+    bad = flds.copy()
+    bad[2, 3, 5] = np.nan
+    clean, _ = gpu_run(F, [sd], [flds])
+    dirty, _ = gpu_run(F, [sd], [bad])
+    st = dirty.energy()["status"].cpu().numpy()
+    assert list(st) == [0, 0, 2, 0]
+    Gc, Gd = clean.greens(), dirty.greens()
+    for w in (0, 1, 3):
+        assert torch.equal(Gc[w], Gd[w])
+
+
+# ---------------------------------------------------- full-size, sampled ---
+def _golden(name):
+    fn = os.path.join(GOLDEN, "oracle_%s.npz" % name)
+    if not os.path.exists(fn):
+        pytest.skip("stored oracle outputs missing: run tests/golden/make_oracle_golden.py")
+    return np.load(fn)
+
+
+def _check_golden(gold, key, trace, logw, G, slices, mixed=False):
+    assert list(gold[key + "_slices"]) == list(slices)
+    E = gold[key + "_E"]
+    lw = gold[key + "_logw"]
+    for j in range(len(slices)):
+        if mixed:
+            assert relc(trace[j, 0] + trace[j, 1], E[j, 0] + E[j, 1]) < MIX_E12, (key, j)
+            assert relc(trace[j, 3], E[j, 3]) < MIX_N, (key, j)
+        else:
+            for c in range(4):
+                assert relc(trace[j, c], E[j, c]) < FP64_REL, (key, j, c, trace[j, c], E[j, c])
+        tol = (MIX_LOGW if mixed else FP64_REL) * max(1.0, abs(lw[j]))
+        assert abs(logw[j] - lw[j]) < tol, (key, j, logw[j], lw[j])
+    tol = MIX_G if mixed else FP64_REL
+    assert rel_mat(np.diagonal(G), gold[key + "_G_diag"]) < tol
+    rows = gold[key + "_G_rows"]
+    assert rel_mat(G[:rows.shape[0]], rows) < tol
+
+
+def _full_size(name, precision):
+    F = _F()
+    wl = si.WORKLOADS[name]
+    gold = _golden(name)
+    systems = [dict(sd, precision=precision) for sd in wl["systems"]]
+    oss = [oracle_system(sd) for sd in systems]
+    flds = [si.fields(si.system_seed(name, i), sd["walkers"], s.n_slices, s.NQ)
+            for i, (sd, s) in enumerate(zip(systems, oss))]
+    ctx, _ = gpu_run(F, systems, flds)
+    for i in range(len(systems)):
+        rec = ctx.records(i)
+        trace, logw = rec["trace"].cpu().numpy(), rec["logw"].cpu().numpy()
+        G = ctx.greens(i).cpu().numpy()
+        for key in gold.files:
+            if key.startswith("s%d_w" % i) and key.endswith("_slices"):
+                k = key[:-len("_slices")]
+                w = int(k.split("_w")[1])
+                _check_golden(gold, k, trace[:, w], logw[:, w], G[w], rec["slices"], mixed=precision == 1)
+    return ctx
+
+
+def test_m171_full_size_fp64():
+    _full_size("ueg_n66_m171", 0)
+
+
+def test_m171_full_size_mixed():
+    _full_size("ueg_n66_m171", 1)
+
+
+def test_m123_full_size_fp64():
+    _full_size("ueg_n38_m123", 0)
+
+
+def test_uneven_four_systems_one_handle():
+    _full_size("ueg_uneven4", 1)
