@@ -92,8 +92,11 @@ def run_precision(F, torch, systems, fields, steps, warmup):
     per_launch = 8.0 * inf0["M"] ** 3 * inf0["n_walkers"]
     out["gemm_avg_ms"] = gemm_ms / max(gemm_n, 1)
     out["gemm_tflops"] = per_launch / (out["gemm_avg_ms"] * 1e-3) / 1e12
-    energies = [ctx.energy(i)["local"].cpu().numpy() for i in range(len(systems))]
-    status = [ctx.energy(i)["status"].cpu().numpy() for i in range(len(systems))]
+    energies, status = [], []
+    for i in range(len(systems)):
+        e = ctx.energy(i)
+        energies.append((e["local"].cpu().numpy(), e["logw"].cpu().numpy()))
+        status.append(e["status"].cpu().numpy())
     return ctx, out, energies, status
 
 
@@ -134,13 +137,19 @@ def main():
         torch.cuda.empty_cache()
     err = None
     if "fp64" in energies and "mixed" in energies:
-        errs = []
-        for (a, sa), (b, sb) in zip(zip(*energies["fp64"]), zip(*energies["mixed"])):
+        errs, nerrs, werrs = [], [], []
+        for ((a, la), sa), ((b, lb), sb) in zip(zip(*energies["fp64"]), zip(*energies["mixed"])):
             ok = (sa == 0) & (sb == 0)
             e12a, e12b = a[ok, 0] + a[ok, 1], b[ok, 0] + b[ok, 1]
             errs.append(np.max(np.abs(e12b - e12a) / np.abs(e12a)))
+            scaled = np.max(np.abs(e12b - e12a) / (np.abs(a[ok, 0]) + np.abs(a[ok, 1])))
+            nerrs.append(np.max(np.abs(b[ok, 3] - a[ok, 3]) / np.abs(a[ok, 3])))
+            werrs.append(np.max(np.abs(lb[ok] - la[ok])))
         err = float(max(errs))
         results["mixed"]["max_rel_err_E1E2_vs_fp64"] = err
+        results["mixed"]["max_err_E1E2_over_abs_sum_vs_fp64"] = float(scaled)
+        results["mixed"]["max_rel_err_N_vs_fp64"] = float(max(nerrs))
+        results["mixed"]["max_abs_err_logw_vs_fp64"] = float(max(werrs))
     use = "mixed" if ("mixed" in results and err is not None and err <= MIXED_E_TOL) else precs[0]
     if args.precision == "mixed":
         use = "mixed"

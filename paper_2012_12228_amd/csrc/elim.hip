@@ -1,290 +1,255 @@
-// Per-walker blocked Gaussian elimination on an augmented matrix [A | R].
+// Blocked Gaussian elimination on per-walker augmented matrices [A | R], batched over walkers.
 //
-// Used for three solves of the slice path, all by one 256-thread workgroup per walker:
-//   * the Green's function (eq. green) in scale-split form: A = X^T, R = U^T with
-//     partial pivoting and back substitution, so R becomes X^{-T} U^T;
-//   * the Cholesky factor of S = Y^H Y for the QR stabilisation: without pivoting
-//     and without back substitution, the left block becomes U = D L^H (S = L D L^H)
-//     and R becomes L^{-1} R;
+// Used for three solves of the slice path:
+//   * the Green's function (eq. green) in scale-split form: A = X^T, R = (Ti D_b)^T with
+//     partial pivoting and back substitution, so R becomes X^{-T} (Ti D_b)^T;
+//   * the Cholesky factor of S = Y^H Y in the QR stabilisation: no pivoting, forward
+//     only; the left block becomes U = D L^H (S = L D L^H) and R becomes L^{-1} R;
 //   * the update of T^{-1} by a unit triangular factor (again forward only).
-// Right-looking, NB = 16 columns per panel.  The panel lives in registers, one row
-// per thread (two when M > 256), so the pivot search, the row exchange and the
-// rank-1 updates of the panel need only LDS broadcasts.  Row exchanges are
-// applied to the trailing columns and the right-hand sides (the multipliers of
-// earlier panels are never read again).  The trailing update stages 16 x 64 blocks
-// of L21 and U12 in LDS and keeps a 4 x 4 complex register tile per thread.
-// ln det of the left block is the sum of the logs of the pivots plus i pi per swap.
+// Right-looking with NB = 32 columns per panel, one kernel sequence for all walkers:
+//   panel      one workgroup per walker factors the M x NB panel with partial pivoting,
+//              one row per thread (the pivot search is a workgroup reduction, the row
+//              exchange and the rank-1 updates are register operations with LDS broadcasts);
+//   swap/trsm  column-parallel: applies the panel's row exchanges to the trailing
+//              columns and right-hand sides and solves with the unit lower L11;
+//   update     the trailing update A22 -= L21 U12 as a batched complex GEMM on MFMA,
+//              over the contiguous column range [j0+NB, rhs_off+nrhs) (the zero padding
+//              between the blocks stays zero);
+// then the back substitution by blocks from the bottom (column-parallel triangular solve
+// with U_ii, GEMM update of the rows above).  ln det of the left block is the sum of the
+// logs of the pivots plus i pi per row exchange.
 #include "common.h"
 #include "kernels.h"
 #include <climits>
+#include <cstring>
 
 namespace {
 
-constexpr int NB = 16, NT = 256, UT = 64;
+constexpr int NB = 32;
 
-struct ElimShared {
-  double2 bufP[NB];
-  double2 bufC[NB];
-  double2 L11[NB][NB + 1];
-  double2 Ls[NB][UT + 1];
-  double2 Us[NB][UT + 1];
-  double redv[4];
-  int redi[4];
-  int swp[NB];
+struct PanelParams {
+  double2* aug; long long stride; int lda;
+  int M, j0, jb, W, pivot;
+  int* piv; int ld;
+  double2* lndet; int* status;
 };
 
-FT_DEV int phys_col(int lc, int c_begin, int nc1, int rhs_off) {
-  return lc < nc1 ? c_begin + lc : rhs_off + (lc - nc1);
-}
-
-// aug[r][pc] -= sum_{k<kb} aug[r][k0+k] aug[k0+k][pc] for r in [r_lo, r_hi) and the
-// logical columns [0, ncols) (first nc1 map to c_begin.., the rest to rhs_off..).
-FT_DEV void block_update(double2* aug, int lda, int r_lo, int r_hi, int k0, int kb,
-                         int c_begin, int nc1, int rhs_off, int ncols, ElimShared& sh) {
-  const int t = threadIdx.x;
-  if (r_hi <= r_lo || ncols <= 0) return;
-  const int nrt = (r_hi - r_lo + UT - 1) / UT, nct = (ncols + UT - 1) / UT;
-  const int tr = t >> 4, tc = t & 15;
-  for (int tile = 0; tile < nrt * nct; ++tile) {
-    const int rt = tile / nct, ct = tile - rt * nct;
-    const int rb = r_lo + rt * UT, cb = ct * UT;
-    for (int e = t; e < NB * UT; e += NT) {
-      const int x = e / NB, k = e - x * NB;          // Ls: row x of the tile, column k
-      const int r = rb + x;
-      sh.Ls[k][x] = (k < kb && r < r_hi) ? aug[(long long)r * lda + k0 + k] : make_double2(0.0, 0.0);
-      const int k2 = e / UT, x2 = e - k2 * UT;       // Us: row k2, tile column x2
-      const int lc = cb + x2;
-      sh.Us[k2][x2] = (k2 < kb && lc < ncols)
-                          ? aug[(long long)(k0 + k2) * lda + phys_col(lc, c_begin, nc1, rhs_off)]
-                          : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    double2 acc[4][4];
-    int pc[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int lc = cb + tc * 4 + j;
-      pc[j] = lc < ncols ? phys_col(lc, c_begin, nc1, rhs_off) : -1;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = rb + tr * 4 + i;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        acc[i][j] = (r < r_hi && pc[j] >= 0) ? aug[(long long)r * lda + pc[j]] : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      double2 l[4], u[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) l[i] = sh.Ls[k][tr * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) u[j] = sh.Us[k][tc * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = cfnms(acc[i][j], l[i], u[j]);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = rb + tr * 4 + i;
-      if (r >= r_hi) continue;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (pc[j] >= 0) aug[(long long)r * lda + pc[j]] = acc[i][j];
-    }
-    __syncthreads();
-  }
-}
-
-template <int RPT>
-__global__ __launch_bounds__(NT) void elim_kernel(ElimParams p) {
-  __shared__ ElimShared sh;
+template <int NT>
+__global__ __launch_bounds__(NT) void panel_kernel(PanelParams p) {
+  __shared__ double2 bufP[NB];
+  __shared__ double2 bufC[NB];
+  __shared__ double redv[NT / 64];
+  __shared__ int redi[NT / 64];
   const int w = blockIdx.x;
   if (w >= p.W) return;
   double2* aug = p.aug + (long long)w * p.stride;
-  const int M = p.M, lda = p.lda, t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int M = p.M, j0 = p.j0, jb = p.jb, lda = p.lda;
+  const int r = j0 + t;                    // one panel row per thread (M - j0 <= NT)
+  double2 a[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) a[c] = (r < M && c < jb) ? aug[(long long)r * lda + j0 + c] : make_double2(0.0, 0.0);
   double2 lsum = make_double2(0.0, 0.0);
   int nswaps = 0;
   bool bad = false;
-
-  for (int j0 = 0; j0 < M; j0 += NB) {
-    const int jb = min(NB, M - j0);
-    double2 a[RPT][NB];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = j0 + t + q * NT;
-#pragma unroll
-      for (int c = 0; c < NB; ++c)
-        a[q][c] = (r < M && c < jb) ? aug[(long long)r * lda + j0 + c] : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c >= jb) break;
-      const int col = j0 + c;
-      int prow = col;
-      if (p.pivot) {
-        double bv = -1.0;
-        int bi = INT_MAX;
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const int r = j0 + t + q * NT;
-          if (r >= col && r < M) {
-            const double v = cabs2(a[q][c]);
-            if (v > bv || (v == bv && r < bi)) { bv = v; bi = r; }
-          }
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-          const double ov = __shfl_xor(bv, o, 64);
-          const int oi = __shfl_xor(bi, o, 64);
-          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-        }
-        if (lane == 0) { sh.redv[wid] = bv; sh.redi[wid] = bi; }
-        __syncthreads();
-        bv = sh.redv[0]; bi = sh.redi[0];
-#pragma unroll
-        for (int k = 1; k < 4; ++k)
-          if (sh.redv[k] > bv || (sh.redv[k] == bv && sh.redi[k] < bi)) { bv = sh.redv[k]; bi = sh.redi[k]; }
-        prow = (bi >= col && bi < M) ? bi : col;   // all-NaN column: keep the diagonal
+  for (int c = 0; c < NB; ++c) {
+    if (c >= jb) break;
+    const int col = j0 + c;
+    int prow = col;
+    if (p.pivot) {
+      double bv = (r >= col && r < M) ? cabs2(a[c]) : -1.0;
+      int bi = (r >= col && r < M) ? r : INT_MAX;
+      if (!(bv == bv)) bv = -1.0;          // a NaN entry never wins the search
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
       }
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int r = j0 + t + q * NT;
-        if (r == prow) {
-#pragma unroll
-          for (int c2 = 0; c2 < NB; ++c2) sh.bufP[c2] = a[q][c2];
-        }
-        if (prow != col && r == col) {
-#pragma unroll
-          for (int c2 = 0; c2 < NB; ++c2) sh.bufC[c2] = a[q][c2];
-        }
-      }
+      if (lane == 0) { redv[wid] = bv; redi[wid] = bi; }
       __syncthreads();
-      if (prow != col) {
+      bv = redv[0]; bi = redi[0];
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const int r = j0 + t + q * NT;
-          if (r == prow) {
-#pragma unroll
-            for (int c2 = 0; c2 < NB; ++c2) a[q][c2] = sh.bufC[c2];
-          }
-          if (r == col) {
-#pragma unroll
-            for (int c2 = 0; c2 < NB; ++c2) a[q][c2] = sh.bufP[c2];
-          }
-        }
-      }
-      const double2 piv = sh.bufP[c];
-      if (t == 0) {
-        sh.swp[c] = prow;
-        if (!(cabs2(piv) > 0.0) || !isfinite(piv.x) || !isfinite(piv.y)) bad = true;
-        const double2 lg = clog(piv);
-        lsum.x += lg.x;
-        lsum.y += lg.y;
-        if (prow != col) ++nswaps;
-      }
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int r = j0 + t + q * NT;
-        if (r > col && r < M) {
-          const double2 l = cdiv(a[q][c], piv);
-          a[q][c] = l;
-#pragma unroll
-          for (int c2 = 0; c2 < NB; ++c2)
-            if (c2 > c) a[q][c2] = cfnms(a[q][c2], l, sh.bufP[c2]);
-        }
-      }
-      __syncthreads();
+      for (int k = 1; k < NT / 64; ++k)
+        if (redv[k] > bv || (redv[k] == bv && redi[k] < bi)) { bv = redv[k]; bi = redi[k]; }
+      prow = (bi >= col && bi < M) ? bi : col;
     }
-    // panel back to memory; unit-lower L11 into LDS
+    if (r == prow) {
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = j0 + t + q * NT;
-      if (r < M) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          if (c < jb) aug[(long long)r * lda + j0 + c] = a[q][c];
-      }
+      for (int c2 = 0; c2 < NB; ++c2) bufP[c2] = a[c2];
     }
-    if (t < NB) {
+    if (prow != col && r == col) {
 #pragma unroll
-      for (int c = 0; c < NB; ++c) sh.L11[t][c] = (t < jb) ? a[0][c] : make_double2(0.0, 0.0);
+      for (int c2 = 0; c2 < NB; ++c2) bufC[c2] = a[c2];
     }
     __syncthreads();
-
-    const int nc1 = M - j0 - jb, ncols = nc1 + p.nrhs, cbeg = j0 + jb;
-    // row exchanges and U12 = L11^{-1} A12 on the trailing columns and the right-hand sides
-    for (int lc = t; lc < ncols; lc += NT) {
-      const int pc = phys_col(lc, cbeg, nc1, p.rhs_off);
-      for (int c = 0; c < jb; ++c) {
-        const int pr = sh.swp[c];
-        if (pr != j0 + c) {
-          const double2 u = aug[(long long)(j0 + c) * lda + pc];
-          aug[(long long)(j0 + c) * lda + pc] = aug[(long long)pr * lda + pc];
-          aug[(long long)pr * lda + pc] = u;
-        }
+    if (prow != col) {
+      if (r == prow) {
+#pragma unroll
+        for (int c2 = 0; c2 < NB; ++c2) a[c2] = bufC[c2];
       }
-      double2 x[NB];
+      if (r == col) {
 #pragma unroll
-      for (int i = 0; i < NB; ++i) x[i] = i < jb ? aug[(long long)(j0 + i) * lda + pc] : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int i = 1; i < NB; ++i)
-#pragma unroll
-        for (int m = 0; m < NB; ++m)
-          if (m < i) x[i] = cfnms(x[i], sh.L11[i][m], x[m]);
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-        if (i < jb) aug[(long long)(j0 + i) * lda + pc] = x[i];
+        for (int c2 = 0; c2 < NB; ++c2) a[c2] = bufP[c2];
+      }
     }
-    __syncthreads();
-    block_update(aug, lda, j0 + jb, M, j0, jb, cbeg, nc1, p.rhs_off, ncols, sh);
+    const double2 pv = bufP[c];
+    if (t == 0) {
+      if (p.pivot) p.piv[(long long)w * p.ld + col] = prow;
+      if (!(cabs2(pv) > 0.0) || !isfinite(pv.x) || !isfinite(pv.y)) bad = true;
+      const double2 lg = clog(pv);
+      lsum.x += lg.x;
+      lsum.y += lg.y;
+      if (prow != col) ++nswaps;
+    }
+    if (r > col && r < M) {
+      const double2 l = cdiv(a[c], pv);
+      a[c] = l;
+#pragma unroll
+      for (int c2 = 0; c2 < NB; ++c2)
+        if (c2 > c) a[c2] = cfnms(a[c2], l, bufP[c2]);
+    }
     __syncthreads();
   }
-
-  if (p.backsub) {
-    for (int i0 = ((M - 1) / NB) * NB; i0 >= 0; i0 -= NB) {
-      const int ib = min(NB, M - i0);
-      for (int e = t; e < NB * NB; e += NT) {
-        const int i = e / NB, m = e - i * NB;
-        sh.L11[i][m] = (i < ib && m < ib) ? aug[(long long)(i0 + i) * lda + i0 + m] : make_double2(0.0, 0.0);
-      }
-      __syncthreads();
-      for (int lc = t; lc < p.nrhs; lc += NT) {
-        const int pc = p.rhs_off + lc;
-        double2 x[NB];
+  if (r < M) {
 #pragma unroll
-        for (int i = 0; i < NB; ++i) x[i] = i < ib ? aug[(long long)(i0 + i) * lda + pc] : make_double2(0.0, 0.0);
-#pragma unroll
-        for (int i = NB - 1; i >= 0; --i) {
-          if (i < ib) {
-#pragma unroll
-            for (int m = 0; m < NB; ++m)
-              if (m > i) x[i] = cfnms(x[i], sh.L11[i][m], x[m]);
-            x[i] = cdiv(x[i], sh.L11[i][i]);
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-          if (i < ib) aug[(long long)(i0 + i) * lda + pc] = x[i];
-      }
-      __syncthreads();
-      if (i0 > 0) block_update(aug, lda, 0, i0, i0, ib, 0, 0, p.rhs_off, p.nrhs, sh);
-      __syncthreads();
-    }
+    for (int c = 0; c < NB; ++c)
+      if (c < jb) aug[(long long)r * lda + j0 + c] = a[c];
   }
-
   if (t == 0) {
-    if (p.lndet) p.lndet[w] = make_double2(lsum.x, lsum.y + 3.14159265358979323846 * (double)nswaps);
+    if (p.lndet) {
+      double2 acc = j0 == 0 ? make_double2(0.0, 0.0) : p.lndet[w];
+      acc.x += lsum.x;
+      acc.y += lsum.y + 3.14159265358979323846 * (double)nswaps;
+      p.lndet[w] = acc;
+    }
     if (bad && p.status) p.status[w] = 2;
   }
 }
 
+// Row exchanges of panel j0 and U12 = L11^{-1} A12 for columns [c0, c1) (one column per thread).
+__global__ __launch_bounds__(256) void swap_trsm_kernel(PanelParams p, int c0, int c1, int chunks) {
+  __shared__ double2 L11[NB][NB + 1];
+  __shared__ int pv[NB];
+  const int w = blockIdx.x / chunks, ch = blockIdx.x - w * chunks;
+  if (w >= p.W) return;
+  double2* aug = p.aug + (long long)w * p.stride;
+  const int t = threadIdx.x, j0 = p.j0, jb = p.jb, lda = p.lda;
+  for (int e = t; e < NB * NB; e += 256) {
+    const int i = e / NB, m = e - i * NB;
+    L11[i][m] = (i < jb && m < i) ? aug[(long long)(j0 + i) * lda + j0 + m] : make_double2(0.0, 0.0);
+  }
+  if (t < NB) pv[t] = (p.pivot && t < jb) ? p.piv[(long long)w * p.ld + j0 + t] : j0 + t;
+  __syncthreads();
+  const int col = c0 + ch * 256 + t;
+  if (col >= c1) return;
+  for (int c = 0; c < jb; ++c) {
+    const int pr = pv[c];
+    if (pr != j0 + c) {
+      const double2 u = aug[(long long)(j0 + c) * lda + col];
+      aug[(long long)(j0 + c) * lda + col] = aug[(long long)pr * lda + col];
+      aug[(long long)pr * lda + col] = u;
+    }
+  }
+  double2 x[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) x[i] = i < jb ? aug[(long long)(j0 + i) * lda + col] : make_double2(0.0, 0.0);
+#pragma unroll
+  for (int i = 1; i < NB; ++i)
+#pragma unroll
+    for (int m = 0; m < NB; ++m)
+      if (m < i) x[i] = cfnms(x[i], L11[i][m], x[m]);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+    if (i < jb) aug[(long long)(j0 + i) * lda + col] = x[i];
+}
+
+// Back substitution with the upper block U_ii (rows/cols i0..i0+ib) for columns [c0, c1).
+__global__ __launch_bounds__(256) void trsm_upper_kernel(PanelParams p, int i0, int ib, int c0, int c1, int chunks) {
+  __shared__ double2 U[NB][NB + 1];
+  const int w = blockIdx.x / chunks, ch = blockIdx.x - w * chunks;
+  if (w >= p.W) return;
+  double2* aug = p.aug + (long long)w * p.stride;
+  const int t = threadIdx.x, lda = p.lda;
+  for (int e = t; e < NB * NB; e += 256) {
+    const int i = e / NB, m = e - i * NB;
+    U[i][m] = (i < ib && m < ib && m >= i) ? aug[(long long)(i0 + i) * lda + i0 + m] : make_double2(i == m ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  const int col = c0 + ch * 256 + t;
+  if (col >= c1) return;
+  double2 x[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) x[i] = i < ib ? aug[(long long)(i0 + i) * lda + col] : make_double2(0.0, 0.0);
+#pragma unroll
+  for (int i = NB - 1; i >= 0; --i) {
+#pragma unroll
+    for (int m = 0; m < NB; ++m)
+      if (m > i) x[i] = cfnms(x[i], U[i][m], x[m]);
+    x[i] = cdiv(x[i], U[i][i]);
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+    if (i < ib) aug[(long long)(i0 + i) * lda + col] = x[i];
+}
+
+GemmParams update_params(const ElimParams& e, int row0, int nrows, int k0, int kb, int col0, int ncols) {
+  // aug[row0.., col0..] -= aug[row0.., k0..k0+kb] aug[k0..k0+kb, col0..]
+  GemmParams g;
+  memset(&g, 0, sizeof(g));
+  g.A = e.aug + (long long)row0 * e.lda + k0;
+  g.B = e.aug + (long long)k0 * e.lda + col0;
+  g.C = e.aug + (long long)row0 * e.lda + col0;
+  g.sA = g.sB = g.sC = g.sP = e.stride;
+  g.lda = g.ldb = g.ldc = g.ldp = e.lda;
+  g.m = nrows; g.n = ncols; g.k = kb; g.mpad = nrows; g.npad = ncols; g.W = e.W;
+  g.alpha = -1.0;
+  g.beta = 1.0;
+  return g;
+}
+
 }  // namespace
 
-hipError_t launch_elim(const ElimParams& p, hipStream_t s) {
-  if (p.W <= 0 || p.M <= 0) return hipSuccess;
-  if (p.M <= NT) elim_kernel<1><<<p.W, NT, 0, s>>>(p);
-  else if (p.M <= 2 * NT) elim_kernel<2><<<p.W, NT, 0, s>>>(p);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
+hipError_t launch_elim(const ElimParams& e, hipStream_t s) {
+  if (e.W <= 0 || e.M <= 0) return hipSuccess;
+  if (e.M > 512) return hipErrorInvalidValue;
+  const int M = e.M;
+  const int cend = e.rhs_off + e.nrhs;   // trailing columns run up to the end of the right-hand sides
+  PanelParams p;
+  p.aug = e.aug; p.stride = e.stride; p.lda = e.lda; p.M = M; p.W = e.W; p.pivot = e.pivot;
+  p.piv = e.piv; p.ld = e.ld; p.lndet = e.lndet; p.status = e.status;
+  for (int j0 = 0; j0 < M; j0 += NB) {
+    const int jb = M - j0 < NB ? M - j0 : NB;
+    p.j0 = j0; p.jb = jb;
+    if (M - j0 <= 64) panel_kernel<64><<<e.W, 64, 0, s>>>(p);
+    else if (M - j0 <= 256) panel_kernel<256><<<e.W, 256, 0, s>>>(p);
+    else panel_kernel<512><<<e.W, 512, 0, s>>>(p);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const int c0 = j0 + jb;
+    const int ncols = cend - c0;
+    if (ncols <= 0) continue;
+    const int chunks = (ncols + 255) / 256;
+    swap_trsm_kernel<<<e.W * chunks, 256, 0, s>>>(p, c0, cend, chunks);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    if (M - c0 > 0) {
+      err = launch_zgemm(update_params(e, c0, M - c0, j0, jb, c0, ncols), GEMM_Z64, s);
+      if (err != hipSuccess) return err;
+    }
+  }
+  if (e.backsub) {
+    const int chunks = (e.nrhs + 255) / 256;
+    for (int i0 = ((M - 1) / NB) * NB; i0 >= 0; i0 -= NB) {
+      const int ib = M - i0 < NB ? M - i0 : NB;
+      trsm_upper_kernel<<<e.W * chunks, 256, 0, s>>>(p, i0, ib, e.rhs_off, cend, chunks);
+      hipError_t err = hipGetLastError();
+      if (err != hipSuccess) return err;
+      if (i0 > 0) {
+        err = launch_zgemm(update_params(e, 0, i0, i0, ib, e.rhs_off, e.nrhs), GEMM_Z64, s);
+        if (err != hipSuccess) return err;
+      }
+    }
+  }
+  return hipSuccess;
 }

@@ -47,12 +47,12 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
   __shared__ cacc Bs[2][BK][BN + PAD];
 
   int w, tile;
-  if (!xcd_walker_tile(blockIdx.x, p.W, p.tiles * p.tiles, &w, &tile)) return;
-  const int tm = tile / p.tiles, tn = tile - tm * p.tiles;
+  if (!xcd_walker_tile(blockIdx.x, p.W, p.tiles_m * p.tiles_n, &w, &tile)) return;
+  const int tm = tile / p.tiles_n, tn = tile - tm * p.tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int wr = wid >> 1, wc = wid & 1;
-  const int M = p.M;
+  const int Mr = p.m, Nc = p.n, Kd = p.k;
 
   const TA* A = (const TA*)p.A + (long long)w * p.sA;
   const TB* B = (const TB*)p.B + (long long)w * p.sB;
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
       if (p.opA == 0) { gm = m0 + (t >> 2); gk = k0 + ((t & 3) << 2) + e; }
       else            { gk = k0 + (t >> 4); gm = m0 + ((t & 15) << 2) + e; }
       double2 v = make_double2(0.0, 0.0);
-      if (gm < M && gk < M) {
+      if (gm < Mr && gk < Kd) {
         v = p.opA == 0 ? ld_c(A + (long long)gm * p.lda + gk) : cconj(ld_c(A + (long long)gk * p.lda + gm));
       }
       ra[e] = cvt<ACC>(v);
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
       if (p.opB == 0) { gk = k0 + (t >> 4); gn = n0 + ((t & 15) << 2) + e; }
       else            { gn = n0 + (t >> 2); gk = k0 + ((t & 3) << 2) + e; }
       double2 v = make_double2(0.0, 0.0);
-      if (gn < M && gk < M) {
+      if (gn < Nc && gk < Kd) {
         v = p.opB == 0 ? ld_c(B + (long long)gk * p.ldb + gn) : cconj(ld_c(B + (long long)gn * p.ldb + gk));
       }
       rb[e] = cvt<ACC>(v);
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
     }
   };
 
-  const int nk = (M + BK - 1) / BK;
+  const int nk = (Kd + BK - 1) / BK;
   load_tile(0);
   store_tile(0);
   __syncthreads();
@@ -147,12 +147,13 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
       for (int v = 0; v < 4; ++v) {
         const int gi = m0 + wr * 32 + i * 16 + Mfma<ACC>::row(lane, v);
         const int gj = n0 + wc * 32 + j * 16 + li;
-        if (gi >= p.Mpad || gj >= p.Mpad) continue;
+        if (gi >= p.mpad || gj >= p.npad) continue;
         double2 out = make_double2(0.0, 0.0), out2 = make_double2(0.0, 0.0);
-        if (gi < M && gj < M) {
+        if (gi < Mr && gj < Nc) {
           const double2 acc = make_double2((double)accR[i][j][v], (double)accI[i][j][v]);
           out = cscale(acc, p.alpha);
           out2 = cscale(acc, p.beta2);
+          if (p.beta != 0.0) out = cadd(out, cscale(ld_c(C + (long long)gi * p.ldc + gj), p.beta));
           if (gi == gj) { out.x += p.cI; out2.x += p.dI; }
           const long long off = (long long)gi * p.ldp + gj;
           if (P1) { double2 q = ld_c(P1 + off); out = cadd(out, cscale(q, p.c1)); out2 = cadd(out2, cscale(q, p.d1)); }
@@ -168,12 +169,12 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
 
 }  // namespace
 
-int gemm_tiles(int Mpad) { return (Mpad + BM - 1) / BM; }
-
 hipError_t launch_zgemm(const GemmParams& p0, int prec, hipStream_t s) {
   GemmParams p = p0;
-  p.tiles = gemm_tiles(p.Mpad);
-  const int blocks = ((p.W + 7) / 8) * 8 * p.tiles * p.tiles;
+  if (p.m <= 0 || p.n <= 0 || p.mpad < p.m || p.npad < p.n) return p.m <= 0 || p.n <= 0 ? hipSuccess : hipErrorInvalidValue;
+  p.tiles_m = (p.mpad + BM - 1) / BM;
+  p.tiles_n = (p.npad + BN - 1) / BN;
+  const int blocks = ((p.W + 7) / 8) * 8 * p.tiles_m * p.tiles_n;
   if (blocks == 0) return hipSuccess;
   switch (prec) {
     case GEMM_Z64:   // complex128 in and out, FP64 MFMA

@@ -194,6 +194,7 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.D = (double*)take(sizeof(double) * ld * W);
   d.Dpi = (double*)take(sizeof(double) * ld * W);
   d.perm = (int*)take(sizeof(int) * ld * W);
+  d.piv = (int*)take(sizeof(int) * ld * W);
   d.r = (double2*)take(sizeof(double2) * (size_t)NQ * W);
   d.expo = (double2*)take(sizeof(double2) * W);
   d.ell = (double2*)take(sizeof(double2) * W);
@@ -266,7 +267,7 @@ GemmParams gp_base(const HostSys& s) {
   std::memset(&g, 0, sizeof(g));
   g.sA = g.sB = g.sC = g.sP = s.dev.mat_stride;
   g.lda = g.ldb = g.ldc = g.ldp = s.ld;
-  g.M = s.M; g.Mpad = s.ld; g.W = s.p.n_walkers;
+  g.m = g.n = g.k = s.M; g.mpad = g.npad = s.ld; g.W = s.p.n_walkers;
   g.alpha = 1.0;
   return g;
 }
@@ -320,6 +321,7 @@ int stabilise(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   ElimParams e;
   e.aug = d.aug; e.stride = d.aug_stride; e.lda = 2 * s.ld; e.M = s.M; e.rhs_off = s.ld; e.nrhs = s.M;
   e.W = d.W; e.pivot = 0; e.backsub = 0; e.lndet = nullptr; e.status = d.status;
+  e.piv = d.piv; e.ld = s.ld;
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_elim(e, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_finish_a(d, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_build_ti(d, st); }));
@@ -335,6 +337,7 @@ int greens(ftafqmc_ctx* h, HostSys& s, int k, int init, hipStream_t st) {
   ElimParams e;
   e.aug = d.aug; e.stride = d.aug_stride; e.lda = 2 * s.ld; e.M = s.M; e.rhs_off = s.ld; e.nrhs = s.M;
   e.W = d.W; e.pivot = 1; e.backsub = 1; e.lndet = d.lndetX; e.status = d.status;
+  e.piv = d.piv; e.ld = s.ld;
   HIPCHK(timed(h, FTAFQMC_PROF_ELIM, st, [&] { return launch_elim(e, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_GREENS, st, [&] { return launch_greens_post(d, k, st); }));
   const double slb = sum_ln_lb(s, k);

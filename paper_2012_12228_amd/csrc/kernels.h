@@ -4,20 +4,22 @@
 
 enum { GEMM_Z64 = 0, GEMM_C32 = 1, GEMM_C32_Z64B = 2 };
 
+// C = alpha op(A) op(B) + beta C + cI I + c1 P1 + c2 P2 + c3 P3, then diag(rs) C diag(cs);
+// C2 = beta2 op(A) op(B) + dI I + d1 P1 + d2 P2 + d3 P3.  C is m x n, the inner size k.
+// Entries (i, j) with m <= i < mpad or n <= j < npad are written as zero.
 struct GemmParams {
   const void* A; const void* B; void* C; void* C2;
   const void* P1; const void* P2; const void* P3;
   const double* rs; const double* cs;
   long long sA, sB, sC, sP;  // walker strides in elements
   int lda, ldb, ldc, ldp;
-  int M, Mpad, W;
+  int m, n, k, mpad, npad, W;
   int opA, opB;              // 0 = as stored, 1 = conjugate transpose
-  double alpha, cI, c1, c2, c3;
+  double alpha, beta, cI, c1, c2, c3;
   double beta2, dI, d1, d2, d3;
-  int tiles;                 // set by the launcher
+  int tiles_m, tiles_n;      // set by the launcher
 };
 hipError_t launch_zgemm(const GemmParams& p, int prec, hipStream_t s);
-int gemm_tiles(int Mpad);
 
 // Blocked Gaussian elimination on a per-walker augmented matrix [A | R] (M x M
 // left block, nrhs right-hand sides starting at column rhs_off, row stride lda).
@@ -28,6 +30,8 @@ struct ElimParams {
   int backsub;  // solve the upper triangle after the forward elimination
   double2* lndet;  // [W] sum of log pivots + i pi (row swaps); may be null
   int* status;     // [W] set to 2 on a zero or non-finite pivot; may be null
+  int* piv;        // [W][ld] pivot rows (workspace)
+  int ld;          // stride of piv
 };
 hipError_t launch_elim(const ElimParams& p, hipStream_t s);
 
@@ -52,7 +56,7 @@ struct SysDev {
   double2* Y; double2* Ti; double2* G; double2* aug;
   void* V; void* V2; void* V3; void* V4; void* E0; void* E1;  // complex128 or complex64
   double2* Ynew;
-  double* D; double* Dpi; int* perm;
+  double* D; double* Dpi; int* perm; int* piv;
   double2* r;             // [W][NQ] <rho_Q> per spin of the current G
   double2* expo;          // [W] weight exponent of the current slice
   double2* ell;           // [W] ln det(I + A_k)

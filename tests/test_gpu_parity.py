@@ -4,7 +4,13 @@ Tolerances (written here, derived in the design notes):
   FP64 path   -- relative 1e-10 for G (max-norm), E_1, E_2, E, N; ln w to 1e-10 * max(1, |ln w|);
                  status words identical.
   mixed path  -- complex64 propagator GEMMs with FP32 accumulation, FP64 everything else:
-                 E_1 + E_2 relative 1e-6, N relative 1e-6, G relative 1e-5, ln w relative 1e-5.
+                 E_1 and E_2 relative 1e-6 each, E_1 + E_2 to 1e-6 (|E_1| + |E_2|) (the
+                 condition scale of a sum: at large r_s the two nearly cancel),
+                 N relative 1e-6, G relative 1e-5; ln w absolute
+                 2e-7 M (1 + k/10) after k slices: ln w = 2 Re(l_k - l_0) + sum of per-slice
+                 terms, where the error of l_k = ln det(I + A_k) is about M eps_fp32 (one
+                 rounding-limited contribution per eigenvalue) and the per-slice terms add a
+                 slowly growing part.
 """
 import os
 
@@ -20,7 +26,11 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 FP64_REL = 1e-10
-MIX_E12, MIX_N, MIX_G, MIX_LOGW = 1e-6, 1e-6, 1e-5, 1e-5
+MIX_E12, MIX_N, MIX_G = 1e-6, 1e-6, 1e-5
+
+
+def mix_logw_tol(M, k):
+    return 2e-7 * M * (1.0 + k / 10.0)
 
 
 def _F():
@@ -52,6 +62,13 @@ def rel_mat(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
+def check_mixed_energy(e1, e2, nn, r1, r2, rn, label):
+    assert relc(e1, r1) < MIX_E12, label
+    assert relc(e2, r2) < MIX_E12, label
+    assert abs((e1 + e2) - (r1 + r2)) < MIX_E12 * (abs(r1) + abs(r2)), label
+    assert relc(nn, rn) < MIX_N, label
+
+
 def check_walker(rec_gpu, logw_gpu, G_gpu, ref, mixed=False, label=""):
     """rec_gpu [n_rec][4] complex, logw_gpu [n_rec]; ref: oracle output dict."""
     recs = ref["records"]
@@ -59,13 +76,12 @@ def check_walker(rec_gpu, logw_gpu, G_gpu, ref, mixed=False, label=""):
     for j, r in enumerate(recs):
         e1, e2, e, nn = rec_gpu[j]
         if mixed:
-            assert relc(e1 + e2, r["E1"] + r["E2"]) < MIX_E12, (label, j)
-            assert relc(nn, r["N"]) < MIX_N, (label, j)
+            check_mixed_energy(e1, e2, nn, r["E1"], r["E2"], r["N"], (label, j))
         else:
             for got, want in ((e1, r["E1"]), (e2, r["E2"]), (e, r["E"]), (nn, r["N"])):
                 assert relc(got, want) < FP64_REL, (label, j, got, want)
         if np.isfinite(r["logw"]):
-            tol = (MIX_LOGW if mixed else FP64_REL) * max(1.0, abs(r["logw"]))
+            tol = mix_logw_tol(G_gpu.shape[0], r["slice"]) if mixed else FP64_REL * max(1.0, abs(r["logw"]))
             assert abs(logw_gpu[j] - r["logw"]) < tol, (label, j, logw_gpu[j], r["logw"])
         else:
             assert logw_gpu[j] == -np.inf, (label, j)
@@ -219,12 +235,11 @@ def _check_golden(gold, key, trace, logw, G, slices, mixed=False):
     lw = gold[key + "_logw"]
     for j in range(len(slices)):
         if mixed:
-            assert relc(trace[j, 0] + trace[j, 1], E[j, 0] + E[j, 1]) < MIX_E12, (key, j)
-            assert relc(trace[j, 3], E[j, 3]) < MIX_N, (key, j)
+            check_mixed_energy(trace[j, 0], trace[j, 1], trace[j, 3], E[j, 0], E[j, 1], E[j, 3], (key, j))
         else:
             for c in range(4):
                 assert relc(trace[j, c], E[j, c]) < FP64_REL, (key, j, c, trace[j, c], E[j, c])
-        tol = (MIX_LOGW if mixed else FP64_REL) * max(1.0, abs(lw[j]))
+        tol = mix_logw_tol(G.shape[0], slices[j]) if mixed else FP64_REL * max(1.0, abs(lw[j]))
         assert abs(logw[j] - lw[j]) < tol, (key, j, logw[j], lw[j])
     tol = MIX_G if mixed else FP64_REL
     assert rel_mat(np.diagonal(G), gold[key + "_G_diag"]) < tol
@@ -267,3 +282,11 @@ def test_m123_full_size_fp64():
 
 def test_uneven_four_systems_one_handle():
     _full_size("ueg_uneven4", 1)
+
+
+def test_m485_full_size_fp64():
+    _full_size("ueg_n114_m485", 0)
+
+
+def test_m485_full_size_mixed():
+    _full_size("ueg_n114_m485", 1)
