@@ -195,6 +195,7 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.Dpi = (double*)take(sizeof(double) * ld * W);
   d.perm = (int*)take(sizeof(int) * ld * W);
   d.piv = (int*)take(sizeof(int) * ld * W);
+  d.tri = (double2*)take(sizeof(double2) * elim_tri_elems(M) * W);
   d.r = (double2*)take(sizeof(double2) * (size_t)NQ * W);
   d.expo = (double2*)take(sizeof(double2) * W);
   d.ell = (double2*)take(sizeof(double2) * W);
@@ -321,7 +322,7 @@ int stabilise(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   ElimParams e;
   e.aug = d.aug; e.stride = d.aug_stride; e.lda = 2 * s.ld; e.M = s.M; e.rhs_off = s.ld; e.nrhs = s.M;
   e.W = d.W; e.pivot = 0; e.backsub = 0; e.lndet = nullptr; e.status = d.status;
-  e.piv = d.piv; e.ld = s.ld;
+  e.piv = d.piv; e.ld = s.ld; e.tri = d.tri;
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_elim(e, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_finish_a(d, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_build_ti(d, st); }));
@@ -337,7 +338,7 @@ int greens(ftafqmc_ctx* h, HostSys& s, int k, int init, hipStream_t st) {
   ElimParams e;
   e.aug = d.aug; e.stride = d.aug_stride; e.lda = 2 * s.ld; e.M = s.M; e.rhs_off = s.ld; e.nrhs = s.M;
   e.W = d.W; e.pivot = 1; e.backsub = 1; e.lndet = d.lndetX; e.status = d.status;
-  e.piv = d.piv; e.ld = s.ld;
+  e.piv = d.piv; e.ld = s.ld; e.tri = d.tri;
   HIPCHK(timed(h, FTAFQMC_PROF_ELIM, st, [&] { return launch_elim(e, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_GREENS, st, [&] { return launch_greens_post(d, k, st); }));
   const double slb = sum_ln_lb(s, k);

@@ -32,8 +32,10 @@ struct ElimParams {
   int* status;     // [W] set to 2 on a zero or non-finite pivot; may be null
   int* piv;        // [W][ld] pivot rows (workspace)
   int ld;          // stride of piv
+  double2* tri;    // [W][elim_tri_elems(M)] triangular-block inverses (workspace)
 };
 hipError_t launch_elim(const ElimParams& p, hipStream_t s);
+size_t elim_tri_elems(int M);
 
 // Per-system constant tables and per-walker state, as device pointers.
 struct SysDev {
@@ -57,6 +59,7 @@ struct SysDev {
   void* V; void* V2; void* V3; void* V4; void* E0; void* E1;  // complex128 or complex64
   double2* Ynew;
   double* D; double* Dpi; int* perm; int* piv;
+  double2* tri;           // [W][elim_tri_elems(M)]
   double2* r;             // [W][NQ] <rho_Q> per spin of the current G
   double2* expo;          // [W] weight exponent of the current slice
   double2* ell;           // [W] ln det(I + A_k)
