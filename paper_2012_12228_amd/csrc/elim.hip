@@ -36,81 +36,100 @@ struct PanelParams {
   double2* tri;   // [W][NB][NB] inverse of the unit lower L11 of this panel
 };
 
-struct PanelCtx {
-  int t, lane, wid, r, M, j0, jb, pivot, nswaps;
-  bool bad;
-  double2 lsum;
-  int* piv;          // this walker's pivot rows
-};
-
 template <int NT>
 struct PanelShared {
-  double2 bufP[NB];
-  double2 bufC[NB];
-  double redv[NT / 64];
-  int redi[NT / 64];
-  double2 Ls[NB][NB + 1];
-  double2 Li[NB][NB + 1];
+  double2 candRow[2][NT / 64][NB];  // each wave's best row, double-buffered by column parity
+  double candVal[2][NT / 64];
+  int candIdx[2][NT / 64];
+  double2 curRow[2][NB];            // logical row `col` (used without pivoting)
+  double2 pivv[NB];                 // pivots of this panel
+  int swapped[NB];
+  double2 Ls[NB][NB + 1];           // unit lower L11
 };
 
-// Elimination step of panel column C (a compile-time index, so the row stays in registers).
+// DPP move of a double within 16-lane rows (CTRL is a row-local pattern, every source exists).
+template <int CTRL> FT_DEV double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// Maximum over the 64 lanes of a wave, returned to every lane.
+FT_DEV double wave_max(double v) {
+  v = fmax(v, dpp_d<0xB1>(v));    // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_d<0x4E>(v));    // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_d<0x124>(v));   // row_ror:4
+  v = fmax(v, dpp_d<0x128>(v));   // row_ror:8
+  v = fmax(v, __shfl_xor(v, 16, 64));
+  v = fmax(v, __shfl_xor(v, 32, 64));
+  return v;
+}
+
+struct PanelCtx {
+  int t, lane, wid, myrow, M, j0, jb, pivot;
+  int* piv;
+};
+
+// Column C of the panel (compile-time, so every register index is static).  Row exchanges
+// only relabel threads: the thread holding logical row prow becomes logical row col and vice
+// versa; rows go to their final positions when the panel is written back.  One barrier per
+// column: each wave publishes its best candidate (value, logical row, entries C..NB-1), and
+// the owner of row col publishes that row for the unpivoted case.
 template <int NT, int C>
 FT_DEV void panel_column(double2 (&a)[NB], PanelCtx& x, PanelShared<NT>& sh) {
   if (C >= x.jb) return;                 // uniform over the workgroup
-  const int col = x.j0 + C, r = x.r, M = x.M;
-  int prow = col;
+  const int col = x.j0 + C, buf = C & 1, M = x.M;
+  const bool cand = x.myrow >= col && x.myrow < M;
   if (x.pivot) {
-    double bv = (r >= col && r < M) ? cabs2(a[C]) : -1.0;
-    int bi = (r >= col && r < M) ? r : INT_MAX;
+    double bv = cand ? cabs2(a[C]) : -1.0;
     if (!(bv == bv)) bv = -1.0;          // a NaN entry never wins the search
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    const double mv = wave_max(bv);
+    // lowest lane among the maxima; ties go to the smaller logical row
+    int best = cand && bv == mv ? x.myrow : INT_MAX;
+    for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
+    if (cand && bv == mv && x.myrow == best) {
+#pragma unroll
+      for (int i = C; i < NB; ++i) sh.candRow[buf][x.wid][i] = a[i];
     }
-    if (x.lane == 0) { sh.redv[x.wid] = bv; sh.redi[x.wid] = bi; }
-    __syncthreads();
-    bv = sh.redv[0]; bi = sh.redi[0];
+    if (x.lane == 0) { sh.candVal[buf][x.wid] = mv; sh.candIdx[buf][x.wid] = best; }
+  } else if (x.myrow == col) {
 #pragma unroll
-    for (int k = 1; k < NT / 64; ++k)
-      if (sh.redv[k] > bv || (sh.redv[k] == bv && sh.redi[k] < bi)) { bv = sh.redv[k]; bi = sh.redi[k]; }
-    prow = (bi >= col && bi < M) ? bi : col;
-  }
-  if (r == prow) {
-#pragma unroll
-    for (int c2 = 0; c2 < NB; ++c2) sh.bufP[c2] = a[c2];
-  }
-  if (prow != col && r == col) {
-#pragma unroll
-    for (int c2 = 0; c2 < NB; ++c2) sh.bufC[c2] = a[c2];
+    for (int i = C; i < NB; ++i) sh.curRow[buf][i] = a[i];
   }
   __syncthreads();
-  if (prow != col) {
-    if (r == prow) {
+  int prow = col;
+  const double2* pr = sh.curRow[buf];
+  if (x.pivot) {
+    double bv = sh.candVal[buf][0];
+    int bi = sh.candIdx[buf][0], win = 0;
 #pragma unroll
-      for (int c2 = 0; c2 < NB; ++c2) a[c2] = sh.bufC[c2];
+    for (int k = 1; k < NT / 64; ++k) {
+      const double v = sh.candVal[buf][k];
+      const int ix = sh.candIdx[buf][k];
+      if (v > bv || (v == bv && ix < bi)) { bv = v; bi = ix; win = k; }
     }
-    if (r == col) {
-#pragma unroll
-      for (int c2 = 0; c2 < NB; ++c2) a[c2] = sh.bufP[c2];
+    prow = (bi >= col && bi < M) ? bi : col;
+    pr = sh.candRow[buf][win];
+    if (prow == col && !(bi >= col && bi < M)) {
+      // no usable candidate (all NaN): the diagonal row stays; its entries are its own
+      pr = nullptr;
     }
+    if (x.myrow == prow) x.myrow = col;
+    else if (x.myrow == col) x.myrow = prow;
   }
-  const double2 pv = sh.bufP[C];
+  double2 pv;
+  if (pr) pv = pr[C];
+  else pv = make_double2(NAN, NAN);
   if (x.t == 0) {
     if (x.pivot) x.piv[col] = prow;
-    if (!(cabs2(pv) > 0.0) || !isfinite(pv.x) || !isfinite(pv.y)) x.bad = true;
-    const double2 lg = clog(pv);
-    x.lsum.x += lg.x;
-    x.lsum.y += lg.y;
-    if (prow != col) ++x.nswaps;
+    sh.pivv[C] = pv;
+    sh.swapped[C] = prow != col;
   }
-  if (r > col && r < M) {
+  if (x.myrow > col && x.myrow < M && pr) {
     const double2 l = cdiv(a[C], pv);
     a[C] = l;
 #pragma unroll
-    for (int c2 = C + 1; c2 < NB; ++c2) a[c2] = cfnms(a[c2], l, sh.bufP[c2]);
+    for (int i = C + 1; i < NB; ++i) a[i] = cfnms(a[i], l, pr[i]);
   }
-  __syncthreads();
 }
 
 template <int NT, int C> struct PanelColumns {
@@ -123,6 +142,8 @@ template <int NT> struct PanelColumns<NT, NB> {
   static FT_DEV void run(double2 (&)[NB], PanelCtx&, PanelShared<NT>&) {}
 };
 
+// One workgroup per walker factors rows [j0, M) x columns [j0, j0+jb) with partial pivoting,
+// one row per thread, then inverts the unit lower L11 (one column of the inverse per thread).
 template <int NT>
 __global__ __launch_bounds__(NT) void panel_kernel(PanelParams p) {
   __shared__ PanelShared<NT> sh;
@@ -131,50 +152,62 @@ __global__ __launch_bounds__(NT) void panel_kernel(PanelParams p) {
   double2* aug = p.aug + (long long)w * p.stride;
   const int t = threadIdx.x;
   const int M = p.M, j0 = p.j0, jb = p.jb, lda = p.lda;
-  const int r = j0 + t;                    // one panel row per thread (M - j0 <= NT)
+  const int r = j0 + t;                    // the row this thread loads (M - j0 <= NT)
   double2 a[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) a[c] = (r < M && c < jb) ? aug[(long long)r * lda + j0 + c] : make_double2(0.0, 0.0);
   PanelCtx x;
-  x.t = t; x.lane = t & 63; x.wid = t >> 6; x.r = r; x.M = M; x.j0 = j0; x.jb = jb; x.pivot = p.pivot;
-  x.nswaps = 0; x.bad = false; x.lsum = make_double2(0.0, 0.0);
+  x.t = t; x.lane = t & 63; x.wid = t >> 6; x.myrow = r; x.M = M; x.j0 = j0; x.jb = jb; x.pivot = p.pivot;
   x.piv = p.piv + (long long)w * p.ld;
   PanelColumns<NT, 0>::run(a, x, sh);
-  double2 lsum = x.lsum;
-  const int nswaps = x.nswaps;
-  const bool bad = x.bad;
-  if (r < M) {
+  const int myrow = x.myrow;
+  if (myrow < M) {
 #pragma unroll
     for (int c = 0; c < NB; ++c)
-      if (c < jb) aug[(long long)r * lda + j0 + c] = a[c];
+      if (c < jb) aug[(long long)myrow * lda + j0 + c] = a[c];
   }
-  // inverse of the unit lower L11 (rows j0..j0+jb are threads 0..jb-1)
-  if (t < NB) {
+  // logical rows j0..j0+jb hold L11 in their strictly lower part
+  if (myrow >= j0 && myrow < j0 + NB) {
+    const int i = myrow - j0;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) sh.Ls[t][c] = (c < t && t < jb) ? a[c] : make_double2(0.0, 0.0);
-  }
-  for (int e = t; e < NB * NB; e += NT) {
-    const int i = e / NB, c = e - i * NB;
-    sh.Li[i][c] = make_double2(i == c ? 1.0 : 0.0, 0.0);
+    for (int c = 0; c < NB; ++c) sh.Ls[i][c] = (c < i && i < jb) ? a[c] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  for (int k = 0; k < jb - 1; ++k) {      // row i of L^{-1} -= L[i][k] * row k, for i > k
-    for (int e = t; e < NB * NB; e += NT) {
-      const int i = e / NB, c = e - i * NB;
-      if (i > k && c <= k) sh.Li[i][c] = cfnms(sh.Li[i][c], sh.Ls[i][k], sh.Li[k][c]);
-    }
-    __syncthreads();
+  // ln det contribution and pivot checks (wave 0 holds all jb <= 32 pivots)
+  double lx = 0.0, ly = 0.0, nsw = 0.0, badv = 0.0;
+  if (t < jb) {
+    const double2 pv = sh.pivv[t];
+    const double2 lg = clog(pv);
+    lx = lg.x;
+    ly = lg.y;
+    nsw = sh.swapped[t] ? 1.0 : 0.0;
+    if (!(cabs2(pv) > 0.0) || !isfinite(pv.x) || !isfinite(pv.y)) badv = 1.0;
   }
-  double2* tri = p.tri + (long long)w * NB * NB;
-  for (int e = t; e < NB * NB; e += NT) tri[e] = sh.Li[e / NB][e % NB];
+  if (x.wid == 0) {
+    lx = wave_sum(lx); ly = wave_sum(ly); nsw = wave_sum(nsw); badv = wave_sum(badv);
+  }
+  // column t of L11^{-1} by forward substitution on e_t
+  if (t < NB) {
+    double2 xcol[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      double2 v = make_double2(i == t ? 1.0 : 0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < i; ++k) v = cfnms(v, sh.Ls[i][k], xcol[k]);
+      xcol[i] = v;
+    }
+    double2* tri = p.tri + (long long)w * NB * NB;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) tri[i * NB + t] = xcol[i];
+  }
   if (t == 0) {
     if (p.lndet) {
       double2 acc = j0 == 0 ? make_double2(0.0, 0.0) : p.lndet[w];
-      acc.x += lsum.x;
-      acc.y += lsum.y + 3.14159265358979323846 * (double)nswaps;
+      acc.x += lx;
+      acc.y += ly + 3.14159265358979323846 * nsw;
       p.lndet[w] = acc;
     }
-    if (bad && p.status) p.status[w] = 2;
+    if (badv > 0.0 && p.status) p.status[w] = 2;
   }
 }
 
@@ -233,6 +266,7 @@ GemmParams aug_params(const ElimParams& e) {
   g.sA = g.sB = g.sC = g.sP = e.stride;
   g.lda = g.ldb = g.ldc = g.ldp = e.lda;
   g.W = e.W;
+  g.role = 1;
   return g;
 }
 
@@ -280,6 +314,7 @@ hipError_t launch_elim(const ElimParams& e, hipStream_t s) {
     p.j0 = j0; p.jb = jb;
     p.tri = linv;                         // L11^{-1} of walker w at linv + w * NB * NB
     if (M - j0 <= 64) panel_kernel<64><<<e.W, 64, 0, s>>>(p);
+    else if (M - j0 <= 128) panel_kernel<128><<<e.W, 128, 0, s>>>(p);
     else if (M - j0 <= 256) panel_kernel<256><<<e.W, 256, 0, s>>>(p);
     else panel_kernel<512><<<e.W, 512, 0, s>>>(p);
     if ((err = hipGetLastError()) != hipSuccess) return err;

@@ -1,10 +1,11 @@
 // Batched complex GEMM on the CDNA4 matrix cores for the slice propagator.
 //
-// C_w = alpha * op(A_w) op(B_w) + cI I + c1 P1_w + c2 P2_w + c3 P3_w, scaled as
-// diag(rs) C diag(cs), with an optional second output C2_w from the same product.
-// The epilogue forms the Paterson-Stockmeyer blocks of the Taylor series of e^V
-// and the half-step kinetic factors of the symmetric Trotter propagator (eq. B)
-// without extra passes over memory.
+// C_w = diag(rs) [alpha op(A_w) op(B_w) + beta C_w + cI I + c1 P1_w + c2 P2_w + c3 P3_w] diag(cs),
+// with up to four extra outputs formed from the same product and the same P_w.  The
+// epilogue builds the Paterson-Stockmeyer blocks of the Taylor series of e^V and applies
+// the half-step kinetic factors of the symmetric Trotter propagator (eq. B) without
+// extra passes over memory.  A single epilogue operand is prefetched during the last
+// k-tile; 16 x 16 blocks outside the m x n result issue no MFMAs.
 //
 // Tiling: 64 x 64 output tile per 256-thread workgroup (2 x 2 waves, each wave
 // 2 x 2 blocks of 16 x 16), K staged through LDS 16 at a time, double-buffered.
@@ -39,7 +40,7 @@ template <> struct Mfma<float> {
 
 template <typename T> FT_DEV double2 ld_c(const T* p) { return to_d2(*p); }
 
-template <typename TA, typename TB, typename TC, typename ACC>
+template <typename TA, typename TB, typename TC, typename ACC, int ROLE>
 __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
   typedef typename cplx_of<ACC>::type cacc;
   typedef typename Mfma<ACC>::acc_t acc_t;
@@ -103,13 +104,43 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
   };
 
   const int nk = (Kd + BK - 1) / BK;
+  TC* C = (TC*)p.C + (long long)w * p.sC;
+  const TC* P1 = p.P1 ? (const TC*)p.P1 + (long long)w * p.sP : nullptr;
+  const TC* P2 = p.P2 ? (const TC*)p.P2 + (long long)w * p.sP : nullptr;
+  const TC* P3 = p.P3 ? (const TC*)p.P3 + (long long)w * p.sP : nullptr;
+  // One epilogue operand (P1 alone, or C when beta != 0) is loaded during the last k-tile
+  // so that its latency overlaps the MFMAs.
+  const bool pre_p1 = P1 && !P2 && !P3 && p.beta == 0.0;
+  const bool pre_c = !P1 && p.beta != 0.0;
+  const TC* PRE = pre_p1 ? P1 : (pre_c ? (const TC*)C : nullptr);
+  const int pre_ld = pre_p1 ? p.ldp : p.ldc;
+  TC pre[2][2][4];                     // kept in the output precision (complex64 in the mixed path)
+  const int li = lane & 15, lk = lane >> 4;
+  // 16 x 16 blocks entirely outside the m x n result are skipped (uniform per wave)
+  bool live[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) live[i][j] = (m0 + wr * 32 + i * 16 < Mr) && (n0 + wc * 32 + j * 16 < Nc);
+
   load_tile(0);
   store_tile(0);
   __syncthreads();
-  const int li = lane & 15, lk = lane >> 4;
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) load_tile(kt + 1);
+    if (kt + 1 == nk && PRE) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int gi = m0 + wr * 32 + i * 16 + Mfma<ACC>::row(lane, v);
+            const int gj = n0 + wc * 32 + j * 16 + li;
+            pre[i][j][v] = (gi < Mr && gj < Nc) ? PRE[(long long)gi * pre_ld + gj] : TC{};
+          }
+    }
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       cacc a[2], b[2];
@@ -122,6 +153,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
         const ACC nai = -a[i].y;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
+          if (!live[i][j]) continue;
           accR[i][j] = Mfma<ACC>::mma(a[i].x, b[j].x, accR[i][j]);
           accR[i][j] = Mfma<ACC>::mma(nai, b[j].y, accR[i][j]);
           accI[i][j] = Mfma<ACC>::mma(a[i].x, b[j].y, accI[i][j]);
@@ -134,11 +166,6 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
   }
 
   // epilogue
-  TC* C = (TC*)p.C + (long long)w * p.sC;
-  TC* C2 = p.C2 ? (TC*)p.C2 + (long long)w * p.sC : nullptr;
-  const TC* P1 = p.P1 ? (const TC*)p.P1 + (long long)w * p.sP : nullptr;
-  const TC* P2 = p.P2 ? (const TC*)p.P2 + (long long)w * p.sP : nullptr;
-  const TC* P3 = p.P3 ? (const TC*)p.P3 + (long long)w * p.sP : nullptr;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -148,22 +175,42 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
         const int gi = m0 + wr * 32 + i * 16 + Mfma<ACC>::row(lane, v);
         const int gj = n0 + wc * 32 + j * 16 + li;
         if (gi >= p.mpad || gj >= p.npad) continue;
-        double2 out = make_double2(0.0, 0.0), out2 = make_double2(0.0, 0.0);
-        if (gi < Mr && gj < Nc) {
-          const double2 acc = make_double2((double)accR[i][j][v], (double)accI[i][j][v]);
+        const long long off = (long long)gi * p.ldc + gj;
+        const bool in = gi < Mr && gj < Nc;
+        const double2 acc = make_double2((double)accR[i][j][v], (double)accI[i][j][v]);
+        double2 q1 = make_double2(0.0, 0.0), q2 = q1, q3 = q1, qc = q1;
+        if (in) {
+          const long long offp = (long long)gi * p.ldp + gj;
+          if (pre_p1) q1 = to_d2(pre[i][j][v]);
+          else if (P1) q1 = ld_c(P1 + offp);
+          if (P2) q2 = ld_c(P2 + offp);
+          if (P3) q3 = ld_c(P3 + offp);
+          if (pre_c) qc = to_d2(pre[i][j][v]);
+          else if (p.beta != 0.0) qc = ld_c(C + off);
+        }
+        const double di = (gi == gj) ? 1.0 : 0.0;
+        double2 out = make_double2(0.0, 0.0);
+        if (in) {
           out = cscale(acc, p.alpha);
-          out2 = cscale(acc, p.beta2);
-          if (p.beta != 0.0) out = cadd(out, cscale(ld_c(C + (long long)gi * p.ldc + gj), p.beta));
-          if (gi == gj) { out.x += p.cI; out2.x += p.dI; }
-          const long long off = (long long)gi * p.ldp + gj;
-          if (P1) { double2 q = ld_c(P1 + off); out = cadd(out, cscale(q, p.c1)); out2 = cadd(out2, cscale(q, p.d1)); }
-          if (P2) { double2 q = ld_c(P2 + off); out = cadd(out, cscale(q, p.c2)); out2 = cadd(out2, cscale(q, p.d2)); }
-          if (P3) { double2 q = ld_c(P3 + off); out = cadd(out, cscale(q, p.c3)); out2 = cadd(out2, cscale(q, p.d3)); }
+          if (p.beta != 0.0) out = cadd(out, cscale(qc, p.beta));
+          out.x += p.cI * di;
+          out = cadd(out, cadd(cscale(q1, p.c1), cadd(cscale(q2, p.c2), cscale(q3, p.c3))));
           if (p.rs) out = cscale(out, p.rs[gi]);
           if (p.cs) out = cscale(out, p.cs[gj]);
         }
-        store_c(C + (long long)gi * p.ldc + gj, out);
-        if (C2) store_c(C2 + (long long)gi * p.ldc + gj, out2);
+        store_c(C + off, out);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (e >= p.nextra) break;
+          const GemmOut& o = p.extra[e];
+          double2 x = make_double2(0.0, 0.0);
+          if (in) {
+            x = cscale(acc, o.cacc);
+            x.x += o.cI * di;
+            x = cadd(x, cadd(cscale(q1, o.c1), cadd(cscale(q2, o.c2), cscale(q3, o.c3))));
+          }
+          store_c((TC*)o.ptr + (long long)w * p.sC + off, x);
+        }
       }
 }
 
@@ -176,13 +223,15 @@ hipError_t launch_zgemm(const GemmParams& p0, int prec, hipStream_t s) {
   p.tiles_n = (p.npad + BN - 1) / BN;
   const int blocks = ((p.W + 7) / 8) * 8 * p.tiles_m * p.tiles_n;
   if (blocks == 0) return hipSuccess;
-  switch (prec) {
-    case GEMM_Z64:   // complex128 in and out, FP64 MFMA
-      zgemm_kernel<double2, double2, double2, double><<<blocks, 256, 0, s>>>(p); break;
-    case GEMM_C32:   // complex64 in and out, FP32 MFMA
-      zgemm_kernel<float2, float2, float2, float><<<blocks, 256, 0, s>>>(p); break;
-    case GEMM_C32_Z64B:  // complex64 A, complex128 B (rounded to complex64), complex128 out
-      zgemm_kernel<float2, double2, double2, float><<<blocks, 256, 0, s>>>(p); break;
+  switch (prec * 2 + (p.role ? 1 : 0)) {
+    case 2 * GEMM_Z64:       // complex128 in and out, FP64 MFMA (propagator chain)
+      zgemm_kernel<double2, double2, double2, double, 0><<<blocks, 256, 0, s>>>(p); break;
+    case 2 * GEMM_Z64 + 1:   // the same for the dense linear algebra
+      zgemm_kernel<double2, double2, double2, double, 1><<<blocks, 256, 0, s>>>(p); break;
+    case 2 * GEMM_C32:       // complex64 in and out, FP32 MFMA
+      zgemm_kernel<float2, float2, float2, float, 0><<<blocks, 256, 0, s>>>(p); break;
+    case 2 * GEMM_C32_Z64B:  // complex64 A, complex128 B (rounded to complex64), complex128 out
+      zgemm_kernel<float2, double2, double2, float, 0><<<blocks, 256, 0, s>>>(p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

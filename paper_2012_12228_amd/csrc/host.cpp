@@ -189,6 +189,7 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.V2 = take(velem * mat * W);
   d.V3 = take(velem * mat * W);
   d.V4 = take(velem * mat * W);
+  for (int k = 0; k < 3; ++k) d.Bk[k] = take(velem * mat * W);
   d.E0 = take(sizeof(double2) * mat * W);
   d.E1 = take(sizeof(double2) * mat * W);
   d.D = (double*)take(sizeof(double) * ld * W);
@@ -275,31 +276,38 @@ GemmParams gp_base(const HostSys& s) {
 
 double inv_fact(int j) { double f = 1.0; for (int i = 2; i <= j; ++i) f *= i; return 1.0 / f; }
 
-// Y <- K e^V K Y with e^V by Paterson-Stockmeyer (blocks of 4): degree 16 in FP64
-// (6 products), degree 12 in mixed precision (5 products); one more to apply.
+// Y <- K e^V K Y with e^V = sum_{j<=deg} V^j / j! by Paterson-Stockmeyer with blocks of 4:
+// B_k = sum_{r<4} a_{4k+r} V^r and e^V = (((a_deg V^4 + B_top) V^4 + ...) V^4 + B_0).
+// FP64: degree 16 (nb = 4 blocks); mixed: degree 12 (nb = 3).  The V^4 product also writes
+// the top Horner term and the lower blocks, so every Horner step reads one matrix.
 int apply_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   SysDev& d = s.dev;
   const bool mixed = s.p.precision == FTAFQMC_MIXED;
   const int prec = mixed ? GEMM_C32 : GEMM_Z64;
-  const int deg = mixed ? 12 : 16;
+  const int nb = mixed ? 3 : 4;
+  const int deg = 4 * nb;
   GemmParams g = gp_base(s);
   g.A = d.V; g.B = d.V; g.C = d.V2;
-  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));                       // V^2
+  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));   // V^2
   g.A = d.V2; g.B = d.V; g.C = d.V3;
-  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));                       // V^3
-  // V^4 and the top Horner block a_deg V^4 + sum_{r<4} a_{deg-4+r} V^r
-  g.A = d.V2; g.B = d.V2; g.C = d.V4; g.C2 = d.E0;
+  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));   // V^3
+  g.A = d.V2; g.B = d.V2; g.C = d.V4;                                                  // V^4 and the blocks
   g.P1 = d.V; g.P2 = d.V2; g.P3 = d.V3;
-  g.beta2 = inv_fact(deg); g.dI = inv_fact(deg - 4); g.d1 = inv_fact(deg - 3); g.d2 = inv_fact(deg - 2); g.d3 = inv_fact(deg - 1);
+  g.nextra = nb;
+  {
+    const int top = 4 * (nb - 1);
+    g.extra[0] = GemmOut{d.E0, inv_fact(deg), inv_fact(top), inv_fact(top + 1), inv_fact(top + 2), inv_fact(top + 3)};
+    for (int k = nb - 2, e = 1; k >= 0; --k, ++e)
+      g.extra[e] = GemmOut{d.Bk[k], 0.0, inv_fact(4 * k), inv_fact(4 * k + 1), inv_fact(4 * k + 2), inv_fact(4 * k + 3)};
+  }
   HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));
   void* cur = d.E0;
   void* nxt = d.E1;
-  for (int top = deg - 8; top >= 0; top -= 4) {
+  for (int k = nb - 2; k >= 0; --k) {
     GemmParams e = gp_base(s);
     e.A = cur; e.B = d.V4; e.C = nxt;
-    e.P1 = d.V; e.P2 = d.V2; e.P3 = d.V3;
-    e.cI = inv_fact(top); e.c1 = inv_fact(top + 1); e.c2 = inv_fact(top + 2); e.c3 = inv_fact(top + 3);
-    if (top == 0) { e.rs = d.kh; e.cs = d.kh; }            // K e^V K
+    e.P1 = d.Bk[k]; e.c1 = 1.0;
+    if (k == 0) { e.rs = d.kh; e.cs = d.kh; }            // K e^V K
     HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(e, prec, st); }));
     std::swap(cur, nxt);
   }
@@ -316,7 +324,7 @@ int stabilise(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_perm(d, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_gather(d, st); }));
   GemmParams g = gp_base(s);
-  g.A = d.E0; g.B = d.E0; g.C = d.aug; g.opA = 1;
+  g.A = d.E0; g.B = d.E0; g.C = d.aug; g.opA = 1; g.role = 1;
   g.sC = d.aug_stride; g.ldc = 2 * s.ld;
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));  // S = E0^H E0 into the left block
   ElimParams e;

@@ -4,11 +4,12 @@
 
 enum { GEMM_Z64 = 0, GEMM_C32 = 1, GEMM_C32_Z64B = 2 };
 
-// C = alpha op(A) op(B) + beta C + cI I + c1 P1 + c2 P2 + c3 P3, then diag(rs) C diag(cs);
-// C2 = beta2 op(A) op(B) + dI I + d1 P1 + d2 P2 + d3 P3.  C is m x n, the inner size k.
-// Entries (i, j) with m <= i < mpad or n <= j < npad are written as zero.
+// Primary output: C = diag(rs) [alpha op(A) op(B) + beta C + cI I + c1 P1 + c2 P2 + c3 P3] diag(cs).
+// Extra outputs X_e = cacc op(A) op(B) + cI I + c1 P1 + c2 P2 + c3 P3 (same layout as C, unscaled).
+// C is m x n with inner size k; entries with m <= i < mpad or n <= j < npad are written as zero.
+struct GemmOut { void* ptr; double cacc, cI, c1, c2, c3; };
 struct GemmParams {
-  const void* A; const void* B; void* C; void* C2;
+  const void* A; const void* B; void* C;
   const void* P1; const void* P2; const void* P3;
   const double* rs; const double* cs;
   long long sA, sB, sC, sP;  // walker strides in elements
@@ -16,7 +17,9 @@ struct GemmParams {
   int m, n, k, mpad, npad, W;
   int opA, opB;              // 0 = as stored, 1 = conjugate transpose
   double alpha, beta, cI, c1, c2, c3;
-  double beta2, dI, d1, d2, d3;
+  int nextra;                // 0..4 extra outputs
+  GemmOut extra[4];
+  int role;                  // 0 = propagator chain, 1 = elimination / stabilisation (separate kernel symbols)
   int tiles_m, tiles_n;      // set by the launcher
 };
 hipError_t launch_zgemm(const GemmParams& p, int prec, hipStream_t s);
@@ -57,6 +60,7 @@ struct SysDev {
   // state
   double2* Y; double2* Ti; double2* G; double2* aug;
   void* V; void* V2; void* V3; void* V4; void* E0; void* E1;  // complex128 or complex64
+  void* Bk[3];            // Paterson-Stockmeyer blocks B_0..B_2 (complex128 or complex64)
   double2* Ynew;
   double* D; double* Dpi; int* perm; int* piv;
   double2* tri;           // [W][elim_tri_elems(M)]
