@@ -93,6 +93,8 @@ typedef struct {
   int n_measure;    /* energy records so far (one per stabilisation boundary and at slice n) */
   int ld;           /* padded leading dimension used internally */
   double beta, dtau, L, omega, mu_T, mu, e_madelung;
+  int gemm_tile_chain;   /* propagator GEMM tile shape chosen by the start-up autotuner */
+  int gemm_tile_apply;   /* tile shape of the product that applies e^V */
 } ftafqmc_info;
 
 /* Bytes of device workspace needed for the n_sys systems listed in p[0..n_sys-1]

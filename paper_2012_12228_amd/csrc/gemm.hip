@@ -7,8 +7,10 @@
 // extra passes over memory.  A single epilogue operand is prefetched during the last
 // k-tile; 16 x 16 blocks outside the m x n result issue no MFMAs.
 //
-// Tiling: 64 x 64 output tile per 256-thread workgroup (2 x 2 waves, each wave
-// 2 x 2 blocks of 16 x 16), K staged through LDS 16 at a time, double-buffered.
+// Tiling: a BM x BN output tile per workgroup of (BM/WM) x (BN/WN) waves, each wave a WM x WN
+// tile of 16 x 16 MFMA blocks; K staged through LDS BK at a time, double-buffered.  Several
+// tile shapes are built; the library times them on the real problem size at start-up and
+// keeps the fastest per system and precision (see gemm_tile_count / the tile field).
 // Complex products use four real MFMAs: re += a.re b.re - a.im b.im,
 // im += a.re b.im + a.im b.re.  FP64 path: v_mfma_f64_16x16x4f64; mixed path:
 // v_mfma_f32_16x16x4f32 with complex64 operands and FP32 accumulation.
@@ -22,7 +24,15 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
+constexpr int PAD = 1;
+
+template <int BM_, int BN_, int BK_, int WM_, int WN_> struct Tile {
+  static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+  static constexpr int WGM = BM / WM, WGN = BN / WN, NT = 64 * WGM * WGN;
+  static constexpr int FM = WM / 16, FN = WN / 16;
+  static constexpr int EA = BM * BK / NT, EB = BK * BN / NT;
+  static_assert(EA * NT == BM * BK && EB * NT == BK * BN, "tile loads must split evenly");
+};
 
 template <typename ACC> struct Mfma;
 template <> struct Mfma<double> {
@@ -40,10 +50,11 @@ template <> struct Mfma<float> {
 
 template <typename T> FT_DEV double2 ld_c(const T* p) { return to_d2(*p); }
 
-template <typename TA, typename TB, typename TC, typename ACC, int ROLE>
-__global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
+template <typename TA, typename TB, typename TC, typename ACC, int ROLE, typename TL>
+__global__ __launch_bounds__(TL::NT) void zgemm_kernel(GemmParams p) {
   typedef typename cplx_of<ACC>::type cacc;
   typedef typename Mfma<ACC>::acc_t acc_t;
+  constexpr int BM = TL::BM, BN = TL::BN, BK = TL::BK, FM = TL::FM, FN = TL::FN, NT = TL::NT;
   __shared__ cacc As[2][BK][BM + PAD];
   __shared__ cacc Bs[2][BK][BN + PAD];
 
@@ -52,54 +63,59 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
   const int tm = tile / p.tiles_n, tn = tile - tm * p.tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
+  const int wr = wid / TL::WGN, wc = wid % TL::WGN;
   const int Mr = p.m, Nc = p.n, Kd = p.k;
 
   const TA* A = (const TA*)p.A + (long long)w * p.sA;
   const TB* B = (const TB*)p.B + (long long)w * p.sB;
 
-  acc_t accR[2][2], accI[2][2];
+  acc_t accR[FM][FN], accI[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) { accR[i][j][v] = 0; accI[i][j][v] = 0; }
 
-  cacc ra[4], rb[4];
-  // global -> registers for k-tile kt
+  cacc ra[TL::EA], rb[TL::EB];
+  // global -> registers for k-tile kt; consecutive threads read consecutive addresses
   auto load_tile = [&](int kt) {
     const int k0 = kt * BK;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int q = 0; q < TL::EA; ++q) {
+      const int e = t + q * NT;
       int gm, gk;
-      if (p.opA == 0) { gm = m0 + (t >> 2); gk = k0 + ((t & 3) << 2) + e; }
-      else            { gk = k0 + (t >> 4); gm = m0 + ((t & 15) << 2) + e; }
+      if (p.opA == 0) { gm = m0 + e / BK; gk = k0 + e % BK; }
+      else            { gk = k0 + e / BM; gm = m0 + e % BM; }
       double2 v = make_double2(0.0, 0.0);
-      if (gm < Mr && gk < Kd) {
+      if (gm < Mr && gk < Kd)
         v = p.opA == 0 ? ld_c(A + (long long)gm * p.lda + gk) : cconj(ld_c(A + (long long)gk * p.lda + gm));
-      }
-      ra[e] = cvt<ACC>(v);
+      ra[q] = cvt<ACC>(v);
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int q = 0; q < TL::EB; ++q) {
+      const int e = t + q * NT;
       int gk, gn;
-      if (p.opB == 0) { gk = k0 + (t >> 4); gn = n0 + ((t & 15) << 2) + e; }
-      else            { gn = n0 + (t >> 2); gk = k0 + ((t & 3) << 2) + e; }
+      if (p.opB == 0) { gk = k0 + e / BN; gn = n0 + e % BN; }
+      else            { gn = n0 + e / BK; gk = k0 + e % BK; }
       double2 v = make_double2(0.0, 0.0);
-      if (gn < Nc && gk < Kd) {
+      if (gn < Nc && gk < Kd)
         v = p.opB == 0 ? ld_c(B + (long long)gk * p.ldb + gn) : cconj(ld_c(B + (long long)gn * p.ldb + gk));
-      }
-      rb[e] = cvt<ACC>(v);
+      rb[q] = cvt<ACC>(v);
     }
   };
   auto store_tile = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      if (p.opA == 0) As[buf][((t & 3) << 2) + e][t >> 2] = ra[e];
-      else            As[buf][t >> 4][((t & 15) << 2) + e] = ra[e];
-      if (p.opB == 0) Bs[buf][t >> 4][((t & 15) << 2) + e] = rb[e];
-      else            Bs[buf][((t & 3) << 2) + e][t >> 2] = rb[e];
+    for (int q = 0; q < TL::EA; ++q) {
+      const int e = t + q * NT;
+      if (p.opA == 0) As[buf][e % BK][e / BK] = ra[q];
+      else            As[buf][e / BM][e % BM] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < TL::EB; ++q) {
+      const int e = t + q * NT;
+      if (p.opB == 0) Bs[buf][e / BN][e % BN] = rb[q];
+      else            Bs[buf][e % BK][e / BK] = rb[q];
     }
   };
 
@@ -114,14 +130,14 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
   const bool pre_c = !P1 && p.beta != 0.0;
   const TC* PRE = pre_p1 ? P1 : (pre_c ? (const TC*)C : nullptr);
   const int pre_ld = pre_p1 ? p.ldp : p.ldc;
-  TC pre[2][2][4];                     // kept in the output precision (complex64 in the mixed path)
+  TC pre[FM][FN][4];                     // kept in the output precision (complex64 in the mixed path)
   const int li = lane & 15, lk = lane >> 4;
   // 16 x 16 blocks entirely outside the m x n result are skipped (uniform per wave)
-  bool live[2][2];
+  bool live[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) live[i][j] = (m0 + wr * 32 + i * 16 < Mr) && (n0 + wc * 32 + j * 16 < Nc);
+    for (int j = 0; j < FN; ++j) live[i][j] = (m0 + wr * TL::WM + i * 16 < Mr) && (n0 + wc * TL::WN + j * 16 < Nc);
 
   load_tile(0);
   store_tile(0);
@@ -131,28 +147,28 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
     if (kt + 1 < nk) load_tile(kt + 1);
     if (kt + 1 == nk && PRE) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int gi = m0 + wr * 32 + i * 16 + Mfma<ACC>::row(lane, v);
-            const int gj = n0 + wc * 32 + j * 16 + li;
+            const int gi = m0 + wr * TL::WM + i * 16 + Mfma<ACC>::row(lane, v);
+            const int gj = n0 + wc * TL::WN + j * 16 + li;
             pre[i][j][v] = (gi < Mr && gj < Nc) ? PRE[(long long)gi * pre_ld + gj] : TC{};
           }
     }
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
-      cacc a[2], b[2];
+      cacc a[FM], b[FN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[buf][ks + lk][wr * 32 + i * 16 + li];
+      for (int i = 0; i < FM; ++i) a[i] = As[buf][ks + lk][wr * TL::WM + i * 16 + li];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[buf][ks + lk][wc * 32 + j * 16 + li];
+      for (int j = 0; j < FN; ++j) b[j] = Bs[buf][ks + lk][wc * TL::WN + j * 16 + li];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < FM; ++i) {
         const ACC nai = -a[i].y;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < FN; ++j) {
           if (!live[i][j]) continue;
           accR[i][j] = Mfma<ACC>::mma(a[i].x, b[j].x, accR[i][j]);
           accR[i][j] = Mfma<ACC>::mma(nai, b[j].y, accR[i][j]);
@@ -167,13 +183,13 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
 
   // epilogue
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gi = m0 + wr * 32 + i * 16 + Mfma<ACC>::row(lane, v);
-        const int gj = n0 + wc * 32 + j * 16 + li;
+        const int gi = m0 + wr * TL::WM + i * 16 + Mfma<ACC>::row(lane, v);
+        const int gj = n0 + wc * TL::WN + j * 16 + li;
         if (gi >= p.mpad || gj >= p.npad) continue;
         const long long off = (long long)gi * p.ldc + gj;
         const bool in = gi < Mr && gj < Nc;
@@ -214,25 +230,50 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
       }
 }
 
-}  // namespace
+typedef Tile<64, 64, 16, 32, 32> T64x64;     // 4 waves of 32 x 32
+typedef Tile<64, 128, 16, 32, 64> T64x128;   // 4 waves of 32 x 64
+typedef Tile<128, 64, 16, 64, 32> T128x64;   // 4 waves of 64 x 32
+typedef Tile<32, 64, 16, 16, 32> T32x64;     // 4 waves of 16 x 32
+typedef Tile<32, 32, 16, 16, 16> T32x32;     // 4 waves of 16 x 16
 
-hipError_t launch_zgemm(const GemmParams& p0, int prec, hipStream_t s) {
-  GemmParams p = p0;
-  if (p.m <= 0 || p.n <= 0 || p.mpad < p.m || p.npad < p.n) return p.m <= 0 || p.n <= 0 ? hipSuccess : hipErrorInvalidValue;
-  p.tiles_m = (p.mpad + BM - 1) / BM;
-  p.tiles_n = (p.npad + BN - 1) / BN;
+template <typename TA, typename TB, typename TC, typename ACC, int ROLE, typename TL>
+hipError_t launch_tile(GemmParams p, hipStream_t s) {
+  p.tiles_m = (p.mpad + TL::BM - 1) / TL::BM;
+  p.tiles_n = (p.npad + TL::BN - 1) / TL::BN;
   const int blocks = ((p.W + 7) / 8) * 8 * p.tiles_m * p.tiles_n;
   if (blocks == 0) return hipSuccess;
-  switch (prec * 2 + (p.role ? 1 : 0)) {
-    case 2 * GEMM_Z64:       // complex128 in and out, FP64 MFMA (propagator chain)
-      zgemm_kernel<double2, double2, double2, double, 0><<<blocks, 256, 0, s>>>(p); break;
-    case 2 * GEMM_Z64 + 1:   // the same for the dense linear algebra
-      zgemm_kernel<double2, double2, double2, double, 1><<<blocks, 256, 0, s>>>(p); break;
-    case 2 * GEMM_C32:       // complex64 in and out, FP32 MFMA
-      zgemm_kernel<float2, float2, float2, float, 0><<<blocks, 256, 0, s>>>(p); break;
-    case 2 * GEMM_C32_Z64B:  // complex64 A, complex128 B (rounded to complex64), complex128 out
-      zgemm_kernel<float2, double2, double2, float, 0><<<blocks, 256, 0, s>>>(p); break;
+  zgemm_kernel<TA, TB, TC, ACC, ROLE, TL><<<blocks, TL::NT, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+template <typename TA, typename TB, typename TC, typename ACC, int ROLE>
+hipError_t launch_shape(const GemmParams& p, hipStream_t s) {
+  switch (p.tile) {
+    case 0: return launch_tile<TA, TB, TC, ACC, ROLE, T64x64>(p, s);
+    case 1: return launch_tile<TA, TB, TC, ACC, ROLE, T64x128>(p, s);
+    case 2: return launch_tile<TA, TB, TC, ACC, ROLE, T128x64>(p, s);
+    case 3: return launch_tile<TA, TB, TC, ACC, ROLE, T32x64>(p, s);
+    case 4: return launch_tile<TA, TB, TC, ACC, ROLE, T32x32>(p, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+}
+
+}  // namespace
+
+int gemm_tile_count() { return 5; }
+
+hipError_t launch_zgemm(const GemmParams& p, int prec, hipStream_t s) {
+  if (p.m <= 0 || p.n <= 0) return hipSuccess;
+  if (p.mpad < p.m || p.npad < p.n) return hipErrorInvalidValue;
+  switch (prec * 2 + (p.role ? 1 : 0)) {
+    case 2 * GEMM_Z64:       // complex128 in and out, FP64 MFMA (propagator chain)
+      return launch_shape<double2, double2, double2, double, 0>(p, s);
+    case 2 * GEMM_Z64 + 1:   // the same for the dense linear algebra (64 x 64 tiles)
+      return launch_tile<double2, double2, double2, double, 1, T64x64>(p, s);
+    case 2 * GEMM_C32:       // complex64 in and out, FP32 MFMA
+      return launch_shape<float2, float2, float2, float, 0>(p, s);
+    case 2 * GEMM_C32_Z64B:  // complex64 A, complex128 B (rounded to complex64), complex128 out
+      return launch_shape<float2, double2, double2, float, 0>(p, s);
+    default: return hipErrorInvalidValue;
+  }
 }

@@ -5,6 +5,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -44,6 +45,7 @@ struct HostSys {
   double2* mean = nullptr;
   int k = 0, nrec = 0;
   std::vector<int> rec_slice;
+  int tile_chain = 0, tile_apply = 0;   // GEMM tile shapes chosen by the start-up autotuner
 };
 
 // Logistic 1/(1+e^x) without overflow.
@@ -287,6 +289,7 @@ int apply_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   const int nb = mixed ? 3 : 4;
   const int deg = 4 * nb;
   GemmParams g = gp_base(s);
+  g.tile = s.tile_chain;
   g.A = d.V; g.B = d.V; g.C = d.V2;
   HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));   // V^2
   g.A = d.V2; g.B = d.V; g.C = d.V3;
@@ -305,6 +308,7 @@ int apply_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   void* nxt = d.E1;
   for (int k = nb - 2; k >= 0; --k) {
     GemmParams e = gp_base(s);
+    e.tile = s.tile_chain;
     e.A = cur; e.B = d.V4; e.C = nxt;
     e.P1 = d.Bk[k]; e.c1 = 1.0;
     if (k == 0) { e.rs = d.kh; e.cs = d.kh; }            // K e^V K
@@ -312,6 +316,7 @@ int apply_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
     std::swap(cur, nxt);
   }
   GemmParams a = gp_base(s);
+  a.tile = s.tile_apply;
   a.A = cur; a.B = d.Y; a.C = d.Ynew;
   HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(a, mixed ? GEMM_C32_Z64B : GEMM_Z64, st); }));
   std::swap(d.Y, d.Ynew);
@@ -352,6 +357,50 @@ int greens(ftafqmc_ctx* h, HostSys& s, int k, int init, hipStream_t st) {
   const double slb = sum_ln_lb(s, k);
   HIPCHK(timed(h, FTAFQMC_PROF_WEIGHT, st, [&] { return launch_weight(d, k, slb, init, st); }));
   return FTAFQMC_OK;
+}
+
+// Start-up autotuner: time every GEMM tile shape on this system's real size (W walkers of
+// M x M x M products) for the propagator chain and for the final apply, keep the fastest.
+// FTAFQMC_GEMM_TILE=<index> in the environment forces one shape (for experiments).
+int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
+  SysDev& d = s.dev;
+  const bool mixed = s.p.precision == FTAFQMC_MIXED;
+  const size_t velem = mixed ? sizeof(float2) : sizeof(double2);
+  const size_t mat = (size_t)s.ld * s.ld * s.p.n_walkers;
+  if (const char* env = std::getenv("FTAFQMC_GEMM_TILE")) {
+    const int t = std::atoi(env);
+    if (t >= 0 && t < gemm_tile_count()) { s.tile_chain = s.tile_apply = t; return FTAFQMC_OK; }
+  }
+  HIPCHK(hipMemsetAsync(d.V, 0, velem * mat, st));
+  HIPCHK(hipMemsetAsync(d.Ynew, 0, sizeof(double2) * mat, st));
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  int rc = FTAFQMC_OK;
+  for (int kind = 0; kind < 2 && rc == FTAFQMC_OK; ++kind) {
+    float best = 1e30f;
+    int besti = 0;
+    for (int t = 0; t < gemm_tile_count(); ++t) {
+      GemmParams g = gp_base(s);
+      g.tile = t;
+      int prec = mixed ? GEMM_C32 : GEMM_Z64;
+      if (kind == 0) { g.A = d.V; g.B = d.V; g.C = d.V2; }
+      else { g.A = d.V; g.B = d.Ynew; g.C = d.E1; if (mixed) prec = GEMM_C32_Z64B; }
+      hipError_t e = launch_zgemm(g, prec, st);                 // warm-up
+      if (e == hipSuccess) e = hipEventRecord(a, st);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_zgemm(g, prec, st);
+      if (e == hipSuccess) e = hipEventRecord(b, st);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e != hipSuccess) { rc = h->set(FTAFQMC_E_HIP, std::string("autotune: ") + hipGetErrorString(e)); break; }
+      if (ms < best) { best = ms; besti = t; }
+    }
+    if (kind == 0) s.tile_chain = besti; else s.tile_apply = besti;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
 }
 
 int reset_sys(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
@@ -446,6 +495,7 @@ int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size
     // the host tables are no longer needed once the copies have completed
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { delete h; return FTAFQMC_E_HIP; }
+    if (autotune_gemm(h, s, st) != FTAFQMC_OK) { delete h; return FTAFQMC_E_HIP; }
     if (reset_sys(h, s, st) != FTAFQMC_OK) { delete h; return FTAFQMC_E_HIP; }
   }
   *out = h;
@@ -461,6 +511,7 @@ int ftafqmc_query(ftafqmc_t h, int sys, ftafqmc_info* out) {
   out->slice = s.k; out->n_measure = s.nrec; out->ld = s.ld;
   out->beta = s.beta; out->dtau = s.dtau; out->L = s.L; out->omega = s.omega;
   out->mu_T = s.muT; out->mu = s.mu; out->e_madelung = s.EM;
+  out->gemm_tile_chain = s.tile_chain; out->gemm_tile_apply = s.tile_apply;
   return FTAFQMC_OK;
 }
 

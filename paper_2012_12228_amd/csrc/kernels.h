@@ -20,9 +20,11 @@ struct GemmParams {
   int nextra;                // 0..4 extra outputs
   GemmOut extra[4];
   int role;                  // 0 = propagator chain, 1 = elimination / stabilisation (separate kernel symbols)
+  int tile;                  // tile shape index (0 .. gemm_tile_count()-1) for role 0
   int tiles_m, tiles_n;      // set by the launcher
 };
 hipError_t launch_zgemm(const GemmParams& p, int prec, hipStream_t s);
+int gemm_tile_count();
 
 // Blocked Gaussian elimination on a per-walker augmented matrix [A | R] (M x M
 // left block, nrhs right-hand sides starting at column rhs_off, row stride lda).

@@ -290,3 +290,27 @@ def test_m485_full_size_fp64():
 
 def test_m485_full_size_mixed():
     _full_size("ueg_n114_m485", 1)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_every_gemm_tile_shape_gives_the_same_path(precision, monkeypatch):
+    """Each tile shape the autotuner may pick reproduces the default shape's result."""
+    F = _F()
+    sd = dict(n_elec=38, rs=1.0, theta=0.25, nmax2=5, dtau=0.05, stab_every=5, walkers=3, precision=precision)
+    s = oracle_system(sd)
+    flds = si.fields(31, 3, s.n_slices, s.NQ)
+    ref = None
+    for tile in range(5):
+        monkeypatch.setenv("FTAFQMC_GEMM_TILE", str(tile))
+        ctx, _ = gpu_run(F, [sd], [flds])
+        assert ctx.info()["gemm_tile_chain"] == tile
+        G = ctx.greens().cpu().numpy()
+        E = ctx.records()["trace"].cpu().numpy()
+        if ref is None:
+            ref = (G, E)
+        else:
+            assert rel_mat(G, ref[0]) < 1e-12, tile
+            assert rel_mat(E, ref[1]) < 1e-12, tile
+    monkeypatch.delenv("FTAFQMC_GEMM_TILE")
+    ctx, _ = gpu_run(F, [sd], [flds])
+    assert 0 <= ctx.info()["gemm_tile_chain"] < 5
