@@ -25,6 +25,20 @@ sys.path.insert(0, ROOT)
 import synthinputs as si  # noqa: E402
 
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per propagator-GEMM launch from the committed rocprofv3 counter summary,
+    or None when no summary exists or the GEMM source changed since it was taken."""
+    import hashlib
+    fn = os.path.join(ROOT, "profiles", "%s_%s_gemm_traffic.txt" % (workload, precision))
+    if not os.path.exists(fn):
+        return None
+    kv = dict(line.strip().split("=", 1) for line in open(fn) if "=" in line and not line.startswith("#"))
+    src = os.path.join(ROOT, "paper_2012_12228_amd", "csrc", "gemm.hip")
+    if hashlib.sha1(open(src, "rb").read()).hexdigest() != kv.get("gemm_sha1"):
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 MIXED_E_TOL = 1e-6
 
 
@@ -109,6 +123,8 @@ def main():
     ap.add_argument("--workload", default="ueg_n66_m171")
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (walkers would shard "
@@ -117,6 +133,13 @@ def main():
     import torch
     import paper_2012_12228_amd as F
     F.load_library()
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 4
+        src_t = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
     wl = si.WORKLOADS[args.workload]
     # field shapes (n slices, N_Q) from the library's own tables
     fields = []
@@ -169,7 +192,8 @@ def main():
             {k: v for k, v in sd.items()} for sd in wl["systems"]], "precision_reported": use},
         "roofline": {"bound": "mfma", "kernel": "propagator complex GEMM (%s MFMA)" % prec_key,
                      "achieved": achieved, "peak": PEAK_TFLOPS[prec_key], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS[prec_key], "traffic": None,
+                     "frac": achieved / PEAK_TFLOPS[prec_key],
+                     "traffic": measured_traffic(args.workload, use),
                      "avg_launch_ms": r["gemm_avg_ms"]},
         "fp64": results.get("fp64"), "mixed": results.get("mixed"),
     }
