@@ -17,10 +17,13 @@ Modules
               "Numerical Stabilization", "Exploiting the stack structure").
   energy   -- the local energy E_M + E_1 + E_2 with Hartree (Gamma_Q) and
               exchange (Lambda_Q) parts, and the electron number.
+  tangent  -- frozen-path derivatives of the weight and the local energy in mu and
+              the kinetic scale lambda, by doubled (block-triangular) products
+              stabilised like the forward path.
 
 Every function is pinned by a "not gpu" test against something other than
 itself (printed values of the paper, closed forms, Fock-space brute force, high
 precision products); the one quantity no pin reaches, a full interacting
 phaseless path, is "parity unpinned" beyond those invariants.
 """
-from . import ueg, path, energy  # noqa: F401
+from . import ueg, path, energy, tangent  # noqa: F401

@@ -172,10 +172,13 @@ def wrap_angle(x):
 ALIVE, KILLED, NUMERIC = 0, 1, 2
 
 
-def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, stop_after=None):
+def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, stop_after=None,
+               record_path=False):
     """Propagate one walker from tau = 0 to tau = beta with fields z[k, q].
 
     stop_after: end the path after that many slices (a bounded sample for timing).
+    record_path: also return the sampled path, i.e. the shifted one-body matrix V_k and the
+    weight exponent of every slice (out["path"]), so that replay_walker can re-run it.
 
     z: complex [n_slices, NQ]; Re z = field of A(Q), Im z = field of B(Q).
     Measures the local energy (energy_fn(sys, G)) after slice k+1 when
@@ -183,6 +186,37 @@ def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, st
     Returns a dict with per-slice ln S and theta, per-measurement records, the
     final G, ln det(I + A) and the weight.
     """
+    Vs, expos = [], []
+
+    def shifted(k, G):
+        P = np.eye(sys.M) - G.T
+        xbA, xbB = force_bias(sys, P)
+        xA, xB = z[k].real, z[k].imag
+        V = one_body_matrix(sys, hs_rho_coefficients(sys, xA - xbA, xB - xbB))
+        expo = np.sum(xA * xbA + xB * xbB - 0.5 * (xbA ** 2 + xbB ** 2))
+        if record_path:
+            Vs.append(V)
+            expos.append(expo)
+        return V, expo
+
+    out = _walk(sys, shifted, measure_every, energy_fn, keep_greens, stop_after)
+    if record_path:
+        out["path"] = dict(V=Vs, expo=expos)
+    return out
+
+
+def replay_walker(sys, frozen, measure_every=None, energy_fn=None, keep_greens=False):
+    """Re-run a recorded path: the shifted one-body matrices V_k and weight exponents are
+    taken from `frozen` (run_walker(..., record_path=True)["path"]) instead of the force bias,
+    while the one-body factors K = exp(-dtau/2 (lambda eps + h - mu)) come from `sys`.
+    Holding the path fixed makes the weight and the estimators plain functions of mu and
+    lambda (the frozen-path derivatives are taken of exactly these functions)."""
+    def recorded(k, G):
+        return frozen["V"][k], frozen["expo"][k]
+    return _walk(sys, recorded, measure_every, energy_fn, keep_greens, None)
+
+
+def _walk(sys, shifted, measure_every, energy_fn, keep_greens, stop_after):
     n, M = sys.n_slices, sys.M
     s = sys.stab_every if measure_every is None else measure_every
     right = RightBlock(M)
@@ -192,18 +226,18 @@ def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, st
     lnS_all = np.zeros(n, dtype=np.complex128)
     theta_all = np.zeros(n)
     lnI_all = np.zeros(n)
+    alive_after = np.zeros(n, dtype=bool)
     records, greens = [], []
+    greens_all = [G.copy()] if keep_greens == "all" else None
+    kh = np.exp(-0.5 * sys.dtau * sys.h1_diag())
     for k in range(n if stop_after is None else min(n, int(stop_after))):
-        P = np.eye(M) - G.T
-        xbA, xbB = force_bias(sys, P)
-        xA, xB = z[k].real, z[k].imag
-        B = slice_propagator(sys, xA - xbA, xB - xbB)
+        V, expo = shifted(k, G)
+        B = kh[:, None] * sla.expm(V) * kh[None, :]          # eq. B
         right.push(B)
         G, ell_new = greens_at(sys, right, k + 1)
         lnS = 2.0 * (ell_new - ell)
         ell = ell_new
         theta = float(wrap_angle(lnS.imag))
-        expo = np.sum(xA * xbA + xB * xbB - 0.5 * (xbA ** 2 + xbB ** 2))
         lnI = lnS.real + expo.real
         lnS_all[k], theta_all[k], lnI_all[k] = lnS, theta, lnI
         if status == ALIVE:
@@ -213,6 +247,9 @@ def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, st
                 status, logw = KILLED, -np.inf
             else:
                 logw += lnI + np.log(np.cos(theta))
+        alive_after[k] = status == ALIVE
+        if greens_all is not None:
+            greens_all.append(G.copy())
         if (k + 1) % s == 0 or k + 1 == n:
             rec = dict(slice=k + 1, logw=logw, status=status, lndet=ell)
             if energy_fn is not None:
@@ -221,5 +258,5 @@ def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, st
             if keep_greens:
                 greens.append(G.copy())
     return dict(G=G, lndet=ell, lndet0=ell0, logw=logw, status=status, lnS=lnS_all,
-                theta=theta_all, lnI=lnI_all, records=records, greens=greens,
-                right=right)
+                theta=theta_all, lnI=lnI_all, alive=alive_after, records=records, greens=greens,
+                greens_all=greens_all, right=right)
