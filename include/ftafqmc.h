@@ -80,8 +80,15 @@ typedef struct {
   double mu;       /* interacting chemical potential; NaN selects mu_T of the trial */
   double kscale;   /* lambda in H_1 = lambda T + h (1 = the physical Hamiltonian) */
   int precision;   /* FTAFQMC_FP64 or FTAFQMC_MIXED */
-  int flags;       /* reserved, 0 */
+  int flags;       /* 0 or FTAFQMC_CHECKPOINT */
 } ftafqmc_params;
+
+/* flags: record the sampled path (the shifted coefficients c_Q and tr G of every slice) so
+ * that ftafqmc_backward can differentiate it.  FP64 systems with M <= 256 only; the workspace
+ * grows by W n N_Q complex128 plus the doubled (2M x 2M) derivative state. */
+#define FTAFQMC_CHECKPOINT 1
+/* ftafqmc_backward modes */
+#define FTAFQMC_FROZEN_PATH 0
 
 /* Derived sizes and constants of one system (host-side values). */
 typedef struct {
@@ -143,11 +150,26 @@ int ftafqmc_energy(ftafqmc_t h, int sys, void* d_local, void* d_mean, double* d_
 int ftafqmc_records(ftafqmc_t h, int sys, void* d_trace, double* d_logw, int* h_slice,
                     void* stream);
 
-/* Adjoint of the weighted mean energy and electron number at the current slice
- * with respect to mu and the kinetic scale lambda, for fixed shifted fields
- * (mode 0 = FROZEN_FIELDS).  d_out [4] double = (d<E>/dmu, d<N>/dmu,
- * d<E>/dlambda, d<N>/dlambda).  Returns FTAFQMC_E_UNSUPPORTED for other modes. */
-int ftafqmc_backward(ftafqmc_t h, int sys, int mode, double* d_out, void* stream);
+/* Derivatives of the weighted means <E> and <N> at tau = beta with respect to mu and the
+ * kinetic scale lambda, for the sampled path held fixed (mode FTAFQMC_FROZEN_PATH): the
+ * fields and their force-bias shifts keep their sampled values, while mu and lambda move in
+ * the half-step factors K = exp(-dtau/2 (lambda eps + h - mu)) of every slice propagator
+ * (eq. B), hence in G, in ln det(I + A_k), in the overlap ratios S_k and phases theta_k of
+ * the phaseless weight (eqs. ftoratio, import, theta), and in the local energy (Sec.
+ * "Uniform Electron Gas").  The mu direction is exact in closed form (K scales by
+ * e^{dtau mu/2}); the lambda direction carries the doubled product [[R, dR], [0, R]] through
+ * the same stabilised factorisation as the forward path.  Replays the recorded path: the
+ * system must have been initialised with FTAFQMC_CHECKPOINT and propagated to slice n.
+ * Device pointers (each may be NULL):
+ *   d_cot    [2] double: cotangents dL/dRe<E>, dL/dRe<N> (needed for d_grad)
+ *   d_jac    [4] complex128: d<E>/dmu, d<N>/dmu, d<E>/dlambda, d<N>/dlambda
+ *   d_grad   [2] double: dL/dmu, dL/dlambda = cot . Re(jac)
+ *   d_walker [W][6] complex128: per walker (d ln w, dE, dN) along mu, then along lambda
+ *            (NaN for a walker whose doubled factorisation broke down).
+ * Walkers that are killed or numerically failed carry zero weight and do not enter the means.
+ * Errors: E_STATE without the record or before slice n; E_UNSUPPORTED for other modes. */
+int ftafqmc_backward(ftafqmc_t h, int sys, int mode, const double* d_cot, void* d_jac,
+                     double* d_grad, void* d_walker, void* stream);
 
 /* Kernel-class timing with HIP events recorded on the caller's stream around every
  * launch (instrumentation).  enable = 1 starts recording; enable = 0 stops, waits for
@@ -155,9 +177,10 @@ int ftafqmc_backward(ftafqmc_t h, int sys, int mode, double* d_out, void* stream
  * h_ms[FTAFQMC_PROF_CLASSES] and the launch counts into h_count (host arrays, may be
  * NULL).  Classes: the propagator GEMMs, the Green's-function elimination, the
  * transposes around it, the weight/force-bias kernel, the coefficient/V gather,
- * the stabilisation, the energy. */
+ * the stabilisation, the energy, the derivative replay (ftafqmc_backward). */
 enum { FTAFQMC_PROF_GEMM = 0, FTAFQMC_PROF_ELIM = 1, FTAFQMC_PROF_GREENS = 2, FTAFQMC_PROF_WEIGHT = 3,
-       FTAFQMC_PROF_COEF = 4, FTAFQMC_PROF_STAB = 5, FTAFQMC_PROF_ENERGY = 6, FTAFQMC_PROF_CLASSES = 7 };
+       FTAFQMC_PROF_COEF = 4, FTAFQMC_PROF_STAB = 5, FTAFQMC_PROF_ENERGY = 6, FTAFQMC_PROF_BACKWARD = 7,
+       FTAFQMC_PROF_CLASSES = 8 };
 int ftafqmc_profile(ftafqmc_t h, int enable, double* h_ms, long long* h_count);
 
 /* Message of the last error on this handle ("" if none); valid until the next call. */

@@ -19,13 +19,15 @@ LIB_PATH = os.path.join(_HERE, "libftafqmc.so")
 FTAFQMC_FP64, FTAFQMC_MIXED = 0, 1
 FTAFQMC_C128, FTAFQMC_C64 = 0, 1
 WALKER_ALIVE, WALKER_KILLED, WALKER_NUMERIC = 0, 1, 2
-FROZEN_FIELDS = 0
+FTAFQMC_CHECKPOINT = 1     # params flag: record the path for ftafqmc_backward
+FROZEN_PATH = 0            # ftafqmc_backward mode
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NUMERIC", -4: "E_STATE", -5: "E_UNSUPPORTED"}
 
 ABI_SYMBOLS = ["ftafqmc_workspace_bytes", "ftafqmc_init_ueg", "ftafqmc_query", "ftafqmc_reset",
                "ftafqmc_propagate", "ftafqmc_greens", "ftafqmc_energy", "ftafqmc_records",
                "ftafqmc_backward", "ftafqmc_profile", "ftafqmc_last_error", "ftafqmc_destroy"]
-PROF_CLASSES = ["gemm", "elim", "greens_transpose", "weight_forcebias", "coef_gather", "stabilise", "energy"]
+PROF_CLASSES = ["gemm", "elim", "greens_transpose", "weight_forcebias", "coef_gather", "stabilise", "energy",
+                "backward"]
 
 
 class Params(ctypes.Structure):
@@ -64,7 +66,7 @@ def load_library():
     lib.ftafqmc_greens.argtypes = [vp, ip, vp, ip, vp]
     lib.ftafqmc_energy.argtypes = [vp, ip, vp, vp, vp, vp, vp]
     lib.ftafqmc_records.argtypes = [vp, ip, vp, vp, ctypes.POINTER(ctypes.c_int), vp]
-    lib.ftafqmc_backward.argtypes = [vp, ip, ip, vp, vp]
+    lib.ftafqmc_backward.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp]
     lib.ftafqmc_profile.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
     lib.ftafqmc_last_error.argtypes = [vp]
     lib.ftafqmc_last_error.restype = ctypes.c_char_p
@@ -151,9 +153,9 @@ def ftafqmc_records(handle, sys, trace, logw, n_rec, device):
     return [slices[i] for i in range(n_rec)]
 
 
-def ftafqmc_backward(handle, sys, mode, out, device):
-    _check(load_library().ftafqmc_backward(handle, sys, mode, _ptr(out), _stream(device)), handle)
-    return out
+def ftafqmc_backward(handle, sys, mode, cot, jac, grad, walker, device):
+    _check(load_library().ftafqmc_backward(handle, sys, mode, _ptr(cot), _ptr(jac), _ptr(grad), _ptr(walker),
+                                           _stream(device)), handle)
 
 
 def ftafqmc_profile(handle, enable):
@@ -228,6 +230,23 @@ class Context:
         slices = ftafqmc_records(self.handle, sys, trace, logw, n, self.device)
         return dict(slices=slices, trace=trace[:n], logw=logw[:n])
 
+    def backward(self, sys=0, cot=None):
+        """Frozen-path derivatives at tau = beta (the system needs flags=FTAFQMC_CHECKPOINT).
+
+        Returns dict(jac [4] complex128 = d<E>/dmu, d<N>/dmu, d<E>/dlambda, d<N>/dlambda,
+        walker [W][6] complex128 = (d ln w, dE, dN) along mu then lambda, and
+        grad [2] float64 = cot . Re(jac) per parameter when cot (dL/dRe<E>, dL/dRe<N>) is given).
+        """
+        W = self.infos[sys]["n_walkers"]
+        jac = torch.empty(4, dtype=torch.complex128, device=self.device)
+        walker = torch.empty((W, 6), dtype=torch.complex128, device=self.device)
+        grad = None
+        if cot is not None:
+            cot = torch.as_tensor(cot, dtype=torch.float64, device=self.device).contiguous()
+            grad = torch.empty(2, dtype=torch.float64, device=self.device)
+        ftafqmc_backward(self.handle, sys, FROZEN_PATH, cot, jac, grad, walker, self.device)
+        return dict(jac=jac, walker=walker, grad=grad)
+
     def profile(self, enable):
         return ftafqmc_profile(self.handle, enable)
 
@@ -241,6 +260,35 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+class FrozenPathMeans(torch.autograd.Function):
+    """(mu, lambda) -> (Re<E>, Re<N>) at tau = beta for one UEG system and fixed fields.
+
+    forward runs the whole path on a fresh handle (FP64, path recorded); backward contracts the
+    cotangents with the frozen-path derivatives computed by ftafqmc_backward.  mu and kscale are
+    0-d float64 tensors; `system` is the dict accepted by Context (mu/kscale/precision/flags
+    are taken from here); fields is the complex128 [W][n][N_Q] device tensor.
+    """
+
+    @staticmethod
+    def forward(ctx, mu, kscale, system, fields):
+        sysdef = dict(system)
+        sysdef.update(mu=float(mu.detach()), kscale=float(kscale.detach()), precision=FTAFQMC_FP64,
+                      flags=FTAFQMC_CHECKPOINT)
+        c = Context(sysdef, device=fields.device)
+        c.propagate(fields)
+        e = c.energy()
+        ctx.context = c
+        return e["mean"][2].real.clone(), e["mean"][3].real.clone()
+
+    @staticmethod
+    def backward(ctx, gE, gN):
+        c = ctx.context
+        cot = torch.stack([gE.reshape(()), gN.reshape(())]).to(torch.float64)
+        g = c.backward(cot=cot)["grad"]
+        c.close()
+        return g[0], g[1], None, None
 
 
 def walker_slices_per_second(systems_info, seconds):

@@ -46,6 +46,9 @@ struct HostSys {
   int k = 0, nrec = 0;
   std::vector<int> rec_slice;
   int tile_chain = 0, tile_apply = 0;   // GEMM tile shapes chosen by the start-up autotuner
+  bool ckpt = false;                    // path recorded for the frozen-path derivative
+  int M2 = 0, ld2 = 0;                  // doubled system of the derivative
+  TanDev tan;
 };
 
 // Logistic 1/(1+e^x) without overflow.
@@ -60,6 +63,9 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
   if (p.n_walkers < 1) return "n_walkers must be >= 1";
   if (p.precision != FTAFQMC_FP64 && p.precision != FTAFQMC_MIXED) return "unknown precision";
   if (!std::isfinite(p.kscale)) return "kscale must be finite";
+  if (p.flags & ~FTAFQMC_CHECKPOINT) return "unknown flags";
+  s.ckpt = (p.flags & FTAFQMC_CHECKPOINT) != 0;
+  if (s.ckpt && p.precision != FTAFQMC_FP64) return "the path record for derivatives needs FP64 propagation";
   // box, temperature, slices (Sec. "Computational Details", eq. fermiT)
   s.L = std::cbrt(4.0 * PI * p.n_elec / 3.0) * p.rs;
   s.omega = s.L * s.L * s.L;
@@ -78,6 +84,9 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
   s.M = (int)s.nvec.size();
   if (s.M > MAX_M) return "basis larger than the supported maximum of 512 plane waves";
   s.ld = (s.M + 15) / 16 * 16;
+  if (s.ckpt && 2 * s.M > MAX_M) return "derivatives double the system: at most 256 plane waves";
+  s.M2 = 2 * s.M;
+  s.ld2 = (s.M2 + 15) / 16 * 16;
   const double k0 = 2.0 * PI / s.L;
   s.eps.assign(s.ld, 0.0);
   for (int i = 0; i < s.M; ++i) {
@@ -215,11 +224,58 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.rec_status = (int*)take(sizeof(int) * (size_t)W * s.nrec_max);
   d.scratch = (double*)take(sizeof(double) * (size_t)ld * W);
   s.mean = (double2*)take(sizeof(double2) * 4);
+  d.rec_c = nullptr;
+  d.rec_trG = nullptr;
+  if (s.ckpt) {
+    const int ld2 = s.ld2;
+    const size_t mat2 = (size_t)ld2 * ld2;
+    TanDev& t = s.tan;
+    d.rec_c = (double2*)take(sizeof(double2) * (size_t)W * s.n * NQ);
+    d.rec_trG = (double2*)take(sizeof(double2) * (size_t)W * (s.n + 1));
+    t.M2 = s.M2; t.ld2 = ld2;
+    t.dd = d;                                     // tables shared; state and scratch doubled
+    t.dd.M = s.M2; t.dd.ld = ld2;
+    t.dd.Y = (double2*)take(sizeof(double2) * mat2 * W);
+    t.dd.D = (double*)take(sizeof(double) * ld2 * W);
+    t.dd.Dpi = (double*)take(sizeof(double) * ld2 * W);
+    t.dd.perm = (int*)take(sizeof(int) * ld2 * W);
+    t.dd.piv = (int*)take(sizeof(int) * ld2 * W);
+    t.dd.tri = (double2*)take(sizeof(double2) * elim_tri_elems(s.M2) * W);
+    t.dd.E0 = take(sizeof(double2) * mat2 * W);
+    t.dd.E1 = take(sizeof(double2) * mat2 * W);
+    t.dd.aug = (double2*)take(sizeof(double2) * 2 * mat2 * W);
+    t.tstat = (int*)take(sizeof(int) * W);
+    t.lndet_dummy = (double2*)take(sizeof(double2) * W);
+    t.dd.status = t.tstat;
+    t.dd.lndetT = t.lndet_dummy;
+    t.dd.mat_stride = (long long)mat2;
+    t.dd.aug_stride = (long long)2 * mat2;
+    t.Ydn = (double2*)take(sizeof(double2) * mat2 * W);
+    t.Td = (double2*)take(sizeof(double2) * mat2 * W);
+    t.Bcat = (double2*)take(sizeof(double2) * (size_t)ld * ld2 * W);
+    t.Fcat = (double2*)take(sizeof(double2) * (size_t)ld * ld2 * W);
+    t.Gst = (double2*)take(sizeof(double2) * (size_t)ld2 * ld * W);
+    t.dG = (double2*)take(sizeof(double2) * 2 * mat * W);
+    t.exch = (double2*)take(sizeof(double2) * (size_t)ld * W);
+    t.dlnw = (double*)take(sizeof(double) * 2 * W);
+    t.dloc = (double2*)take(sizeof(double2) * 8 * W);
+    t.alive = (int*)take(sizeof(int) * W);
+    t.bc_stride = (long long)ld * ld2;
+    t.gs_stride = (long long)ld2 * ld;
+  }
   s.bytes = off - s.off_begin;
   d.M = M; d.ld = ld; d.NQ = NQ; d.W = W; d.n = s.n; d.grid_dim = s.gdim; d.grid_c0 = s.gc0;
   d.dtau = s.dtau; d.kscale = s.p.kscale; d.e_madelung = s.EM;
   d.mat_stride = (long long)mat;
   d.aug_stride = (long long)2 * mat;
+  if (s.ckpt) {
+    SysDev& dd = s.tan.dd;
+    dd.NQ = NQ; dd.W = W; dd.n = s.n; dd.grid_dim = s.gdim; dd.grid_c0 = s.gc0;
+    dd.dtau = s.dtau; dd.kscale = s.p.kscale; dd.e_madelung = s.EM;
+    dd.idx = d.idx; dd.neg = d.neg; dd.vq = d.vq; dd.sq = d.sq; dd.eps = d.eps; dd.kh = d.kh; dd.lnbt = d.lnbt;
+    dd.qptr = d.qptr; dd.qpair = d.qpair; dd.grid = d.grid; dd.flat = d.flat;
+    dd.rec_c = nullptr; dd.rec_trG = nullptr;
+  }
   return off;
 }
 
@@ -282,7 +338,8 @@ double inv_fact(int j) { double f = 1.0; for (int i = 2; i <= j; ++i) f *= i; re
 // B_k = sum_{r<4} a_{4k+r} V^r and e^V = (((a_deg V^4 + B_top) V^4 + ...) V^4 + B_0).
 // FP64: degree 16 (nb = 4 blocks); mixed: degree 12 (nb = 3).  The V^4 product also writes
 // the top Horner term and the lower blocks, so every Horner step reads one matrix.
-int apply_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
+// Forms B = K e^V K from d.V; *B_out points at the buffer that holds it (E0 or E1).
+int form_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st, void** B_out) {
   SysDev& d = s.dev;
   const bool mixed = s.p.precision == FTAFQMC_MIXED;
   const int prec = mixed ? GEMM_C32 : GEMM_Z64;
@@ -315,6 +372,16 @@ int apply_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
     HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(e, prec, st); }));
     std::swap(cur, nxt);
   }
+  *B_out = cur;
+  return FTAFQMC_OK;
+}
+
+int apply_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
+  SysDev& d = s.dev;
+  const bool mixed = s.p.precision == FTAFQMC_MIXED;
+  void* cur = nullptr;
+  int rc = form_propagator(h, s, st, &cur);
+  if (rc) return rc;
   GemmParams a = gp_base(s);
   a.tile = s.tile_apply;
   a.A = cur; a.B = d.Y; a.C = d.Ynew;
@@ -430,6 +497,116 @@ int step(ftafqmc_ctx* h, HostSys& s, const double2* fields, hipStream_t st) {
     ++s.nrec;
   }
   s.k = k + 1;
+  return FTAFQMC_OK;
+}
+
+// ------------------------------------------------------------ derivative ---
+GemmParams gp_dd(const HostSys& s) {       // 2M x 2M products of the doubled system
+  GemmParams g;
+  std::memset(&g, 0, sizeof(g));
+  g.sA = g.sB = g.sC = g.sP = s.tan.dd.mat_stride;
+  g.lda = g.ldb = g.ldc = g.ldp = s.ld2;
+  g.m = g.n = g.k = s.M2; g.mpad = g.npad = s.ld2; g.W = s.p.n_walkers;
+  g.alpha = 1.0; g.role = 1;
+  return g;
+}
+
+ElimParams ep_dd(const HostSys& s, int pivot, int backsub) {
+  const SysDev& dd = s.tan.dd;
+  ElimParams e;
+  e.aug = dd.aug; e.stride = dd.aug_stride; e.lda = 2 * s.ld2; e.M = s.M2; e.rhs_off = s.ld2; e.nrhs = s.M2;
+  e.W = dd.W; e.pivot = pivot; e.backsub = backsub; e.lndet = nullptr; e.status = dd.status;
+  e.piv = dd.piv; e.ld = s.ld2; e.tri = dd.tri;
+  return e;
+}
+
+// Doubled Green's function (cyclic at slice k, or literal at tau = beta) into Gst / the lambda dG.
+int doubled_greens(ftafqmc_ctx* h, HostSys& s, int k, int literal, hipStream_t st) {
+  TanDev& t = s.tan;
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_cyc_form(s.dev, t, k, literal, st); }));
+  const ElimParams e = ep_dd(s, 1, 1);
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_elim(e, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_cyc_post(s.dev, t, k, literal, st); }));
+  return FTAFQMC_OK;
+}
+
+// One slice of the doubled product: Rd <- [[B, dB], [0, B]] Rd, then the pre-pivoted
+// Cholesky-QR re-factorisation Yd Dd Td with Td <- Ru Td[perm, :].
+int doubled_push(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
+  TanDev& t = s.tan;
+  SysDev& dd = t.dd;
+  const int M = s.M;
+  GemmParams g;
+  std::memset(&g, 0, sizeof(g));
+  g.W = s.p.n_walkers; g.alpha = 1.0; g.role = 1;
+  g.sA = t.bc_stride; g.sB = g.sC = dd.mat_stride;
+  g.lda = s.ld2; g.ldb = g.ldc = s.ld2;
+  g.A = t.Bcat; g.B = dd.Y; g.C = t.Ydn;                         // rows < M: [B | dB] Rd
+  g.m = M; g.n = s.M2; g.k = s.M2; g.mpad = M; g.npad = s.ld2;
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));
+  g.B = dd.Y + (size_t)M * s.ld2; g.C = t.Ydn + (size_t)M * s.ld2;  // rows >= M: B Rd_bottom
+  g.k = M; g.mpad = s.ld2 - M;
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));
+  std::swap(dd.Y, t.Ydn);
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_stab_perm(dd, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_stab_gather(dd, st); }));
+  GemmParams gs = gp_dd(s);
+  gs.A = dd.E0; gs.B = dd.E0; gs.C = dd.aug; gs.opA = 1;
+  gs.sC = dd.aug_stride; gs.ldc = 2 * s.ld2;
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(gs, GEMM_Z64, st); }));
+  const ElimParams e = ep_dd(s, 0, 0);
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_elim(e, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_stab_finish_a(dd, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_permute_rows(t, st); }));
+  GemmParams gt = gp_dd(s);
+  gt.A = dd.E1; gt.B = dd.E0; gt.C = t.Td;
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(gt, GEMM_Z64, st); }));
+  return FTAFQMC_OK;
+}
+
+// Frozen-path derivatives of <E> and <N> at tau = beta in mu and lambda (replays the recorded path).
+int backward(ftafqmc_ctx* h, HostSys& s, const double* cot, double2* jac, double* grad, double2* walker,
+             hipStream_t st) {
+  SysDev& d = s.dev;
+  TanDev& t = s.tan;
+  const int M = s.M, ld = s.ld, W = s.p.n_walkers;
+  HIPCHK(launch_tan_init(d, t, st));
+  for (int k = 0; k < s.n; ++k) {
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_coef_replay(d, k, st); }));
+    void* B = nullptr;
+    int rc = form_propagator(h, s, st, &B);
+    if (rc) return rc;
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_tan_prep(d, t, (const double2*)B, st); }));
+    rc = doubled_greens(h, s, k, 0, st);
+    if (rc) return rc;
+    // [I + Phi | dPhi] = [I + W - W Gc11 | dW - (dW Gc11 + W Gc12)], Fcat = [dW | W]
+    GemmParams g;
+    std::memset(&g, 0, sizeof(g));
+    g.W = W; g.role = 1; g.alpha = -1.0; g.c1 = 1.0;
+    g.sA = g.sP = t.bc_stride; g.sB = t.gs_stride; g.sC = d.aug_stride;
+    g.lda = g.ldp = s.ld2; g.ldb = ld; g.ldc = 2 * ld;
+    g.A = t.Fcat + M; g.P1 = t.Fcat + M; g.B = t.Gst; g.C = d.aug; g.cI = 1.0;
+    g.m = M; g.n = M; g.k = M; g.mpad = M; g.npad = ld;
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));
+    g.A = t.Fcat; g.P1 = t.Fcat; g.C = d.aug + ld; g.cI = 0.0; g.k = s.M2;
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));
+    ElimParams e;
+    e.aug = d.aug; e.stride = d.aug_stride; e.lda = 2 * ld; e.M = M; e.rhs_off = ld; e.nrhs = M;
+    e.W = W; e.pivot = 1; e.backsub = 1; e.lndet = nullptr; e.status = t.tstat;
+    e.piv = d.piv; e.ld = ld; e.tri = d.tri;
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_elim(e, st); }));
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_tan_weight(d, t, k, st); }));
+    rc = doubled_push(h, s, st);
+    if (rc) return rc;
+  }
+  int rc = doubled_greens(h, s, s.n, 1, st);                      // lambda: dG_n
+  if (rc) return rc;
+  GemmParams g = gp_base(s);                                      // mu: dG_n = beta (G G - G)
+  g.role = 1; g.A = d.G; g.B = d.G; g.C = t.dG; g.P1 = d.G; g.alpha = s.beta; g.c1 = -s.beta;
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));
+  for (int dir = 0; dir < 2; ++dir)
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_energy_tangent(d, t, dir, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_tan_mean(d, t, cot, jac, grad, walker, st); }));
   return FTAFQMC_OK;
 }
 
@@ -580,11 +757,16 @@ int ftafqmc_records(ftafqmc_t h, int sys, void* d_trace, double* d_logw, int* h_
   return FTAFQMC_OK;
 }
 
-int ftafqmc_backward(ftafqmc_t h, int sys, int mode, double* d_out, void* stream) {
+int ftafqmc_backward(ftafqmc_t h, int sys, int mode, const double* d_cot, void* d_jac, double* d_grad,
+                     void* d_walker, void* stream) {
   int rc = check_handle(h, sys);
   if (rc) return rc;
-  (void)mode; (void)d_out; (void)stream;
-  return h->set(FTAFQMC_E_UNSUPPORTED, "backward not built yet");
+  if (mode != FTAFQMC_FROZEN_PATH) return h->set(FTAFQMC_E_UNSUPPORTED, "only the frozen-path mode is built");
+  HostSys& s = h->sys[sys];
+  if (!s.ckpt) return h->set(FTAFQMC_E_STATE, "the system was initialised without FTAFQMC_CHECKPOINT");
+  if (s.k != s.n) return h->set(FTAFQMC_E_STATE, "the path has not reached tau = beta");
+  if (d_grad && !d_cot) return h->set(FTAFQMC_E_ARG, "d_grad needs d_cot");
+  return backward(h, s, d_cot, (double2*)d_jac, d_grad, (double2*)d_walker, (hipStream_t)stream);
 }
 
 int ftafqmc_profile(ftafqmc_t h, int enable, double* h_ms, long long* h_count) {

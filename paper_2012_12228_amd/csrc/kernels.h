@@ -79,9 +79,45 @@ struct SysDev {
   double* rec_logw;       // [nrec_max][W]
   int* rec_status;        // [nrec_max][W]
   double* scratch;        // [W][ld] reals
+  double2* rec_c;         // [W][n][NQ] shifted coefficients c_Q of every slice (path record), or null
+  double2* rec_trG;       // [W][n+1] tr G_k of every slice, or null
   long long mat_stride;   // ld*ld
   long long aug_stride;   // ld*2*ld
 };
+
+// Frozen-path tangent state of one system: the doubled product [[R, dR], [0, R]] (2M x 2M,
+// stored with leading dimension ld2) in the form Yd diag(Dd) Td, re-factorised every slice.
+// dd is the doubled system seen as a SysDev (M = 2M, ld = ld2) so that the stabilisation and
+// elimination launchers serve it unchanged.
+struct TanDev {
+  int M2, ld2;
+  SysDev dd;              // Y = Yd, D = Dd, E0/E1/aug/perm/piv/tri/Dpi doubled scratch, status = tstat
+  double2* Ydn;           // [W][ld2][ld2] product before re-factorisation
+  double2* Td;            // [W][ld2][ld2]
+  double2* Bcat;          // [W][ld][ld2] = [B | dB] of the current slice (rows < M)
+  double2* Fcat;          // [W][ld][ld2] = [dB B_T^{-1} | B B_T^{-1} - I]
+  double2* Gst;           // [W][ld2][ld] = cyclic Green's function rows stacked: [Gc_11 ; Gc_12]
+  double2* dG;            // [2][W][ld][ld] dG at tau = beta along mu and lambda
+  double2* exch;          // [W][ld]
+  double* dlnw;           // [W][2]
+  double2* dloc;          // [W][2][4] (dE1, dE2, dE, dN) along mu and lambda
+  int* alive;             // [W]
+  int* tstat;             // [W] 0, or 2 when a doubled factorisation broke down
+  double2* lndet_dummy;   // [W] (the stabilisation records a permutation parity there)
+  long long bc_stride;    // ld*ld2
+  long long gs_stride;    // ld2*ld
+};
+
+hipError_t launch_coef_replay(const SysDev& s, int k, hipStream_t st);             // V from rec_c[k]
+hipError_t launch_tan_init(const SysDev& s, const TanDev& t, hipStream_t st);
+hipError_t launch_tan_prep(const SysDev& s, const TanDev& t, const double2* B, hipStream_t st);
+hipError_t launch_cyc_form(const SysDev& s, const TanDev& t, int k, int literal, hipStream_t st);
+hipError_t launch_cyc_post(const SysDev& s, const TanDev& t, int k, int literal, hipStream_t st);
+hipError_t launch_tan_weight(const SysDev& s, const TanDev& t, int k, hipStream_t st);
+hipError_t launch_permute_rows(const TanDev& t, hipStream_t st);                 // dd.E0 = Td[perm, :]
+hipError_t launch_energy_tangent(const SysDev& s, const TanDev& t, int dir, hipStream_t st);
+hipError_t launch_tan_mean(const SysDev& s, const TanDev& t, const double* cot, double2* jac,
+                           double* grad, double2* walker, hipStream_t st);
 
 hipError_t launch_init_state(const SysDev& s, hipStream_t st);
 hipError_t launch_coef_v(const SysDev& s, const double2* fields, int k, int mixed, hipStream_t st);

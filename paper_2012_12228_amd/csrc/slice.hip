@@ -61,6 +61,7 @@ __global__ __launch_bounds__(NT) void coef_v_kernel(SysDev s, const double2* fie
     c.x -= 2.0 * s.dtau * vqv * rn.x;
     c.y -= 2.0 * s.dtau * vqv * rn.y;
     csh[q] = c;
+    if (s.rec_c) s.rec_c[((long long)w * s.n + k) * s.NQ + q] = c;
     // xbar_A = -2i s (r_q + r_-q), xbar_B = 2 s (r_q - r_-q)
     const double2 sp = make_double2(rq.x + rn.x, rq.y + rn.y), sm = make_double2(rq.x - rn.x, rq.y - rn.y);
     const double2 xa = make_double2(2.0 * sqv * sp.y, -2.0 * sqv * sp.x);
@@ -177,6 +178,12 @@ __global__ __launch_bounds__(NT) void weight_kernel(SysDev s, int k, double sum_
   for (int i = threadIdx.x; i < s.M; i += NT) sdb += log(fmax(fabs(D[i]), 1.0));   // -ln D_b
   sdb = block_sum_256(sdb, red);
   bad = block_sum_256(bad, red);
+  if (s.rec_trG) {                       // tr G_k, kept for the frozen-path derivative in mu
+    double2 tr = zero2();
+    for (int i = threadIdx.x; i < s.M; i += NT) tr = cadd(tr, G[(long long)i * s.ld + i]);
+    tr = block_csum_256(tr, red);
+    if (threadIdx.x == 0) s.rec_trG[(long long)w * (s.n + 1) + k] = tr;
+  }
   if (threadIdx.x != 0) return;
   const double2 lx = s.lndetX[w], lt = s.lndetT[w];
   // ln det(I + A) = ln det X + ln det T - sum ln L_b - sum ln D_b

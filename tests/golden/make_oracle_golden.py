@@ -4,7 +4,10 @@ Calls only oracle/ and the seeded input generator.  For each workload and each
 sampled walker it runs the FP64 oracle over the whole path and keeps, at every
 energy record (each stabilisation boundary and the last slice): E_1, E_2, E, N,
 ln w and the status; plus the final Green's function's diagonal and first rows.
+For the derivative workload it also keeps each sampled walker's frozen-path
+derivatives (d ln w, dE, dN in mu and in lambda) from oracle.tangent.
 Usage: python tests/golden/make_oracle_golden.py [workload ...]
+       python tests/golden/make_oracle_golden.py tangent
 """
 import os
 import sys
@@ -15,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from oracle import ueg, path, energy  # noqa: E402
+from oracle import ueg, path, energy, tangent  # noqa: E402
 import synthinputs as si  # noqa: E402
 
 SAMPLES = {
@@ -25,6 +28,7 @@ SAMPLES = {
     "ueg_n114_m485": {0: [0, 511]},
 }
 G_ROWS = 8
+TANGENT_SAMPLES = {"ueg_n38_m123": [0, 63, 127]}
 
 
 def one(args):
@@ -48,6 +52,37 @@ def one(args):
     )
 
 
+def one_tangent(args):
+    name, w = args
+    from threadpoolctl import threadpool_limits
+    sd = si.WORKLOADS[name]["systems"][0]
+    s = ueg.UEGSystem(sd["n_elec"], sd["rs"], sd["theta"], sd["nmax2"], sd["dtau"], stab_every=sd["stab_every"])
+    z = si.walker_fields(si.system_seed(name, 0), w, s.n_slices, s.NQ)
+    with threadpool_limits(2):
+        fwd, tans = tangent.walker_tangents(s, z)
+    out = dict(logw=fwd["logw"], status=fwd["status"], E=fwd["E"]["E"], N=fwd["E"]["N"])
+    for p, t in tans.items():
+        for k in ("dlogw", "dE", "dN", "dE1", "dE2"):
+            out["%s_%s" % (p, k)] = t[k]
+        out[p + "_dG_rows"] = t["dG"][:G_ROWS].copy()
+    return out
+
+
+def main_tangent():
+    jobs = [(n, w) for n, ws in TANGENT_SAMPLES.items() for w in ws]
+    with ProcessPoolExecutor(max_workers=min(4, len(jobs))) as ex:
+        results = list(ex.map(one_tangent, jobs))
+    for n in TANGENT_SAMPLES:
+        arrays = {}
+        for (jn, w), r in zip(jobs, results):
+            if jn == n:
+                for k, v in r.items():
+                    arrays["w%d_%s" % (w, k)] = np.asarray(v)
+        fn = os.path.join(HERE, "oracle_tangent_%s.npz" % n)
+        np.savez_compressed(fn, **arrays)
+        print("wrote", fn, os.path.getsize(fn), "bytes")
+
+
 def main(names):
     jobs = [(n, sidx, w) for n in names for sidx, ws in SAMPLES[n].items() for w in ws]
     with ProcessPoolExecutor(max_workers=min(4, len(jobs))) as ex:
@@ -67,4 +102,7 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or list(SAMPLES))
+    if sys.argv[1:] == ["tangent"]:
+        main_tangent()
+    else:
+        main(sys.argv[1:] or list(SAMPLES))

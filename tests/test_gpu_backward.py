@@ -1,0 +1,180 @@
+"""Frozen-path derivatives on the GPU (ftafqmc_backward, through the C ABI) against the oracle.
+
+The oracle's tangent (oracle.tangent, pinned by central differences, closed forms and
+80-digit products in test_oracle_tangent.py) runs on the same seeded fields.  Both sides
+differentiate their own recorded path; the two paths agree to the FP64 parity bar, and so
+must the derivatives:
+  per walker  d ln w, dE, dN along mu and lambda: |gpu - oracle| <= 1e-10 max(1, |oracle|);
+  ensemble    d<E>, d<N> along mu and lambda: the same bound.
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ueg, path, tangent  # noqa: E402
+import synthinputs as si  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+REL = 1e-10
+
+
+def _F():
+    import paper_2012_12228_amd as F
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F.load_library()
+    return F
+
+
+def close(got, want, rel=REL):
+    return abs(got - want) <= rel * max(1.0, abs(want))
+
+
+def oracle_system(sd):
+    return ueg.UEGSystem(sd["n_elec"], sd["rs"], sd["theta"], sd["nmax2"], sd["dtau"],
+                         stab_every=sd.get("stab_every", 10), mu=sd.get("mu"), kscale=sd.get("kscale", 1.0))
+
+
+def gpu_backward(F, sd, flds):
+    sd = dict(sd, precision=F.FTAFQMC_FP64, flags=F.FTAFQMC_CHECKPOINT)
+    ctx = F.Context(sd)
+    ctx.propagate(torch.from_numpy(np.ascontiguousarray(flds)).cuda())
+    e = ctx.energy()
+    b = ctx.backward(cot=[0.7, -1.3])
+    torch.cuda.synchronize()
+    out = dict(local=e["local"].cpu().numpy(), mean=e["mean"].cpu().numpy(), logw=e["logw"].cpu().numpy(),
+               status=e["status"].cpu().numpy(), jac=b["jac"].cpu().numpy(), grad=b["grad"].cpu().numpy(),
+               walker=b["walker"].cpu().numpy())
+    ctx.close()
+    return out
+
+
+def check_against_oracle(s, flds, g, label):
+    W = flds.shape[0]
+    lw, st, E, N = [], [], [], []
+    d = {p: dict(dlogw=[], dE=[], dN=[]) for p in ("mu", "kscale")}
+    for w in range(W):
+        fwd, tans = tangent.walker_tangents(s, flds[w])
+        lw.append(fwd["logw"]); st.append(fwd["status"]); E.append(fwd["E"]["E"]); N.append(fwd["E"]["N"])
+        assert g["status"][w] == fwd["status"], (label, w)
+        for j, p in enumerate(("mu", "kscale")):
+            t = tans[p]
+            for k in ("dlogw", "dE", "dN"):
+                d[p][k].append(t[k])
+            if fwd["status"] != path.ALIVE:
+                continue
+            gw = g["walker"][w, 3 * j:3 * j + 3]
+            assert close(gw[0].real, t["dlogw"]), (label, w, p, "dlogw", gw[0], t["dlogw"])
+            assert close(gw[1], t["dE"]), (label, w, p, "dE", gw[1], t["dE"])
+            assert close(gw[2], t["dN"]), (label, w, p, "dN", gw[2], t["dN"])
+    for j, p in enumerate(("mu", "kscale")):
+        _, dmE = tangent.ensemble_tangent(np.array(E), np.array(d[p]["dE"]), np.array(lw), np.array(d[p]["dlogw"]), st)
+        _, dmN = tangent.ensemble_tangent(np.array(N), np.array(d[p]["dN"]), np.array(lw), np.array(d[p]["dlogw"]), st)
+        assert close(g["jac"][2 * j], dmE), (label, p, g["jac"][2 * j], dmE)
+        assert close(g["jac"][2 * j + 1], dmN), (label, p, g["jac"][2 * j + 1], dmN)
+    # grad = cot . Re(jac)
+    assert g["grad"][0] == pytest.approx(0.7 * g["jac"][0].real - 1.3 * g["jac"][1].real, rel=1e-14, abs=1e-14)
+    assert g["grad"][1] == pytest.approx(0.7 * g["jac"][2].real - 1.3 * g["jac"][3].real, rel=1e-14, abs=1e-14)
+
+
+def test_backward_m19_all_walkers():
+    F = _F()
+    sd = si.WORKLOADS["ueg_n14_m19"]["systems"][0]
+    s = oracle_system(sd)
+    flds = si.fields(si.system_seed("ueg_n14_m19", 0), sd["walkers"], s.n_slices, s.NQ)
+    check_against_oracle(s, flds, gpu_backward(F, sd, flds), "m19")
+
+
+def test_backward_ragged_m57_kscale_mu():
+    """M = 57 (ragged against the 16/32/64 tiles; 2M = 114), lambda != 1, explicit mu."""
+    F = _F()
+    sd = dict(n_elec=38, rs=1.0, theta=0.25, nmax2=5, dtau=0.05, stab_every=4, walkers=6, kscale=0.9, mu=1.5)
+    s = oracle_system(sd)
+    flds = si.fields(4242, sd["walkers"], s.n_slices, s.NQ)
+    check_against_oracle(s, flds, gpu_backward(F, sd, flds), "m57")
+
+
+def test_backward_at_cond_1e30():
+    """M = 7, Theta = 0.035: the product spans ~30 decades; the doubled factorisation must hold."""
+    F = _F()
+    sd = dict(n_elec=2, rs=0.5, theta=0.035, nmax2=1, dtau=0.05, stab_every=1, walkers=8)
+    s = oracle_system(sd)
+    flds = si.fields(5, sd["walkers"], s.n_slices, s.NQ)
+    check_against_oracle(s, flds, gpu_backward(F, sd, flds), "m7")
+
+
+def test_backward_m123_full_size_sampled():
+    """The derivative workload at full size (M = 123, n = 174, 128 walkers): sampled walkers
+    against stored oracle derivatives, and the ensemble reduction against the GPU's own
+    per-walker values."""
+    F = _F()
+    name = "ueg_n38_m123"
+    sd = si.WORKLOADS[name]["systems"][0]
+    s = oracle_system(sd)
+    W = sd["walkers"]
+    flds = si.fields(si.system_seed(name, 0), W, s.n_slices, s.NQ)
+    g = gpu_backward(F, sd, flds)
+    gold = np.load(os.path.join(GOLDEN, "oracle_tangent_%s.npz" % name))
+    ws = sorted({int(k.split("_")[0][1:]) for k in gold.files})
+    assert ws
+    for w in ws:
+        assert g["status"][w] == int(gold["w%d_status" % w])
+        if int(gold["w%d_status" % w]) != path.ALIVE:
+            continue
+        assert close(g["logw"][w], float(gold["w%d_logw" % w]))
+        for j, p in enumerate(("mu", "kscale")):
+            gw = g["walker"][w, 3 * j:3 * j + 3]
+            assert close(gw[0].real, float(gold["w%d_%s_dlogw" % (w, p)])), (w, p)
+            assert close(gw[1], complex(gold["w%d_%s_dE" % (w, p)])), (w, p, gw[1], gold["w%d_%s_dE" % (w, p)])
+            assert close(gw[2], complex(gold["w%d_%s_dN" % (w, p)])), (w, p)
+    wk = g["walker"]
+    for j in range(2):
+        _, dmE = tangent.ensemble_tangent(g["local"][:, 2], wk[:, 3 * j + 1], g["logw"], wk[:, 3 * j].real, g["status"])
+        _, dmN = tangent.ensemble_tangent(g["local"][:, 3], wk[:, 3 * j + 2], g["logw"], wk[:, 3 * j].real, g["status"])
+        assert close(g["jac"][2 * j], dmE, 1e-12)
+        assert close(g["jac"][2 * j + 1], dmN, 1e-12)
+
+
+def test_backward_state_errors():
+    F = _F()
+    sd = dict(si.WORKLOADS["ueg_n14_m19"]["systems"][0], walkers=4)
+    s = oracle_system(sd)
+    flds = torch.from_numpy(si.fields(1, 4, s.n_slices, s.NQ)).cuda()
+    ctx = F.Context(dict(sd, flags=0))
+    ctx.propagate(flds)
+    with pytest.raises(RuntimeError, match="E_STATE"):
+        ctx.backward()
+    ctx.close()
+    ctx = F.Context(dict(sd, flags=F.FTAFQMC_CHECKPOINT))
+    ctx.propagate(flds, n_slices=3)
+    with pytest.raises(RuntimeError, match="E_STATE"):
+        ctx.backward()
+    ctx.close()
+    with pytest.raises(RuntimeError, match="E_ARG"):
+        F.Context(dict(sd, flags=F.FTAFQMC_CHECKPOINT, precision=F.FTAFQMC_MIXED))
+
+
+def test_autograd_function_contracts_the_cotangents():
+    """FrozenPathMeans: torch.autograd gradients equal the contraction of ftafqmc_backward's
+    Jacobian with the cotangents of (Re<E>, Re<N>)."""
+    F = _F()
+    sd = dict(si.WORKLOADS["ueg_n14_m19"]["systems"][0], walkers=16)
+    s = oracle_system(sd)
+    flds = torch.from_numpy(si.fields(77, 16, s.n_slices, s.NQ)).cuda()
+    mu = torch.tensor(s.mu_T + 0.1, dtype=torch.float64, device="cuda", requires_grad=True)
+    lam = torch.tensor(1.05, dtype=torch.float64, device="cuda", requires_grad=True)
+    E, N = F.FrozenPathMeans.apply(mu, lam, sd, flds)
+    loss = 2.0 * E - 0.5 * N
+    gmu, glam = torch.autograd.grad(loss, (mu, lam))
+    ctx = F.Context(dict(sd, mu=float(mu.detach()), kscale=float(lam.detach()), flags=F.FTAFQMC_CHECKPOINT))
+    ctx.propagate(flds)
+    ctx.energy()
+    jac = ctx.backward()["jac"].cpu().numpy()
+    ctx.close()
+    assert float(gmu) == pytest.approx(2.0 * jac[0].real - 0.5 * jac[1].real, rel=1e-13)
+    assert float(glam) == pytest.approx(2.0 * jac[2].real - 0.5 * jac[3].real, rel=1e-13)
