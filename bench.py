@@ -115,6 +115,38 @@ def run_precision(F, torch, systems, fields, steps, warmup):
     return ctx, out, energies, status
 
 
+def time_backward(F, torch, workload="ueg_n38_m123"):
+    """Wall time of one frozen-path derivative pass (ftafqmc_backward) on the derivative
+    workload, beside the FP64 forward path it differentiates (both with inputs in HBM)."""
+    wl = si.WORKLOADS[workload]
+    sd = dict(wl["systems"][0], precision=0, flags=F.FTAFQMC_CHECKPOINT)
+    ctx = F.Context(sd)
+    inf = ctx.info()
+    f = torch.from_numpy(si.fields(si.system_seed(workload, 0), sd["walkers"], inf["n_slices"], inf["n_q"])).cuda()
+    ctx.propagate(f)
+    ctx.energy()
+    ctx.backward()                                   # warm-up of both passes
+    torch.cuda.synchronize()
+    ctx.reset()
+    t0 = time.perf_counter()
+    ctx.propagate(f)
+    ctx.energy()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.profile(True)
+    b = ctx.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    prof = ctx.profile(False)
+    jac = b["jac"].cpu().numpy()
+    ctx.close()
+    ws = inf["n_walkers"] * inf["n_slices"]
+    return {"workload": workload, "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
+            "walker_slices_per_s_backward": ws / (t2 - t1),
+            "profile_ms": {k: v[0] for k, v in prof.items() if v[1]},
+            "d<E>/dmu": jac[0].real, "d<N>/dmu": jac[1].real, "d<E>/dlambda": jac[2].real, "d<N>/dlambda": jac[3].real}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +155,7 @@ def main():
     ap.add_argument("--workload", default="ueg_n66_m171")
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-backward", action="store_true", help="skip the derivative-pass timing")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -197,6 +230,9 @@ def main():
                      "avg_launch_ms": r["gemm_avg_ms"]},
         "fp64": results.get("fp64"), "mixed": results.get("mixed"),
     }
+    if not args.no_backward:
+        torch.cuda.empty_cache()
+        line["backward"] = time_backward(F, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(line))
