@@ -102,6 +102,7 @@ typedef struct {
   double beta, dtau, L, omega, mu_T, mu, e_madelung;
   int gemm_tile_chain;   /* propagator GEMM tile shape chosen by the start-up autotuner */
   int gemm_tile_apply;   /* tile shape of the product that applies e^V */
+  int gemm_tile_shapes;  /* number of tile shapes built (valid values of FTAFQMC_GEMM_TILE) */
 } ftafqmc_info;
 
 /* Bytes of device workspace needed for the n_sys systems listed in p[0..n_sys-1]

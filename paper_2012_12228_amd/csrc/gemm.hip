@@ -235,6 +235,10 @@ typedef Tile<64, 128, 16, 32, 64> T64x128;   // 4 waves of 32 x 64
 typedef Tile<128, 64, 16, 64, 32> T128x64;   // 4 waves of 64 x 32
 typedef Tile<32, 64, 16, 16, 32> T32x64;     // 4 waves of 16 x 32
 typedef Tile<32, 32, 16, 16, 16> T32x32;     // 4 waves of 16 x 16
+// 16 waves of small per-wave tiles: few registers per wave (high occupancy) while the
+// 64-row / 64- or 128-column workgroup tile still shares every LDS-staged operand.
+typedef Tile<64, 64, 16, 16, 16> T64x64w16;
+typedef Tile<64, 128, 16, 16, 32> T64x128w16;
 
 template <typename TA, typename TB, typename TC, typename ACC, int ROLE, typename TL>
 hipError_t launch_tile(GemmParams p, hipStream_t s) {
@@ -254,13 +258,15 @@ hipError_t launch_shape(const GemmParams& p, hipStream_t s) {
     case 2: return launch_tile<TA, TB, TC, ACC, ROLE, T128x64>(p, s);
     case 3: return launch_tile<TA, TB, TC, ACC, ROLE, T32x64>(p, s);
     case 4: return launch_tile<TA, TB, TC, ACC, ROLE, T32x32>(p, s);
+    case 5: return launch_tile<TA, TB, TC, ACC, ROLE, T64x64w16>(p, s);
+    case 6: return launch_tile<TA, TB, TC, ACC, ROLE, T64x128w16>(p, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
-int gemm_tile_count() { return 5; }
+int gemm_tile_count() { return 7; }
 
 hipError_t launch_zgemm(const GemmParams& p, int prec, hipStream_t s) {
   if (p.m <= 0 || p.n <= 0) return hipSuccess;
@@ -268,8 +274,8 @@ hipError_t launch_zgemm(const GemmParams& p, int prec, hipStream_t s) {
   switch (prec * 2 + (p.role ? 1 : 0)) {
     case 2 * GEMM_Z64:       // complex128 in and out, FP64 MFMA (propagator chain)
       return launch_shape<double2, double2, double2, double, 0>(p, s);
-    case 2 * GEMM_Z64 + 1:   // the same for the dense linear algebra (64 x 64 tiles)
-      return launch_tile<double2, double2, double2, double, 1, T64x64>(p, s);
+    case 2 * GEMM_Z64 + 1:   // the same for the dense linear algebra (64 x 64 tiles, 16 waves)
+      return launch_tile<double2, double2, double2, double, 1, T64x64w16>(p, s);
     case 2 * GEMM_C32:       // complex64 in and out, FP32 MFMA
       return launch_shape<float2, float2, float2, float, 0>(p, s);
     case 2 * GEMM_C32_Z64B:  // complex64 A, complex128 B (rounded to complex64), complex128 out

@@ -689,6 +689,7 @@ int ftafqmc_query(ftafqmc_t h, int sys, ftafqmc_info* out) {
   out->beta = s.beta; out->dtau = s.dtau; out->L = s.L; out->omega = s.omega;
   out->mu_T = s.muT; out->mu = s.mu; out->e_madelung = s.EM;
   out->gemm_tile_chain = s.tile_chain; out->gemm_tile_apply = s.tile_apply;
+  out->gemm_tile_shapes = gemm_tile_count();
   return FTAFQMC_OK;
 }
 
