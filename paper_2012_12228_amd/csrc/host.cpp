@@ -268,6 +268,7 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.dtau = s.dtau; d.kscale = s.p.kscale; d.e_madelung = s.EM;
   d.mat_stride = (long long)mat;
   d.aug_stride = (long long)2 * mat;
+  d.w_off = 0; d.rec_W = W;
   if (s.ckpt) {
     SysDev& dd = s.tan.dd;
     dd.NQ = NQ; dd.W = W; dd.n = s.n; dd.grid_dim = s.gdim; dd.grid_c0 = s.gc0;
@@ -275,8 +276,35 @@ size_t layout(HostSys& s, char* base, size_t off) {
     dd.idx = d.idx; dd.neg = d.neg; dd.vq = d.vq; dd.sq = d.sq; dd.eps = d.eps; dd.kh = d.kh; dd.lnbt = d.lnbt;
     dd.qptr = d.qptr; dd.qpair = d.qpair; dd.grid = d.grid; dd.flat = d.flat;
     dd.rec_c = nullptr; dd.rec_trG = nullptr;
+    dd.w_off = 0; dd.rec_W = W;
   }
   return off;
+}
+
+// The walkers [w0, w0 + nw) of a system as a SysDev of their own: every per-walker array is
+// offset by w0 walkers; the tables and the record arrays (indexed through w_off, rec_W) are shared.
+SysDev walker_view(const HostSys& s, int w0, int nw) {
+  SysDev v = s.dev;
+  const long long mat = v.mat_stride;
+  const size_t velem = s.p.precision == FTAFQMC_MIXED ? sizeof(float2) : sizeof(double2);
+  const long long ld = s.ld, w = w0;
+  v.Y += w * mat; v.Ti += w * mat; v.G += w * mat; v.Ynew += w * mat;
+  v.aug += w * v.aug_stride;
+  auto offv = [&](void* q, size_t bytes) { return q ? (void*)((char*)q + (size_t)w * bytes) : nullptr; };
+  v.V = offv(v.V, velem * mat); v.V2 = offv(v.V2, velem * mat);
+  v.V3 = offv(v.V3, velem * mat); v.V4 = offv(v.V4, velem * mat);
+  for (int k = 0; k < 3; ++k) v.Bk[k] = offv(v.Bk[k], velem * mat);
+  v.E0 = offv(v.E0, sizeof(double2) * mat); v.E1 = offv(v.E1, sizeof(double2) * mat);
+  v.D += w * ld; v.Dpi += w * ld; v.perm += w * ld; v.piv += w * ld;
+  v.tri += w * (long long)elim_tri_elems(s.M);
+  v.r += w * s.NQ;
+  v.expo += w; v.ell += w; v.lndetT += w; v.lndetX += w; v.logw += w; v.status += w;
+  v.slice_lnS += w * s.n; v.slice_theta += w * s.n;
+  v.exch += w * ld; v.local += w * 4; v.scratch += w * ld;
+  if (v.rec_c) v.rec_c += w * s.n * (long long)s.NQ;
+  if (v.rec_trG) v.rec_trG += w * (s.n + 1);
+  v.W = nw; v.w_off = w0; v.rec_W = s.p.n_walkers;
+  return v;
 }
 
 }  // namespace
@@ -290,6 +318,9 @@ struct ftafqmc_ctx {
   std::string err;
   bool prof = false;
   std::vector<ProfEvent> events;
+  int groups = 2;                       // walker groups per system in ftafqmc_propagate
+  hipStream_t side = nullptr;           // second stream of the walker groups (default priority)
+  hipEvent_t fork = nullptr, join = nullptr;
   int set(int code, const std::string& m) { err = m; return code; }
 };
 
@@ -322,12 +353,12 @@ double sum_ln_lb(const HostSys& s, int k) {
   return a;
 }
 
-GemmParams gp_base(const HostSys& s) {
+GemmParams gp_base(const HostSys& s, const SysDev& d) {
   GemmParams g;
   std::memset(&g, 0, sizeof(g));
-  g.sA = g.sB = g.sC = g.sP = s.dev.mat_stride;
+  g.sA = g.sB = g.sC = g.sP = d.mat_stride;
   g.lda = g.ldb = g.ldc = g.ldp = s.ld;
-  g.m = g.n = g.k = s.M; g.mpad = g.npad = s.ld; g.W = s.p.n_walkers;
+  g.m = g.n = g.k = s.M; g.mpad = g.npad = s.ld; g.W = d.W;
   g.alpha = 1.0;
   return g;
 }
@@ -339,13 +370,12 @@ double inv_fact(int j) { double f = 1.0; for (int i = 2; i <= j; ++i) f *= i; re
 // FP64: degree 16 (nb = 4 blocks); mixed: degree 12 (nb = 3).  The V^4 product also writes
 // the top Horner term and the lower blocks, so every Horner step reads one matrix.
 // Forms B = K e^V K from d.V; *B_out points at the buffer that holds it (E0 or E1).
-int form_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st, void** B_out) {
-  SysDev& d = s.dev;
+int form_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st, void** B_out) {
   const bool mixed = s.p.precision == FTAFQMC_MIXED;
   const int prec = mixed ? GEMM_C32 : GEMM_Z64;
   const int nb = mixed ? 3 : 4;
   const int deg = 4 * nb;
-  GemmParams g = gp_base(s);
+  GemmParams g = gp_base(s, d);
   g.tile = s.tile_chain;
   g.A = d.V; g.B = d.V; g.C = d.V2;
   HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));   // V^2
@@ -364,7 +394,7 @@ int form_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st, void** B_out) {
   void* cur = d.E0;
   void* nxt = d.E1;
   for (int k = nb - 2; k >= 0; --k) {
-    GemmParams e = gp_base(s);
+    GemmParams e = gp_base(s, d);
     e.tile = s.tile_chain;
     e.A = cur; e.B = d.V4; e.C = nxt;
     e.P1 = d.Bk[k]; e.c1 = 1.0;
@@ -376,13 +406,12 @@ int form_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st, void** B_out) {
   return FTAFQMC_OK;
 }
 
-int apply_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
-  SysDev& d = s.dev;
+int apply_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st) {
   const bool mixed = s.p.precision == FTAFQMC_MIXED;
   void* cur = nullptr;
-  int rc = form_propagator(h, s, st, &cur);
+  int rc = form_propagator(h, s, d, st, &cur);
   if (rc) return rc;
-  GemmParams a = gp_base(s);
+  GemmParams a = gp_base(s, d);
   a.tile = s.tile_apply;
   a.A = cur; a.B = d.Y; a.C = d.Ynew;
   HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(a, mixed ? GEMM_C32_Z64B : GEMM_Z64, st); }));
@@ -391,11 +420,10 @@ int apply_propagator(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
 }
 
 // Pre-pivoted QR of Y diag(D) by one Cholesky-QR pass; updates Y, D and Ti = T^{-1}.
-int stabilise(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
-  SysDev& d = s.dev;
+int stabilise(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st) {
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_perm(d, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_gather(d, st); }));
-  GemmParams g = gp_base(s);
+  GemmParams g = gp_base(s, d);
   g.A = d.E0; g.B = d.E0; g.C = d.aug; g.opA = 1; g.role = 1;
   g.sC = d.aug_stride; g.ldc = 2 * s.ld;
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));  // S = E0^H E0 into the left block
@@ -412,8 +440,7 @@ int stabilise(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
 }
 
 // G_k, ln det(I + A_k), the weight update of the slice that ended at k, r_Q of G_k.
-int greens(ftafqmc_ctx* h, HostSys& s, int k, int init, hipStream_t st) {
-  SysDev& d = s.dev;
+int greens(ftafqmc_ctx* h, HostSys& s, SysDev& d, int k, int init, hipStream_t st) {
   HIPCHK(timed(h, FTAFQMC_PROF_GREENS, st, [&] { return launch_greens_form(d, k, st); }));
   ElimParams e;
   e.aug = d.aug; e.stride = d.aug_stride; e.lda = 2 * s.ld; e.M = s.M; e.rhs_off = s.ld; e.nrhs = s.M;
@@ -448,7 +475,7 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
     float best = 1e30f;
     int besti = 0;
     for (int t = 0; t < gemm_tile_count(); ++t) {
-      GemmParams g = gp_base(s);
+      GemmParams g = gp_base(s, d);
       g.tile = t;
       int prec = mixed ? GEMM_C32 : GEMM_Z64;
       if (kind == 0) { g.A = d.V; g.B = d.V; g.C = d.V2; }
@@ -472,7 +499,7 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
 
 int reset_sys(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   HIPCHK(launch_init_state(s.dev, st));
-  int rc = greens(h, s, 0, 1, st);
+  int rc = greens(h, s, s.dev, 0, 1, st);
   if (rc) return rc;
   s.k = 0;
   s.nrec = 0;
@@ -480,24 +507,51 @@ int reset_sys(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   return FTAFQMC_OK;
 }
 
-int step(ftafqmc_ctx* h, HostSys& s, const double2* fields, hipStream_t st) {
-  const int k = s.k;
+// One slice k -> k+1 for the walkers of view d (fields of those walkers), on stream st.
+int slice_step(ftafqmc_ctx* h, HostSys& s, SysDev& d, const double2* fields, int k, int rec, hipStream_t st) {
   const int mixed = s.p.precision == FTAFQMC_MIXED;
-  HIPCHK(timed(h, FTAFQMC_PROF_COEF, st, [&] { return launch_coef_v(s.dev, fields, k, mixed, st); }));
-  int rc = apply_propagator(h, s, st);
+  HIPCHK(timed(h, FTAFQMC_PROF_COEF, st, [&] { return launch_coef_v(d, fields, k, mixed, st); }));
+  int rc = apply_propagator(h, s, d, st);
   if (rc) return rc;
+  if (rec >= 0) { rc = stabilise(h, s, d, st); if (rc) return rc; }
+  rc = greens(h, s, d, k + 1, 0, st);
+  if (rc) return rc;
+  if (rec >= 0) HIPCHK(timed(h, FTAFQMC_PROF_ENERGY, st, [&] { return launch_energy(d, rec, st); }));
+  return FTAFQMC_OK;
+}
+
+// One slice for every walker of system s.  The walkers are split into groups that run on the
+// caller's stream and the handle's side stream: the elimination of one group is latency bound
+// (a workgroup per walker walks its pivot columns one by one) and overlaps with the GEMMs of the
+// other.  Walkers are independent, so the results do not depend on the split.
+int step(ftafqmc_ctx* h, HostSys& s, std::vector<SysDev>& views, const double2* fields, hipStream_t st) {
+  const int k = s.k;
   const bool boundary = ((k + 1) % s.p.stab_every == 0) || (k + 1 == s.n);
-  if (boundary) { rc = stabilise(h, s, st); if (rc) return rc; }
-  rc = greens(h, s, k + 1, 0, st);
-  if (rc) return rc;
+  const int rec = boundary ? s.nrec : -1;
+  for (size_t g = 0; g < views.size(); ++g) {
+    SysDev& d = views[g];
+    const double2* f = fields + (long long)d.w_off * s.n * s.NQ;
+    int rc = slice_step(h, s, d, f, k, rec, g == 0 ? st : h->side);
+    if (rc) return rc;
+  }
+  std::swap(s.dev.Y, s.dev.Ynew);           // every view swapped its own pointers once
   if (boundary) {
-    const int rec = s.nrec;
-    HIPCHK(timed(h, FTAFQMC_PROF_ENERGY, st, [&] { return launch_energy(s.dev, rec, st); }));
     s.rec_slice.push_back(k + 1);
     ++s.nrec;
   }
   s.k = k + 1;
   return FTAFQMC_OK;
+}
+
+// Walker groups of a system for the two streams (one group for small batches).
+std::vector<SysDev> make_views(const HostSys& s, int ngroups) {
+  const int W = s.p.n_walkers;
+  std::vector<SysDev> v;
+  if (ngroups < 2 || W < 16) { v.push_back(walker_view(s, 0, W)); return v; }
+  const int n0 = ((W / 2 + 7) / 8) * 8;
+  v.push_back(walker_view(s, 0, n0));
+  v.push_back(walker_view(s, n0, W - n0));
+  return v;
 }
 
 // ------------------------------------------------------------ derivative ---
@@ -574,7 +628,7 @@ int backward(ftafqmc_ctx* h, HostSys& s, const double* cot, double2* jac, double
   for (int k = 0; k < s.n; ++k) {
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_coef_replay(d, k, st); }));
     void* B = nullptr;
-    int rc = form_propagator(h, s, st, &B);
+    int rc = form_propagator(h, s, d, st, &B);
     if (rc) return rc;
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_tan_prep(d, t, (const double2*)B, st); }));
     rc = doubled_greens(h, s, k, 0, st);
@@ -601,7 +655,7 @@ int backward(ftafqmc_ctx* h, HostSys& s, const double* cot, double2* jac, double
   }
   int rc = doubled_greens(h, s, s.n, 1, st);                      // lambda: dG_n
   if (rc) return rc;
-  GemmParams g = gp_base(s);                                      // mu: dG_n = beta (G G - G)
+  GemmParams g = gp_base(s, d);                                      // mu: dG_n = beta (G G - G)
   g.role = 1; g.A = d.G; g.B = d.G; g.C = t.dG; g.P1 = d.G; g.alpha = s.beta; g.c1 = -s.beta;
   HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));
   for (int dir = 0; dir < 2; ++dir)
@@ -646,6 +700,13 @@ int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size
     off = layout(h->sys[i], nullptr, off);
   }
   if (off > ws_bytes) { delete h; return FTAFQMC_E_ARG; }
+  if (const char* env = std::getenv("FTAFQMC_WALKER_GROUPS")) h->groups = std::atoi(env) >= 2 ? 2 : 1;
+  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->join, hipEventDisableTiming) != hipSuccess) {
+    ftafqmc_destroy(h);
+    return FTAFQMC_E_HIP;
+  }
   h->ws = (char*)d_workspace;
   h->ws_bytes = ws_bytes;
   hipStream_t st = (hipStream_t)stream;
@@ -671,9 +732,9 @@ int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size
     if (e == hipSuccess) e = up(d.flat, s.flat.data(), sizeof(int) * s.M);
     // the host tables are no longer needed once the copies have completed
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) { delete h; return FTAFQMC_E_HIP; }
-    if (autotune_gemm(h, s, st) != FTAFQMC_OK) { delete h; return FTAFQMC_E_HIP; }
-    if (reset_sys(h, s, st) != FTAFQMC_OK) { delete h; return FTAFQMC_E_HIP; }
+    if (e != hipSuccess) { ftafqmc_destroy(h); return FTAFQMC_E_HIP; }
+    if (autotune_gemm(h, s, st) != FTAFQMC_OK) { ftafqmc_destroy(h); return FTAFQMC_E_HIP; }
+    if (reset_sys(h, s, st) != FTAFQMC_OK) { ftafqmc_destroy(h); return FTAFQMC_E_HIP; }
   }
   *out = h;
   return FTAFQMC_OK;
@@ -708,18 +769,26 @@ int ftafqmc_propagate(ftafqmc_t h, const void* const* d_fields, int n_slices, vo
   for (size_t i = 0; i < h->sys.size(); ++i)
     if (!d_fields[i]) return h->set(FTAFQMC_E_ARG, "null fields pointer");
   hipStream_t st = (hipStream_t)stream;
-  for (int j = 0; j < n_slices; ++j) {
+  std::vector<std::vector<SysDev>> views;
+  for (auto& s : h->sys) views.push_back(make_views(s, h->groups));
+  // the side stream starts after the work already queued on the caller's stream, and the
+  // caller's stream continues only after the side stream's work (fork / join)
+  HIPCHK(hipEventRecord(h->fork, st));
+  HIPCHK(hipStreamWaitEvent(h->side, h->fork, 0));
+  int rc = FTAFQMC_OK;
+  for (int j = 0; j < n_slices && rc == FTAFQMC_OK; ++j) {
     bool any = false;
-    for (size_t i = 0; i < h->sys.size(); ++i) {
+    for (size_t i = 0; i < h->sys.size() && rc == FTAFQMC_OK; ++i) {
       HostSys& s = h->sys[i];
       if (s.k >= s.n) continue;
       any = true;
-      int rc = step(h, s, (const double2*)d_fields[i], st);
-      if (rc) return rc;
+      rc = step(h, s, views[i], (const double2*)d_fields[i], st);
     }
     if (!any) break;
   }
-  return FTAFQMC_OK;
+  HIPCHK(hipEventRecord(h->join, h->side));
+  HIPCHK(hipStreamWaitEvent(st, h->join, 0));
+  return rc;
 }
 
 int ftafqmc_greens(ftafqmc_t h, int sys, void* d_G, int dtype, void* stream) {
@@ -799,6 +868,9 @@ const char* ftafqmc_last_error(ftafqmc_t h) { return h ? h->err.c_str() : "null 
 void ftafqmc_destroy(ftafqmc_t h) {
   if (!h) return;
   for (auto& ev : h->events) { (void)hipEventDestroy(ev.a); (void)hipEventDestroy(ev.b); }
+  if (h->side) { (void)hipStreamSynchronize(h->side); (void)hipStreamDestroy(h->side); }
+  if (h->fork) (void)hipEventDestroy(h->fork);
+  if (h->join) (void)hipEventDestroy(h->join);
   delete h;
 }
 

@@ -81,6 +81,7 @@ struct SysDev {
   double* scratch;        // [W][ld] reals
   double2* rec_c;         // [W][n][NQ] shifted coefficients c_Q of every slice (path record), or null
   double2* rec_trG;       // [W][n+1] tr G_k of every slice, or null
+  int w_off, rec_W;       // walker offset of this view and walker count of the record arrays
   long long mat_stride;   // ld*ld
   long long aug_stride;   // ld*2*ld
 };

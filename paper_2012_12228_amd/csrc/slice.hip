@@ -468,10 +468,11 @@ __global__ __launch_bounds__(NT) void energy_finish_kernel(SysDev s, int rec) {
   double2* out = s.local + (long long)w * 4;
   out[0] = E1; out[1] = E2; out[2] = E; out[3] = N;
   if (rec >= 0) {
-    double2* ro = s.rec_E + ((long long)rec * s.W + w) * 4;
+    const long long rw = (long long)rec * s.rec_W + s.w_off + w;   // records span all walkers of the system
+    double2* ro = s.rec_E + rw * 4;
     ro[0] = E1; ro[1] = E2; ro[2] = E; ro[3] = N;
-    s.rec_logw[(long long)rec * s.W + w] = s.logw[w];
-    s.rec_status[(long long)rec * s.W + w] = s.status[w];
+    s.rec_logw[rw] = s.logw[w];
+    s.rec_status[rw] = s.status[w];
   }
 }
 
