@@ -319,8 +319,9 @@ struct ftafqmc_ctx {
   bool prof = false;
   std::vector<ProfEvent> events;
   int groups = 2;                       // walker groups per system in ftafqmc_propagate
-  hipStream_t side = nullptr;           // second stream of the walker groups (default priority)
-  hipEvent_t fork = nullptr, join = nullptr;
+  static constexpr int MAX_GROUPS = 4;
+  hipStream_t side[MAX_GROUPS - 1] = {}; // streams of groups 1.. (default priority)
+  hipEvent_t fork = nullptr, join[MAX_GROUPS - 1] = {};
   int set(int code, const std::string& m) { err = m; return code; }
 };
 
@@ -531,7 +532,7 @@ int step(ftafqmc_ctx* h, HostSys& s, std::vector<SysDev>& views, const double2* 
   for (size_t g = 0; g < views.size(); ++g) {
     SysDev& d = views[g];
     const double2* f = fields + (long long)d.w_off * s.n * s.NQ;
-    int rc = slice_step(h, s, d, f, k, rec, g == 0 ? st : h->side);
+    int rc = slice_step(h, s, d, f, k, rec, g == 0 ? st : h->side[g - 1]);
     if (rc) return rc;
   }
   std::swap(s.dev.Y, s.dev.Ynew);           // every view swapped its own pointers once
@@ -543,14 +544,18 @@ int step(ftafqmc_ctx* h, HostSys& s, std::vector<SysDev>& views, const double2* 
   return FTAFQMC_OK;
 }
 
-// Walker groups of a system for the two streams (one group for small batches).
+// Walker groups of a system, one per stream: boundaries at multiples of 8 (the XCD count)
+// nearest to g W / ng, at most W / 8 groups; empty groups are dropped.
 std::vector<SysDev> make_views(const HostSys& s, int ngroups) {
   const int W = s.p.n_walkers;
+  const int ng = std::max(1, std::min(ngroups, W / 8));
   std::vector<SysDev> v;
-  if (ngroups < 2 || W < 16) { v.push_back(walker_view(s, 0, W)); return v; }
-  const int n0 = ((W / 2 + 7) / 8) * 8;
-  v.push_back(walker_view(s, 0, n0));
-  v.push_back(walker_view(s, n0, W - n0));
+  int w0 = 0;
+  for (int g = 1; g <= ng; ++g) {
+    const int b = g == ng ? W : std::min(W, (g * W / ng + 4) / 8 * 8);
+    if (b > w0) v.push_back(walker_view(s, w0, b - w0));
+    w0 = std::max(w0, b);
+  }
   return v;
 }
 
@@ -700,13 +705,13 @@ int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size
     off = layout(h->sys[i], nullptr, off);
   }
   if (off > ws_bytes) { delete h; return FTAFQMC_E_ARG; }
-  if (const char* env = std::getenv("FTAFQMC_WALKER_GROUPS")) h->groups = std::atoi(env) >= 2 ? 2 : 1;
-  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->join, hipEventDisableTiming) != hipSuccess) {
-    ftafqmc_destroy(h);
-    return FTAFQMC_E_HIP;
-  }
+  if (const char* env = std::getenv("FTAFQMC_WALKER_GROUPS"))
+    h->groups = std::max(1, std::min(ftafqmc_ctx::MAX_GROUPS, std::atoi(env)));
+  bool ok = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) == hipSuccess;
+  for (int g = 0; ok && g + 1 < h->groups; ++g)
+    ok = hipStreamCreateWithFlags(&h->side[g], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&h->join[g], hipEventDisableTiming) == hipSuccess;
+  if (!ok) { ftafqmc_destroy(h); return FTAFQMC_E_HIP; }
   h->ws = (char*)d_workspace;
   h->ws_bytes = ws_bytes;
   hipStream_t st = (hipStream_t)stream;
@@ -774,7 +779,7 @@ int ftafqmc_propagate(ftafqmc_t h, const void* const* d_fields, int n_slices, vo
   // the side stream starts after the work already queued on the caller's stream, and the
   // caller's stream continues only after the side stream's work (fork / join)
   HIPCHK(hipEventRecord(h->fork, st));
-  HIPCHK(hipStreamWaitEvent(h->side, h->fork, 0));
+  for (int g = 0; g + 1 < h->groups; ++g) HIPCHK(hipStreamWaitEvent(h->side[g], h->fork, 0));
   int rc = FTAFQMC_OK;
   for (int j = 0; j < n_slices && rc == FTAFQMC_OK; ++j) {
     bool any = false;
@@ -786,8 +791,10 @@ int ftafqmc_propagate(ftafqmc_t h, const void* const* d_fields, int n_slices, vo
     }
     if (!any) break;
   }
-  HIPCHK(hipEventRecord(h->join, h->side));
-  HIPCHK(hipStreamWaitEvent(st, h->join, 0));
+  for (int g = 0; g + 1 < h->groups; ++g) {
+    HIPCHK(hipEventRecord(h->join[g], h->side[g]));
+    HIPCHK(hipStreamWaitEvent(st, h->join[g], 0));
+  }
   return rc;
 }
 
@@ -868,9 +875,11 @@ const char* ftafqmc_last_error(ftafqmc_t h) { return h ? h->err.c_str() : "null 
 void ftafqmc_destroy(ftafqmc_t h) {
   if (!h) return;
   for (auto& ev : h->events) { (void)hipEventDestroy(ev.a); (void)hipEventDestroy(ev.b); }
-  if (h->side) { (void)hipStreamSynchronize(h->side); (void)hipStreamDestroy(h->side); }
+  for (int g = 0; g + 1 < ftafqmc_ctx::MAX_GROUPS; ++g) {
+    if (h->side[g]) { (void)hipStreamSynchronize(h->side[g]); (void)hipStreamDestroy(h->side[g]); }
+    if (h->join[g]) (void)hipEventDestroy(h->join[g]);
+  }
   if (h->fork) (void)hipEventDestroy(h->fork);
-  if (h->join) (void)hipEventDestroy(h->join);
   delete h;
 }
 
