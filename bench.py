@@ -100,12 +100,17 @@ def run_precision(F, torch, systems, fields, steps, warmup):
            "profile_ms_per_step": {k: v[0] / steps for k, v in prof.items()},
            "launches_per_step": {k: v[1] // steps for k, v in prof.items()}}
     gemm_ms, gemm_n = prof["gemm"]
-    flops = sum(8.0 * inf["M"] ** 3 * inf["n_walkers"] * inf["n_slices"] for inf in infos) / (len(systems))
-    # algorithmic flops of one propagator GEMM launch: 8 M^3 per walker (one system)
-    inf0 = infos[0]
-    per_launch = 8.0 * inf0["M"] ** 3 * inf0["n_walkers"]
+    # Propagator products per slice: V^2, V^3, V^4 (with the Taylor blocks), the Horner steps and
+    # the apply; 7 in FP64 (degree 16), 6 in mixed (degree 12).  Each walker group of a system
+    # launches them for its own walkers: one complex M x M x M product per walker and launch
+    # (8 M^3 algorithmic flops per walker), so the total does not depend on the grouping.
+    products = 7 if systems[0].get("precision", 0) == 0 else 6
+    assert gemm_n == products * sum(inf["n_slices"] * inf["walker_groups"] for inf in infos) * steps, (gemm_n, products)
+    flops = steps * sum(products * inf["n_slices"] * 8.0 * inf["M"] ** 3 * inf["n_walkers"] for inf in infos)
     out["gemm_avg_ms"] = gemm_ms / max(gemm_n, 1)
-    out["gemm_tflops"] = per_launch / (out["gemm_avg_ms"] * 1e-3) / 1e12
+    out["gemm_flops_per_launch"] = flops / max(gemm_n, 1)
+    out["gemm_tflops"] = flops / (gemm_ms * 1e-3) / 1e12
+    out["walker_groups"] = [inf["walker_groups"] for inf in infos]
     energies, status = [], []
     for i in range(len(systems)):
         e = ctx.energy(i)
@@ -156,6 +161,8 @@ def main():
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true", help="skip the derivative-pass timing")
+    ap.add_argument("--overlap", action="store_true",
+                    help="propagate with FTAFQMC_OVERLAP (two walker groups on two streams)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -187,7 +194,8 @@ def main():
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     energies = {}
     for p in precs:
-        systems = [dict(sd, precision=0 if p == "fp64" else 1) for sd in wl["systems"]]
+        systems = [dict(sd, precision=0 if p == "fp64" else 1, flags=F.FTAFQMC_OVERLAP if args.overlap else 0)
+                   for sd in wl["systems"]]
         ctx, out, en, st = run_precision(F, torch, systems, fields, args.steps, args.warmup)
         results[p], energies[p] = out, (en, st)
         del ctx
@@ -222,7 +230,8 @@ def main():
         "dtype": "c64-fp32mfma+f64" if use == "mixed" else "f64",
         "data": "synthetic (seeded N(0,1) auxiliary fields, free-electron trial)",
         "config": {"workload": args.workload, "systems": [
-            {k: v for k, v in sd.items()} for sd in wl["systems"]], "precision_reported": use},
+            {k: v for k, v in sd.items()} for sd in wl["systems"]], "precision_reported": use,
+            "walker_groups": r["walker_groups"]},
         "roofline": {"bound": "mfma", "kernel": "propagator complex GEMM (%s MFMA)" % prec_key,
                      "achieved": achieved, "peak": PEAK_TFLOPS[prec_key], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[prec_key],

@@ -80,13 +80,18 @@ typedef struct {
   double mu;       /* interacting chemical potential; NaN selects mu_T of the trial */
   double kscale;   /* lambda in H_1 = lambda T + h (1 = the physical Hamiltonian) */
   int precision;   /* FTAFQMC_FP64 or FTAFQMC_MIXED */
-  int flags;       /* 0 or FTAFQMC_CHECKPOINT */
+  int flags;       /* 0, or FTAFQMC_CHECKPOINT and/or FTAFQMC_OVERLAP */
 } ftafqmc_params;
 
 /* flags: record the sampled path (the shifted coefficients c_Q and tr G of every slice) so
  * that ftafqmc_backward can differentiate it.  FP64 systems with M <= 256 only; the workspace
  * grows by W n N_Q complex128 plus the doubled (2M x 2M) derivative state. */
 #define FTAFQMC_CHECKPOINT 1
+/* flags: split the system's walkers into two groups that propagate on two streams (the
+ * caller's and one the handle owns), so that one group's latency-bound eliminations overlap
+ * with the other group's GEMMs.  Results are identical; throughput is higher where the
+ * elimination dominates (M up to about 256), and each GEMM launch then shares the GPU. */
+#define FTAFQMC_OVERLAP 2
 /* ftafqmc_backward modes */
 #define FTAFQMC_FROZEN_PATH 0
 
@@ -103,6 +108,7 @@ typedef struct {
   int gemm_tile_chain;   /* propagator GEMM tile shape chosen by the start-up autotuner */
   int gemm_tile_apply;   /* tile shape of the product that applies e^V */
   int gemm_tile_shapes;  /* number of tile shapes built (valid values of FTAFQMC_GEMM_TILE) */
+  int walker_groups;     /* walker groups whose eliminations overlap on separate streams */
 } ftafqmc_info;
 
 /* Bytes of device workspace needed for the n_sys systems listed in p[0..n_sys-1]

@@ -20,6 +20,7 @@ FTAFQMC_FP64, FTAFQMC_MIXED = 0, 1
 FTAFQMC_C128, FTAFQMC_C64 = 0, 1
 WALKER_ALIVE, WALKER_KILLED, WALKER_NUMERIC = 0, 1, 2
 FTAFQMC_CHECKPOINT = 1     # params flag: record the path for ftafqmc_backward
+FTAFQMC_OVERLAP = 2        # params flag: two walker groups on two streams
 FROZEN_PATH = 0            # ftafqmc_backward mode
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NUMERIC", -4: "E_STATE", -5: "E_UNSUPPORTED"}
 
@@ -44,7 +45,7 @@ class Info(ctypes.Structure):
                 ("L", ctypes.c_double), ("omega", ctypes.c_double), ("mu_T", ctypes.c_double),
                 ("mu", ctypes.c_double), ("e_madelung", ctypes.c_double),
                 ("gemm_tile_chain", ctypes.c_int), ("gemm_tile_apply", ctypes.c_int),
-                ("gemm_tile_shapes", ctypes.c_int)]
+                ("gemm_tile_shapes", ctypes.c_int), ("walker_groups", ctypes.c_int)]
 
 
 _lib_handle = None

@@ -47,6 +47,7 @@ struct HostSys {
   std::vector<int> rec_slice;
   int tile_chain = 0, tile_apply = 0;   // GEMM tile shapes chosen by the start-up autotuner
   bool ckpt = false;                    // path recorded for the frozen-path derivative
+  int groups = 1;                       // walker groups (streams) of ftafqmc_propagate
   int M2 = 0, ld2 = 0;                  // doubled system of the derivative
   TanDev tan;
 };
@@ -63,7 +64,8 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
   if (p.n_walkers < 1) return "n_walkers must be >= 1";
   if (p.precision != FTAFQMC_FP64 && p.precision != FTAFQMC_MIXED) return "unknown precision";
   if (!std::isfinite(p.kscale)) return "kscale must be finite";
-  if (p.flags & ~FTAFQMC_CHECKPOINT) return "unknown flags";
+  if (p.flags & ~(FTAFQMC_CHECKPOINT | FTAFQMC_OVERLAP)) return "unknown flags";
+  s.groups = (p.flags & FTAFQMC_OVERLAP) ? 2 : 1;
   s.ckpt = (p.flags & FTAFQMC_CHECKPOINT) != 0;
   if (s.ckpt && p.precision != FTAFQMC_FP64) return "the path record for derivatives needs FP64 propagation";
   // box, temperature, slices (Sec. "Computational Details", eq. fermiT)
@@ -318,7 +320,7 @@ struct ftafqmc_ctx {
   std::string err;
   bool prof = false;
   std::vector<ProfEvent> events;
-  int groups = 2;                       // walker groups per system in ftafqmc_propagate
+  int groups = 1;                       // streams in use: the caller's and groups - 1 side streams
   static constexpr int MAX_GROUPS = 4;
   hipStream_t side[MAX_GROUPS - 1] = {}; // streams of groups 1.. (default priority)
   hipEvent_t fork = nullptr, join[MAX_GROUPS - 1] = {};
@@ -705,8 +707,12 @@ int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size
     off = layout(h->sys[i], nullptr, off);
   }
   if (off > ws_bytes) { delete h; return FTAFQMC_E_ARG; }
-  if (const char* env = std::getenv("FTAFQMC_WALKER_GROUPS"))
-    h->groups = std::max(1, std::min(ftafqmc_ctx::MAX_GROUPS, std::atoi(env)));
+  h->groups = 1;
+  for (auto& s : h->sys) {
+    if (const char* env = std::getenv("FTAFQMC_WALKER_GROUPS"))   // experiments: force a group count
+      s.groups = std::max(1, std::min(ftafqmc_ctx::MAX_GROUPS, std::atoi(env)));
+    h->groups = std::max(h->groups, s.groups);
+  }
   bool ok = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) == hipSuccess;
   for (int g = 0; ok && g + 1 < h->groups; ++g)
     ok = hipStreamCreateWithFlags(&h->side[g], hipStreamNonBlocking) == hipSuccess &&
@@ -756,6 +762,7 @@ int ftafqmc_query(ftafqmc_t h, int sys, ftafqmc_info* out) {
   out->mu_T = s.muT; out->mu = s.mu; out->e_madelung = s.EM;
   out->gemm_tile_chain = s.tile_chain; out->gemm_tile_apply = s.tile_apply;
   out->gemm_tile_shapes = gemm_tile_count();
+  out->walker_groups = (int)make_views(s, s.groups).size();
   return FTAFQMC_OK;
 }
 
@@ -775,7 +782,7 @@ int ftafqmc_propagate(ftafqmc_t h, const void* const* d_fields, int n_slices, vo
     if (!d_fields[i]) return h->set(FTAFQMC_E_ARG, "null fields pointer");
   hipStream_t st = (hipStream_t)stream;
   std::vector<std::vector<SysDev>> views;
-  for (auto& s : h->sys) views.push_back(make_views(s, h->groups));
+  for (auto& s : h->sys) views.push_back(make_views(s, s.groups));
   // the side stream starts after the work already queued on the caller's stream, and the
   // caller's stream continues only after the side stream's work (fork / join)
   HIPCHK(hipEventRecord(h->fork, st));

@@ -318,3 +318,29 @@ def test_every_gemm_tile_shape_gives_the_same_path(precision, monkeypatch):
     monkeypatch.delenv("FTAFQMC_GEMM_TILE")
     ctx, _ = gpu_run(F, [sd], [flds])
     assert 0 <= ctx.info()["gemm_tile_chain"] < n_tiles
+
+
+def test_overlapped_walker_groups_give_identical_results():
+    """FTAFQMC_OVERLAP (two walker groups on two streams) changes the schedule only: records,
+    weights and G are bit-identical to the single-stream run, for one system and for an uneven
+    pair of systems in one handle, and the path record feeds the same derivatives."""
+    F = _F()
+    sd = dict(n_elec=38, rs=1.0, theta=0.25, nmax2=5, dtau=0.05, stab_every=5, walkers=24)
+    sd2 = dict(n_elec=14, rs=0.5, theta=0.0625, nmax2=2, dtau=0.05, stab_every=10, walkers=17)
+    s1, s2 = oracle_system(sd), oracle_system(sd2)
+    f1 = si.fields(91, sd["walkers"], s1.n_slices, s1.NQ)
+    f2 = si.fields(92, sd2["walkers"], s2.n_slices, s2.NQ)
+    out = {}
+    for flags in (0, F.FTAFQMC_OVERLAP):
+        ctx, _ = gpu_run(F, [dict(sd, flags=flags | F.FTAFQMC_CHECKPOINT), dict(sd2, flags=flags)], [f1, f2])
+        assert ctx.info(0)["walker_groups"] == (2 if flags else 1)
+        res = []
+        for i in range(2):
+            rec = ctx.records(i)
+            res += [rec["trace"].cpu().numpy(), rec["logw"].cpu().numpy(), ctx.greens(i).cpu().numpy()]
+        ctx.energy(0)
+        res.append(ctx.backward(0)["walker"].cpu().numpy())
+        out[flags] = res
+        ctx.close()
+    for a, b in zip(out[0], out[F.FTAFQMC_OVERLAP]):
+        assert np.array_equal(a, b)
