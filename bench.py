@@ -120,6 +120,28 @@ def run_precision(F, torch, systems, fields, steps, warmup):
     return ctx, out, energies, status
 
 
+def time_graph(F, torch, systems, fields, steps):
+    """Whole paths replayed from a captured HIP graph (FTAFQMC_GRAPH), timed without the
+    per-launch profiling events (which keep propagation eager)."""
+    ctx = F.Context([dict(sd, flags=sd.get("flags", 0) | F.FTAFQMC_GRAPH) for sd in systems])
+    infos = [ctx.info(i) for i in range(len(systems))]
+    for _ in range(2):                                # capture, then one replay
+        ctx.reset()
+        ctx.propagate(fields)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.reset()
+        ctx.propagate(fields)
+        for i in range(len(systems)):
+            ctx.energy(i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.close()
+    ws = sum(inf["n_walkers"] * inf["n_slices"] for inf in infos)
+    return {"walker_slices_per_s": ws * steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps}
+
+
 def time_backward(F, torch, workload="ueg_n38_m123"):
     """Wall time of one frozen-path derivative pass (ftafqmc_backward) on the derivative
     workload, beside the FP64 forward path it differentiates (both with inputs in HBM)."""
@@ -161,6 +183,8 @@ def main():
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true", help="skip the derivative-pass timing")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time whole paths replayed from a captured HIP graph (no profiling events)")
     ap.add_argument("--overlap", action="store_true",
                     help="propagate with FTAFQMC_OVERLAP (two walker groups on two streams)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -200,6 +224,8 @@ def main():
         results[p], energies[p] = out, (en, st)
         del ctx
         torch.cuda.empty_cache()
+        if args.graph:
+            out["graph_replay"] = time_graph(F, torch, systems, fields, args.steps)
     err = None
     if "fp64" in energies and "mixed" in energies:
         errs, nerrs, werrs = [], [], []

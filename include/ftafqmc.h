@@ -80,7 +80,7 @@ typedef struct {
   double mu;       /* interacting chemical potential; NaN selects mu_T of the trial */
   double kscale;   /* lambda in H_1 = lambda T + h (1 = the physical Hamiltonian) */
   int precision;   /* FTAFQMC_FP64 or FTAFQMC_MIXED */
-  int flags;       /* 0, or FTAFQMC_CHECKPOINT and/or FTAFQMC_OVERLAP */
+  int flags;       /* 0, or any of FTAFQMC_CHECKPOINT, FTAFQMC_OVERLAP, FTAFQMC_GRAPH */
 } ftafqmc_params;
 
 /* flags: record the sampled path (the shifted coefficients c_Q and tr G of every slice) so
@@ -92,6 +92,11 @@ typedef struct {
  * with the other group's GEMMs.  Results are identical; throughput is higher where the
  * elimination dominates (M up to about 256), and each GEMM launch then shares the GPU. */
 #define FTAFQMC_OVERLAP 2
+/* flags (on any system of a handle): a call of ftafqmc_propagate that runs every system's whole
+ * path from slice 0 is captured once into a HIP graph and replayed by later such calls with the
+ * same field buffers (their contents may change between calls).  Results are identical to the
+ * eager launches; profiling (ftafqmc_profile) runs eagerly. */
+#define FTAFQMC_GRAPH 4
 /* ftafqmc_backward modes */
 #define FTAFQMC_FROZEN_PATH 0
 

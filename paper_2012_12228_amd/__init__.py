@@ -21,6 +21,7 @@ FTAFQMC_C128, FTAFQMC_C64 = 0, 1
 WALKER_ALIVE, WALKER_KILLED, WALKER_NUMERIC = 0, 1, 2
 FTAFQMC_CHECKPOINT = 1     # params flag: record the path for ftafqmc_backward
 FTAFQMC_OVERLAP = 2        # params flag: two walker groups on two streams
+FTAFQMC_GRAPH = 4          # params flag: replay whole-path propagation from a captured HIP graph
 FROZEN_PATH = 0            # ftafqmc_backward mode
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NUMERIC", -4: "E_STATE", -5: "E_UNSUPPORTED"}
 

@@ -48,6 +48,8 @@ struct HostSys {
   int tile_chain = 0, tile_apply = 0;   // GEMM tile shapes chosen by the start-up autotuner
   bool ckpt = false;                    // path recorded for the frozen-path derivative
   int groups = 1;                       // walker groups (streams) of ftafqmc_propagate
+  double2* Y0 = nullptr;                // the buffers Y and Ynew start as at every reset
+  double2* Ynew0 = nullptr;
   int M2 = 0, ld2 = 0;                  // doubled system of the derivative
   TanDev tan;
 };
@@ -64,7 +66,7 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
   if (p.n_walkers < 1) return "n_walkers must be >= 1";
   if (p.precision != FTAFQMC_FP64 && p.precision != FTAFQMC_MIXED) return "unknown precision";
   if (!std::isfinite(p.kscale)) return "kscale must be finite";
-  if (p.flags & ~(FTAFQMC_CHECKPOINT | FTAFQMC_OVERLAP)) return "unknown flags";
+  if (p.flags & ~(FTAFQMC_CHECKPOINT | FTAFQMC_OVERLAP | FTAFQMC_GRAPH)) return "unknown flags";
   s.groups = (p.flags & FTAFQMC_OVERLAP) ? 2 : 1;
   s.ckpt = (p.flags & FTAFQMC_CHECKPOINT) != 0;
   if (s.ckpt && p.precision != FTAFQMC_FP64) return "the path record for derivatives needs FP64 propagation";
@@ -271,6 +273,7 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.mat_stride = (long long)mat;
   d.aug_stride = (long long)2 * mat;
   d.w_off = 0; d.rec_W = W;
+  s.Y0 = d.Y; s.Ynew0 = d.Ynew;
   if (s.ckpt) {
     SysDev& dd = s.tan.dd;
     dd.NQ = NQ; dd.W = W; dd.n = s.n; dd.grid_dim = s.gdim; dd.grid_c0 = s.gc0;
@@ -324,6 +327,13 @@ struct ftafqmc_ctx {
   static constexpr int MAX_GROUPS = 4;
   hipStream_t side[MAX_GROUPS - 1] = {}; // streams of groups 1.. (default priority)
   hipEvent_t fork = nullptr, join[MAX_GROUPS - 1] = {};
+  // FTAFQMC_GRAPH: the launch sequence of a whole path, captured once and replayed
+  bool graph = false;
+  hipStream_t cap = nullptr;            // capture stream (the caller's may be the legacy default stream)
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const void*> gfields;     // field buffers the captured path reads
+  struct SysAfter { int k, nrec; std::vector<int> rec_slice; double2* Y; double2* Ynew; };
+  std::vector<SysAfter> gafter;         // host-side state of every system after the path
   int set(int code, const std::string& m) { err = m; return code; }
 };
 
@@ -501,6 +511,8 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
 }
 
 int reset_sys(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
+  s.dev.Y = s.Y0;                       // every path starts from the same buffers (graph replay)
+  s.dev.Ynew = s.Ynew0;
   HIPCHK(launch_init_state(s.dev, st));
   int rc = greens(h, s, s.dev, 0, 1, st);
   if (rc) return rc;
@@ -671,6 +683,32 @@ int backward(ftafqmc_ctx* h, HostSys& s, const double* cot, double2* jac, double
   return FTAFQMC_OK;
 }
 
+// The launch sequence of ftafqmc_propagate for n_slices slices (eager, or under graph capture).
+int run_slices(ftafqmc_ctx* h, const void* const* d_fields, int n_slices, hipStream_t st) {
+  std::vector<std::vector<SysDev>> views;
+  for (auto& s : h->sys) views.push_back(make_views(s, s.groups));
+  // the side stream starts after the work already queued on the caller's stream, and the
+  // caller's stream continues only after the side stream's work (fork / join)
+  HIPCHK(hipEventRecord(h->fork, st));
+  for (int g = 0; g + 1 < h->groups; ++g) HIPCHK(hipStreamWaitEvent(h->side[g], h->fork, 0));
+  int rc = FTAFQMC_OK;
+  for (int j = 0; j < n_slices && rc == FTAFQMC_OK; ++j) {
+    bool any = false;
+    for (size_t i = 0; i < h->sys.size() && rc == FTAFQMC_OK; ++i) {
+      HostSys& s = h->sys[i];
+      if (s.k >= s.n) continue;
+      any = true;
+      rc = step(h, s, views[i], (const double2*)d_fields[i], st);
+    }
+    if (!any) break;
+  }
+  for (int g = 0; g + 1 < h->groups; ++g) {
+    HIPCHK(hipEventRecord(h->join[g], h->side[g]));
+    HIPCHK(hipStreamWaitEvent(st, h->join[g], 0));
+  }
+  return rc;
+}
+
 int check_handle(ftafqmc_ctx* h, int sys) {
   if (!h) return FTAFQMC_E_ARG;
   if (sys < 0 || sys >= (int)h->sys.size()) return h->set(FTAFQMC_E_ARG, "system index out of range");
@@ -709,6 +747,7 @@ int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size
   if (off > ws_bytes) { delete h; return FTAFQMC_E_ARG; }
   h->groups = 1;
   for (auto& s : h->sys) {
+    if (s.p.flags & FTAFQMC_GRAPH) h->graph = true;
     if (const char* env = std::getenv("FTAFQMC_WALKER_GROUPS"))   // experiments: force a group count
       s.groups = std::max(1, std::min(ftafqmc_ctx::MAX_GROUPS, std::atoi(env)));
     h->groups = std::max(h->groups, s.groups);
@@ -781,28 +820,37 @@ int ftafqmc_propagate(ftafqmc_t h, const void* const* d_fields, int n_slices, vo
   for (size_t i = 0; i < h->sys.size(); ++i)
     if (!d_fields[i]) return h->set(FTAFQMC_E_ARG, "null fields pointer");
   hipStream_t st = (hipStream_t)stream;
-  std::vector<std::vector<SysDev>> views;
-  for (auto& s : h->sys) views.push_back(make_views(s, s.groups));
-  // the side stream starts after the work already queued on the caller's stream, and the
-  // caller's stream continues only after the side stream's work (fork / join)
-  HIPCHK(hipEventRecord(h->fork, st));
-  for (int g = 0; g + 1 < h->groups; ++g) HIPCHK(hipStreamWaitEvent(h->side[g], h->fork, 0));
-  int rc = FTAFQMC_OK;
-  for (int j = 0; j < n_slices && rc == FTAFQMC_OK; ++j) {
-    bool any = false;
-    for (size_t i = 0; i < h->sys.size() && rc == FTAFQMC_OK; ++i) {
-      HostSys& s = h->sys[i];
-      if (s.k >= s.n) continue;
-      any = true;
-      rc = step(h, s, views[i], (const double2*)d_fields[i], st);
+  bool whole = h->graph && !h->prof;
+  for (auto& s : h->sys) whole = whole && s.k == 0 && n_slices >= s.n;
+  if (!whole) return run_slices(h, d_fields, n_slices, st);
+  std::vector<const void*> key(d_fields, d_fields + h->sys.size());
+  if (!h->gexec || key != h->gfields) {
+    if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+    if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    // record on the capture stream (nothing runs); the instantiated graph is launched on st
+    HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = run_slices(h, d_fields, n_slices, h->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap, &g);
+    if (rc != FTAFQMC_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != FTAFQMC_OK ? rc : h->set(FTAFQMC_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
     }
-    if (!any) break;
+    const hipError_t e2 = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) { h->gexec = nullptr; return h->set(FTAFQMC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e2)); }
+    h->gfields = key;
+    h->gafter.clear();
+    for (auto& s : h->sys) h->gafter.push_back({s.k, s.nrec, s.rec_slice, s.dev.Y, s.dev.Ynew});
+  } else {
+    for (size_t i = 0; i < h->sys.size(); ++i) {   // the replay leaves every system where the capture did
+      HostSys& s = h->sys[i];
+      const ftafqmc_ctx::SysAfter& a = h->gafter[i];
+      s.k = a.k; s.nrec = a.nrec; s.rec_slice = a.rec_slice; s.dev.Y = a.Y; s.dev.Ynew = a.Ynew;
+    }
   }
-  for (int g = 0; g + 1 < h->groups; ++g) {
-    HIPCHK(hipEventRecord(h->join[g], h->side[g]));
-    HIPCHK(hipStreamWaitEvent(st, h->join[g], 0));
-  }
-  return rc;
+  HIPCHK(hipGraphLaunch(h->gexec, st));
+  return FTAFQMC_OK;
 }
 
 int ftafqmc_greens(ftafqmc_t h, int sys, void* d_G, int dtype, void* stream) {
@@ -887,6 +935,8 @@ void ftafqmc_destroy(ftafqmc_t h) {
     if (h->join[g]) (void)hipEventDestroy(h->join[g]);
   }
   if (h->fork) (void)hipEventDestroy(h->fork);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->cap) { (void)hipStreamSynchronize(h->cap); (void)hipStreamDestroy(h->cap); }
   delete h;
 }
 

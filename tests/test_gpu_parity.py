@@ -344,3 +344,44 @@ def test_overlapped_walker_groups_give_identical_results():
         ctx.close()
     for a, b in zip(out[0], out[F.FTAFQMC_OVERLAP]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("overlap", [0, 1], ids=["one_stream", "overlap"])
+def test_graph_replays_match_eager_paths(overlap):
+    """FTAFQMC_GRAPH: the first whole-path call is captured, later calls replay the graph.  Every
+    replay, with eager work (energy, G copies, a reset) between replays and with new field values
+    written into the same buffer, gives bit-identical records and G to eager propagation."""
+    F = _F()
+    extra = F.FTAFQMC_OVERLAP if overlap else 0
+    sd = dict(n_elec=38, rs=1.0, theta=0.25, nmax2=5, dtau=0.05, stab_every=4, walkers=24)
+    sd2 = dict(n_elec=14, rs=0.5, theta=0.0625, nmax2=2, dtau=0.05, stab_every=10, walkers=9)
+    s1, s2 = oracle_system(sd), oracle_system(sd2)
+    fa = [si.fields(s, sdx["walkers"], so.n_slices, so.NQ) for s, sdx, so in ((61, sd, s1), (62, sd2, s2))]
+    fb = [si.fields(s, sdx["walkers"], so.n_slices, so.NQ) for s, sdx, so in ((71, sd, s1), (72, sd2, s2))]
+
+    def snapshot(ctx):
+        out = []
+        for i in range(2):
+            rec = ctx.records(i)
+            out += [rec["trace"].cpu().numpy(), rec["logw"].cpu().numpy(), ctx.greens(i).cpu().numpy()]
+        return out
+
+    refs = []
+    for fl in (fa, fb):
+        ctx, _ = gpu_run(F, [dict(sd, flags=extra), dict(sd2, flags=extra)], fl)
+        refs.append(snapshot(ctx))
+        ctx.close()
+    ctx = F.Context([dict(sd, flags=extra | F.FTAFQMC_GRAPH), dict(sd2, flags=extra)])
+    bufs = [torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in fa]
+    for rep, which in enumerate([0, 0, 1, 0]):
+        for b, f in zip(bufs, (fa, fb)[which]):
+            b.copy_(torch.from_numpy(np.ascontiguousarray(f)).cuda())
+        if rep:
+            ctx.energy(0)
+            ctx.reset()
+        ctx.propagate(bufs)
+        torch.cuda.synchronize()
+        assert ctx.info(0)["slice"] == s1.n_slices and ctx.info(1)["slice"] == s2.n_slices
+        for a, b in zip(snapshot(ctx), refs[which]):
+            assert np.array_equal(a, b), (rep, which)
+    ctx.close()
