@@ -2,23 +2,27 @@
 //
 // Used for three solves of the slice path:
 //   * the Green's function (eq. green) in scale-split form: A = X^T, R = (Ti D_b)^T with
-//     partial pivoting and back substitution, so R becomes X^{-T} (Ti D_b)^T;
+//     partial pivoting, by blocked Gauss-Jordan, so R becomes X^{-T} (Ti D_b)^T;
 //   * the Cholesky factor of S = Y^H Y in the QR stabilisation: no pivoting, forward
 //     only; the left block becomes U = D L^H (S = L D L^H) and R becomes L^{-1} R;
 //   * the update of T^{-1} by a unit triangular factor (again forward only).
-// Right-looking with NB = 32 columns per panel, one kernel sequence for all walkers:
+// NB = 32 columns per panel, one kernel sequence for all walkers:
 //   panel   one workgroup per walker factors the panel with partial pivoting, one row per
 //           thread (pivot search = workgroup reduction, row exchange and rank-1 updates =
-//           register operations with LDS broadcasts), then inverts the unit lower L11 in LDS;
-//   swap    column-parallel row exchanges of the trailing columns and right-hand sides;
+//           register operations with LDS broadcasts), then inverts the triangular factors of
+//           the pivot block in LDS;
+//   swap    column-parallel row exchanges;
+// Forward elimination (LU, right-looking):
 //   trsm    U12 = L11^{-1} A12 as a small in-place MFMA GEMM (each workgroup owns whole
 //           columns and reads them completely before it writes);
 //   update  A22 -= L21 U12 as a batched MFMA GEMM over the contiguous column range
 //           [j0+NB, rhs_off+nrhs) (the zero padding between the two blocks stays zero).
-// Back substitution: the inverses of the diagonal blocks of U in one launch, then by
-// blocks from the bottom an in-place GEMM H_i = U_ii^{-1} R_i and the update of the rows
-// above.  ln det of the left block is the sum of the logs of the pivots plus i pi per
-// row exchange.
+// Gauss-Jordan (the solve with right-hand sides): the panel kernel leaves the panel columns
+// untouched and returns A11^{-1} = U11^{-1} L11^{-1} of the pivot block; the row exchanges run
+// over the panel columns too, the pivot rows become P = A11^{-1} [A12 | R1] in place, and every
+// other row, above and below, takes row_i -= A_i1 P.  After the last panel the right-hand block
+// holds the solution in natural order: row exchanges only reorder equations.
+// ln det of the left block is the sum of the logs of the pivots plus i pi per row exchange.
 #include "common.h"
 #include "kernels.h"
 #include <climits>
@@ -31,6 +35,7 @@ constexpr int NB = 32;
 struct PanelParams {
   double2* aug; long long stride; int lda;
   int M, j0, jb, W, pivot;
+  int gj;         // Gauss-Jordan: keep the panel columns, return A11^{-1} instead of L11^{-1}
   int* piv; int ld;
   double2* lndet; int* status;
   double2* tri;   // [W][NB][NB] inverse of the unit lower L11 of this panel
@@ -44,7 +49,9 @@ struct PanelShared {
   double2 curRow[2][NB];            // logical row `col` (used without pivoting)
   double2 pivv[NB];                 // pivots of this panel
   int swapped[NB];
-  double2 Ls[NB][NB + 1];           // unit lower L11
+  double2 Ls[NB][NB + 1];           // unit lower L11, then its inverse
+  double2 Us[NB][NB + 1];           // upper U11, then its inverse (Gauss-Jordan)
+  double2 rpiv[NB];                 // 1 / U11_ii
 };
 
 // DPP move of a double within 16-lane rows (CTRL is a row-local pattern, every source exists).
@@ -161,17 +168,26 @@ __global__ __launch_bounds__(NT) void panel_kernel(PanelParams p) {
   x.piv = p.piv + (long long)w * p.ld;
   PanelColumns<NT, 0>::run(a, x, sh);
   const int myrow = x.myrow;
-  if (myrow < M) {
+  if (myrow < M && !p.gj) {
 #pragma unroll
     for (int c = 0; c < NB; ++c)
       if (c < jb) aug[(long long)myrow * lda + j0 + c] = a[c];
   }
-  // logical rows j0..j0+jb hold L11 in their strictly lower part
+  // logical rows j0..j0+jb hold L11 in their strictly lower part and U11 in the rest
   if (myrow >= j0 && myrow < j0 + NB) {
     const int i = myrow - j0;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) sh.Ls[i][c] = (c < i && i < jb) ? a[c] : make_double2(0.0, 0.0);
+    for (int c = 0; c < NB; ++c) {
+      sh.Ls[i][c] = (c < i && i < jb) ? a[c] : make_double2(0.0, 0.0);
+      sh.Us[i][c] = (c >= i && i < jb && c < jb) ? a[c] : make_double2(0.0, 0.0);
+    }
   }
+  // rows of the pivot block beyond jb (last panel) are the identity
+  for (int i = jb + t; i < NB; i += NT)
+    for (int c = 0; c < NB; ++c) {
+      sh.Ls[i][c] = make_double2(0.0, 0.0);
+      sh.Us[i][c] = make_double2(c == i ? 1.0 : 0.0, 0.0);
+    }
   __syncthreads();
   // ln det contribution and pivot checks (wave 0 holds all jb <= 32 pivots)
   double lx = 0.0, ly = 0.0, nsw = 0.0, badv = 0.0;
@@ -187,6 +203,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(PanelParams p) {
     lx = wave_sum(lx); ly = wave_sum(ly); nsw = wave_sum(nsw); badv = wave_sum(badv);
   }
   // column t of L11^{-1} by forward substitution on e_t
+  double2* tri = p.tri + (long long)w * NB * NB;
   if (t < NB) {
     double2 xcol[NB];
 #pragma unroll
@@ -196,9 +213,39 @@ __global__ __launch_bounds__(NT) void panel_kernel(PanelParams p) {
       for (int k = 0; k < i; ++k) v = cfnms(v, sh.Ls[i][k], xcol[k]);
       xcol[i] = v;
     }
-    double2* tri = p.tri + (long long)w * NB * NB;
+    if (!p.gj) {
 #pragma unroll
-    for (int i = 0; i < NB; ++i) tri[i * NB + t] = xcol[i];
+      for (int i = 0; i < NB; ++i) tri[i * NB + t] = xcol[i];
+    } else {
+      // threads 0..NB-1 are one wave: every read of Ls above precedes these writes
+#pragma unroll
+      for (int i = 0; i < NB; ++i) sh.Ls[i][t] = xcol[i];
+      sh.rpiv[t] = cdiv(make_double2(1.0, 0.0), sh.Us[t][t]);
+    }
+  }
+  if (p.gj) {
+    __syncthreads();
+    // column t of U11^{-1} by back substitution on e_t (again one wave, in place)
+    if (t < NB) {
+      double2 xcol[NB];
+#pragma unroll
+      for (int i = NB - 1; i >= 0; --i) {
+        double2 v = make_double2(i == t ? 1.0 : 0.0, 0.0);
+#pragma unroll
+        for (int k = i + 1; k < NB; ++k) v = cfnms(v, sh.Us[i][k], xcol[k]);
+        xcol[i] = cmul(v, sh.rpiv[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i) sh.Us[i][t] = xcol[i];
+    }
+    __syncthreads();
+    // A11^{-1} = U11^{-1} L11^{-1}
+    for (int e = t; e < NB * NB; e += NT) {
+      const int i = e / NB, j = e - i * NB;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int k = (i > j ? i : j); k < NB; ++k) acc = cadd(acc, cmul(sh.Us[i][k], sh.Ls[k][j]));
+      tri[e] = acc;
+    }
   }
   if (t == 0) {
     if (p.lndet) {
@@ -230,34 +277,6 @@ __global__ __launch_bounds__(256) void swap_kernel(PanelParams p, int c0, int c1
       aug[(long long)pr * lda + col] = u;
     }
   }
-}
-
-// Inverses of the upper triangular diagonal blocks U_bb, one workgroup per (walker, block).
-__global__ __launch_bounds__(256) void tri_inv_upper_kernel(PanelParams p, int nblk, double2* uinv) {
-  __shared__ double2 U[NB][NB + 1];
-  __shared__ double2 X[NB][NB + 1];
-  const int w = blockIdx.x / nblk, b = blockIdx.x - w * nblk;
-  if (w >= p.W) return;
-  const int i0 = b * NB, ib = min(NB, p.M - i0), t = threadIdx.x;
-  const double2* aug = p.aug + (long long)w * p.stride;
-  for (int e = t; e < NB * NB; e += 256) {
-    const int i = e / NB, c = e - i * NB;
-    U[i][c] = (i < ib && c < ib && c >= i) ? aug[(long long)(i0 + i) * p.lda + i0 + c]
-                                            : make_double2(i == c ? 1.0 : 0.0, 0.0);
-    X[i][c] = make_double2(i == c ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
-  // U X = I from the last row up: X[k][:] = (I[k][:] - sum_{m>k} U[k][m] X[m][:]) / U[k][k]
-  for (int k = NB - 1; k >= 0; --k) {
-    if (t < NB) {
-      double2 v = X[k][t];
-      for (int m = k + 1; m < NB; ++m) v = cfnms(v, U[k][m], X[m][t]);
-      X[k][t] = cdiv(v, U[k][k]);
-    }
-    __syncthreads();
-  }
-  double2* out = uinv + ((long long)w * nblk + b) * NB * NB;
-  for (int e = t; e < NB * NB; e += 256) out[e] = X[e / NB][e % NB];
 }
 
 GemmParams aug_params(const ElimParams& e) {
@@ -295,24 +314,22 @@ GemmParams tri_params(const ElimParams& e, const double2* T, long long sT, int r
 
 }  // namespace
 
-size_t elim_tri_elems(int M) { return (size_t)((M + NB - 1) / NB) * NB * NB; }
+size_t elim_tri_elems(int) { return (size_t)NB * NB; }
 
 hipError_t launch_elim(const ElimParams& e, hipStream_t s) {
   if (e.W <= 0 || e.M <= 0) return hipSuccess;
   if (e.M > 512 || !e.tri) return hipErrorInvalidValue;
   const int M = e.M;
   const int cend = e.rhs_off + e.nrhs;   // trailing columns run up to the end of the right-hand sides
-  const int nblk = (M + NB - 1) / NB;
-  double2* linv = e.tri;                  // forward phase: [W][NB][NB], the current panel's L11^{-1}
-  double2* uinv = e.tri;                  // back substitution: [W][nblk][NB][NB], the U_bb^{-1}
+  const bool gj = e.backsub != 0;        // a solve: Gauss-Jordan, no back substitution
   PanelParams p;
   p.aug = e.aug; p.stride = e.stride; p.lda = e.lda; p.M = M; p.W = e.W; p.pivot = e.pivot;
-  p.piv = e.piv; p.ld = e.ld; p.lndet = e.lndet; p.status = e.status;
+  p.piv = e.piv; p.ld = e.ld; p.lndet = e.lndet; p.status = e.status; p.gj = gj ? 1 : 0;
+  p.tri = e.tri;                          // [W][NB][NB]: L11^{-1} (forward) or A11^{-1} (Gauss-Jordan)
   hipError_t err;
   for (int j0 = 0; j0 < M; j0 += NB) {
     const int jb = M - j0 < NB ? M - j0 : NB;
     p.j0 = j0; p.jb = jb;
-    p.tri = linv;                         // L11^{-1} of walker w at linv + w * NB * NB
     if (M - j0 <= 64) panel_kernel<64><<<e.W, 64, 0, s>>>(p);
     else if (M - j0 <= 128) panel_kernel<128><<<e.W, 128, 0, s>>>(p);
     else if (M - j0 <= 256) panel_kernel<256><<<e.W, 256, 0, s>>>(p);
@@ -322,24 +339,20 @@ hipError_t launch_elim(const ElimParams& e, hipStream_t s) {
     const int ncols = cend - c0;
     if (ncols <= 0) continue;
     if (e.pivot) {
-      const int chunks = (ncols + 255) / 256;
-      swap_kernel<<<e.W * chunks, 256, 0, s>>>(p, c0, cend, chunks);
+      const int s0 = gj ? j0 : c0;        // Gauss-Jordan keeps the panel columns in memory: swap them too
+      const int chunks = (cend - s0 + 255) / 256;
+      swap_kernel<<<e.W * chunks, 256, 0, s>>>(p, s0, cend, chunks);
       if ((err = hipGetLastError()) != hipSuccess) return err;
     }
-    if ((err = launch_zgemm(tri_params(e, linv, (long long)NB * NB, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
+    if ((err = launch_zgemm(tri_params(e, e.tri, (long long)NB * NB, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
       return err;
-    if (M - c0 > 0 && (err = launch_zgemm(update_params(e, c0, M - c0, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
-      return err;
-  }
-  if (e.backsub) {
-    tri_inv_upper_kernel<<<e.W * nblk, 256, 0, s>>>(p, nblk, uinv);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    for (int b = nblk - 1; b >= 0; --b) {
-      const int i0 = b * NB, ib = M - i0 < NB ? M - i0 : NB;
-      GemmParams g = tri_params(e, uinv + (long long)b * NB * NB, (long long)nblk * NB * NB, i0, ib, e.rhs_off, e.nrhs);
+    if (gj) {
+      GemmParams g = update_params(e, 0, M, j0, jb, c0, ncols);   // every row but the pivot rows
+      g.skip0 = j0;
+      g.skip1 = j0 + jb;
       if ((err = launch_zgemm(g, GEMM_Z64, s)) != hipSuccess) return err;
-      if (i0 > 0 && (err = launch_zgemm(update_params(e, 0, i0, i0, ib, e.rhs_off, e.nrhs), GEMM_Z64, s)) != hipSuccess)
-        return err;
+    } else if (M - c0 > 0 && (err = launch_zgemm(update_params(e, c0, M - c0, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess) {
+      return err;
     }
   }
   return hipSuccess;

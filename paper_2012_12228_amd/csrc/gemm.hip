@@ -24,7 +24,7 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int PAD = 1;
+constexpr int PAD = 1;   // LDS row padding (complex elements)
 
 template <int BM_, int BN_, int BK_, int WM_, int WN_> struct Tile {
   static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
@@ -55,8 +55,11 @@ __global__ __launch_bounds__(TL::NT) void zgemm_kernel(GemmParams p) {
   typedef typename cplx_of<ACC>::type cacc;
   typedef typename Mfma<ACC>::acc_t acc_t;
   constexpr int BM = TL::BM, BN = TL::BN, BK = TL::BK, FM = TL::FM, FN = TL::FN, NT = TL::NT;
-  __shared__ cacc As[2][BK][BM + PAD];
+  // A is staged k-contiguous (As[m][k]: the coalesced loads store without a transpose), B as stored
+  __shared__ cacc As[2][BM][BK + PAD];
   __shared__ cacc Bs[2][BK][BN + PAD];
+  // the propagator products use A and B as stored; only the dense linear algebra takes A^H
+  const int opA = ROLE == 1 ? p.opA : 0, opB = ROLE == 1 ? p.opB : 0;
 
   int w, tile;
   if (!xcd_walker_tile(blockIdx.x, p.W, p.tiles_m * p.tiles_n, &w, &tile)) return;
@@ -85,22 +88,22 @@ __global__ __launch_bounds__(TL::NT) void zgemm_kernel(GemmParams p) {
     for (int q = 0; q < TL::EA; ++q) {
       const int e = t + q * NT;
       int gm, gk;
-      if (p.opA == 0) { gm = m0 + e / BK; gk = k0 + e % BK; }
+      if (opA == 0) { gm = m0 + e / BK; gk = k0 + e % BK; }
       else            { gk = k0 + e / BM; gm = m0 + e % BM; }
       double2 v = make_double2(0.0, 0.0);
       if (gm < Mr && gk < Kd)
-        v = p.opA == 0 ? ld_c(A + (long long)gm * p.lda + gk) : cconj(ld_c(A + (long long)gk * p.lda + gm));
+        v = opA == 0 ? ld_c(A + (long long)gm * p.lda + gk) : cconj(ld_c(A + (long long)gk * p.lda + gm));
       ra[q] = cvt<ACC>(v);
     }
 #pragma unroll
     for (int q = 0; q < TL::EB; ++q) {
       const int e = t + q * NT;
       int gk, gn;
-      if (p.opB == 0) { gk = k0 + e / BN; gn = n0 + e % BN; }
+      if (opB == 0) { gk = k0 + e / BN; gn = n0 + e % BN; }
       else            { gn = n0 + e / BK; gk = k0 + e % BK; }
       double2 v = make_double2(0.0, 0.0);
       if (gn < Nc && gk < Kd)
-        v = p.opB == 0 ? ld_c(B + (long long)gk * p.ldb + gn) : cconj(ld_c(B + (long long)gn * p.ldb + gk));
+        v = opB == 0 ? ld_c(B + (long long)gk * p.ldb + gn) : cconj(ld_c(B + (long long)gn * p.ldb + gk));
       rb[q] = cvt<ACC>(v);
     }
   };
@@ -108,14 +111,14 @@ __global__ __launch_bounds__(TL::NT) void zgemm_kernel(GemmParams p) {
 #pragma unroll
     for (int q = 0; q < TL::EA; ++q) {
       const int e = t + q * NT;
-      if (p.opA == 0) As[buf][e % BK][e / BK] = ra[q];
-      else            As[buf][e / BM][e % BM] = ra[q];
+      if (opA == 0) As[buf][e / BK][e % BK] = ra[q];
+      else          As[buf][e % BM][e / BM] = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < TL::EB; ++q) {
       const int e = t + q * NT;
-      if (p.opB == 0) Bs[buf][e / BN][e % BN] = rb[q];
-      else            Bs[buf][e % BK][e / BK] = rb[q];
+      if (opB == 0) Bs[buf][e / BN][e % BN] = rb[q];
+      else          Bs[buf][e % BK][e / BK] = rb[q];
     }
   };
 
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(TL::NT) void zgemm_kernel(GemmParams p) {
     for (int ks = 0; ks < BK; ks += 4) {
       cacc a[FM], b[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) a[i] = As[buf][ks + lk][wr * TL::WM + i * 16 + li];
+      for (int i = 0; i < FM; ++i) a[i] = As[buf][wr * TL::WM + i * 16 + li][ks + lk];
 #pragma unroll
       for (int j = 0; j < FN; ++j) b[j] = Bs[buf][ks + lk][wc * TL::WN + j * 16 + li];
 #pragma unroll
@@ -191,6 +194,7 @@ __global__ __launch_bounds__(TL::NT) void zgemm_kernel(GemmParams p) {
         const int gi = m0 + wr * TL::WM + i * 16 + Mfma<ACC>::row(lane, v);
         const int gj = n0 + wc * TL::WN + j * 16 + li;
         if (gi >= p.mpad || gj >= p.npad) continue;
+        if (ROLE == 1 && gi >= p.skip0 && gi < p.skip1) continue;   // rows left untouched
         const long long off = (long long)gi * p.ldc + gj;
         const bool in = gi < Mr && gj < Nc;
         const double2 acc = make_double2((double)accR[i][j][v], (double)accI[i][j][v]);

@@ -22,6 +22,7 @@ struct GemmParams {
   int role;                  // 0 = propagator chain, 1 = elimination / stabilisation (separate kernel symbols)
   int tile;                  // tile shape index (0 .. gemm_tile_count()-1) for role 0
   int tiles_m, tiles_n;      // set by the launcher
+  int skip0, skip1;          // role 1: rows [skip0, skip1) of C are not written
 };
 hipError_t launch_zgemm(const GemmParams& p, int prec, hipStream_t s);
 int gemm_tile_count();
@@ -32,12 +33,12 @@ struct ElimParams {
   double2* aug; long long stride; int lda;
   int M, rhs_off, nrhs, W;
   int pivot;    // partial (row) pivoting
-  int backsub;  // solve the upper triangle after the forward elimination
+  int backsub;  // solve: Gauss-Jordan to the solution in the right-hand block (else forward only)
   double2* lndet;  // [W] sum of log pivots + i pi (row swaps); may be null
   int* status;     // [W] set to 2 on a zero or non-finite pivot; may be null
   int* piv;        // [W][ld] pivot rows (workspace)
   int ld;          // stride of piv
-  double2* tri;    // [W][elim_tri_elems(M)] triangular-block inverses (workspace)
+  double2* tri;    // [W][elim_tri_elems(M)] inverse of the current pivot block (workspace)
 };
 hipError_t launch_elim(const ElimParams& p, hipStream_t s);
 size_t elim_tri_elems(int M);
