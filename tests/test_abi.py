@@ -46,3 +46,42 @@ def test_invalid_parameters_are_rejected(bad):
     sysdef.update(bad)
     with pytest.raises(RuntimeError, match="E_ARG"):
         F.ftafqmc_workspace_bytes([sysdef])
+
+
+@pytest.mark.parametrize("bad", [dict(flags=8), dict(flags=1, precision=1), dict(flags=1, nmax2=11, n_elec=66, theta=0.125)])
+def test_invalid_flags_are_rejected(bad):
+    """Unknown flag bits, a path record with mixed precision, and a path record whose doubled
+    system would exceed the elimination's 512 rows (M = 171 is fine; M > 256 is not)."""
+    _lib()
+    sysdef = dict(si.WORKLOADS["ueg_n14_m19"]["systems"][0])
+    sysdef.update(bad)
+    if bad.get("nmax2") == 11:
+        sysdef.update(nmax2=24, n_elec=114)          # M = 485
+    with pytest.raises(RuntimeError, match="E_ARG"):
+        F.ftafqmc_workspace_bytes([sysdef])
+
+
+def test_flag_values_match_the_header():
+    text = open(HEADER).read()
+    for name, val in (("FTAFQMC_CHECKPOINT", F.FTAFQMC_CHECKPOINT), ("FTAFQMC_OVERLAP", F.FTAFQMC_OVERLAP),
+                      ("FTAFQMC_GRAPH", F.FTAFQMC_GRAPH), ("FTAFQMC_FROZEN_PATH", F.FROZEN_PATH)):
+        m = re.search(r"#define\s+%s\s+(\d+)" % name, text)
+        assert m and int(m.group(1)) == val, name
+
+
+def test_path_record_grows_the_workspace():
+    _lib()
+    sd = dict(si.WORKLOADS["ueg_n38_m123"]["systems"][0])
+    plain = F.ftafqmc_workspace_bytes([sd])
+    rec = F.ftafqmc_workspace_bytes([dict(sd, flags=F.FTAFQMC_CHECKPOINT)])
+    # the record alone holds W n N_Q complex128 coefficients
+    assert rec - plain > sd["walkers"] * 174 * 828 * 16
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
