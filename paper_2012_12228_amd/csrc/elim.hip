@@ -7,10 +7,12 @@
 //     only; the left block becomes U = D L^H (S = L D L^H) and R becomes L^{-1} R;
 //   * the update of T^{-1} by a unit triangular factor (again forward only).
 // NB = 32 columns per panel, one kernel sequence for all walkers:
-//   panel   one workgroup per walker factors the panel with partial pivoting, one row per
-//           thread (pivot search = workgroup reduction, row exchange and rank-1 updates =
-//           register operations with LDS broadcasts), then inverts the triangular factors of
-//           the pivot block in LDS;
+//   panel   one workgroup per walker, one row per thread (pivot search = workgroup reduction,
+//           row exchange = relabelling, updates = register operations with LDS broadcasts of
+//           the pivot row).  Forward elimination: LU of the panel, then L11^{-1}.  Gauss-Jordan:
+//           in-place Gauss-Jordan inversion of the pivot block inside the column loop (a
+//           runtime loop over columns with the row rotated in registers, so the loop body is
+//           small and stays in the instruction cache);
 //   swap    column-parallel row exchanges;
 // Forward elimination (LU, right-looking):
 //   trsm    U12 = L11^{-1} A12 as a small in-place MFMA GEMM (each workgroup owns whole
@@ -18,7 +20,7 @@
 //   update  A22 -= L21 U12 as a batched MFMA GEMM over the contiguous column range
 //           [j0+NB, rhs_off+nrhs) (the zero padding between the two blocks stays zero).
 // Gauss-Jordan (the solve with right-hand sides): the panel kernel leaves the panel columns
-// untouched and returns A11^{-1} = U11^{-1} L11^{-1} of the pivot block; the row exchanges run
+// untouched and returns A11^{-1} of the pivot block; the row exchanges run
 // over the panel columns too, the pivot rows become P = A11^{-1} [A12 | R1] in place, and every
 // other row, above and below, takes row_i -= A_i1 P.  After the last panel the right-hand block
 // holds the solution in natural order: row exchanges only reorder equations.
@@ -38,20 +40,14 @@ struct PanelParams {
   int gj;         // Gauss-Jordan: keep the panel columns, return A11^{-1} instead of L11^{-1}
   int* piv; int ld;
   double2* lndet; int* status;
-  double2* tri;   // [W][NB][NB] inverse of the unit lower L11 of this panel
+  double2* tri;   // [W][NB][NB] L11^{-1} (forward) or A11^{-1} (Gauss-Jordan) of this panel
 };
 
 template <int NT>
 struct PanelShared {
-  double2 candRow[2][NT / 64][NB];  // each wave's best row, double-buffered by column parity
-  double candVal[2][NT / 64];
-  int candIdx[2][NT / 64];
-  double2 curRow[2][NB];            // logical row `col` (used without pivoting)
+  double2 curRow[2][NB];            // row `col`, double-buffered by column parity
   double2 pivv[NB];                 // pivots of this panel
-  int swapped[NB];
-  double2 Ls[NB][NB + 1];           // unit lower L11, then its inverse
-  double2 Us[NB][NB + 1];           // upper U11, then its inverse (Gauss-Jordan)
-  double2 rpiv[NB];                 // 1 / U11_ii
+  double2 Ls[NB][NB + 1];           // unit lower L11
 };
 
 // DPP move of a double within 16-lane rows (CTRL is a row-local pattern, every source exists).
@@ -60,78 +56,26 @@ template <int CTRL> FT_DEV double dpp_d(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
-// Maximum over the 64 lanes of a wave, returned to every lane.
-FT_DEV double wave_max(double v) {
-  v = fmax(v, dpp_d<0xB1>(v));    // quad_perm [1,0,3,2]
-  v = fmax(v, dpp_d<0x4E>(v));    // quad_perm [2,3,0,1]
-  v = fmax(v, dpp_d<0x124>(v));   // row_ror:4
-  v = fmax(v, dpp_d<0x128>(v));   // row_ror:8
-  v = fmax(v, __shfl_xor(v, 16, 64));
-  v = fmax(v, __shfl_xor(v, 32, 64));
-  return v;
-}
 
 struct PanelCtx {
-  int t, lane, wid, myrow, M, j0, jb, pivot;
-  int* piv;
+  int t, myrow, M, j0, jb;
 };
 
-// Column C of the panel (compile-time, so every register index is static).  Row exchanges
-// only relabel threads: the thread holding logical row prow becomes logical row col and vice
-// versa; rows go to their final positions when the panel is written back.  One barrier per
-// column: each wave publishes its best candidate (value, logical row, entries C..NB-1), and
-// the owner of row col publishes that row for the unpivoted case.
+// Column C of the forward (unpivoted) panel, compile-time so that every register index is
+// static.  One barrier per column: the owner of row col publishes it.
 template <int NT, int C>
 FT_DEV void panel_column(double2 (&a)[NB], PanelCtx& x, PanelShared<NT>& sh) {
   if (C >= x.jb) return;                 // uniform over the workgroup
-  const int col = x.j0 + C, buf = C & 1, M = x.M;
-  const bool cand = x.myrow >= col && x.myrow < M;
-  if (x.pivot) {
-    double bv = cand ? cabs2(a[C]) : -1.0;
-    if (!(bv == bv)) bv = -1.0;          // a NaN entry never wins the search
-    const double mv = wave_max(bv);
-    // lowest lane among the maxima; ties go to the smaller logical row
-    int best = cand && bv == mv ? x.myrow : INT_MAX;
-    for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
-    if (cand && bv == mv && x.myrow == best) {
-#pragma unroll
-      for (int i = C; i < NB; ++i) sh.candRow[buf][x.wid][i] = a[i];
-    }
-    if (x.lane == 0) { sh.candVal[buf][x.wid] = mv; sh.candIdx[buf][x.wid] = best; }
-  } else if (x.myrow == col) {
+  const int col = x.j0 + C, buf = C & 1;
+  if (x.myrow == col) {
 #pragma unroll
     for (int i = C; i < NB; ++i) sh.curRow[buf][i] = a[i];
   }
   __syncthreads();
-  int prow = col;
   const double2* pr = sh.curRow[buf];
-  if (x.pivot) {
-    double bv = sh.candVal[buf][0];
-    int bi = sh.candIdx[buf][0], win = 0;
-#pragma unroll
-    for (int k = 1; k < NT / 64; ++k) {
-      const double v = sh.candVal[buf][k];
-      const int ix = sh.candIdx[buf][k];
-      if (v > bv || (v == bv && ix < bi)) { bv = v; bi = ix; win = k; }
-    }
-    prow = (bi >= col && bi < M) ? bi : col;
-    pr = sh.candRow[buf][win];
-    if (prow == col && !(bi >= col && bi < M)) {
-      // no usable candidate (all NaN): the diagonal row stays; its entries are its own
-      pr = nullptr;
-    }
-    if (x.myrow == prow) x.myrow = col;
-    else if (x.myrow == col) x.myrow = prow;
-  }
-  double2 pv;
-  if (pr) pv = pr[C];
-  else pv = make_double2(NAN, NAN);
-  if (x.t == 0) {
-    if (x.pivot) x.piv[col] = prow;
-    sh.pivv[C] = pv;
-    sh.swapped[C] = prow != col;
-  }
-  if (x.myrow > col && x.myrow < M && pr) {
+  const double2 pv = pr[C];
+  if (x.t == 0) sh.pivv[C] = pv;
+  if (x.myrow > col && x.myrow < x.M) {
     const double2 l = cdiv(a[C], pv);
     a[C] = l;
 #pragma unroll
@@ -149,8 +93,9 @@ template <int NT> struct PanelColumns<NT, NB> {
   static FT_DEV void run(double2 (&)[NB], PanelCtx&, PanelShared<NT>&) {}
 };
 
-// One workgroup per walker factors rows [j0, M) x columns [j0, j0+jb) with partial pivoting,
-// one row per thread, then inverts the unit lower L11 (one column of the inverse per thread).
+// Forward elimination: one workgroup per walker factors rows [j0, M) x columns [j0, j0+jb)
+// without pivoting, one row per thread, writes L21 and U11 back and L11^{-1} to tri (one
+// column of the inverse per thread).
 template <int NT>
 __global__ __launch_bounds__(NT) void panel_kernel(PanelParams p) {
   __shared__ PanelShared<NT> sh;
@@ -159,48 +104,38 @@ __global__ __launch_bounds__(NT) void panel_kernel(PanelParams p) {
   double2* aug = p.aug + (long long)w * p.stride;
   const int t = threadIdx.x;
   const int M = p.M, j0 = p.j0, jb = p.jb, lda = p.lda;
-  const int r = j0 + t;                    // the row this thread loads (M - j0 <= NT)
+  const int r = j0 + t;                    // the row this thread holds (M - j0 <= NT)
   double2 a[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) a[c] = (r < M && c < jb) ? aug[(long long)r * lda + j0 + c] : make_double2(0.0, 0.0);
   PanelCtx x;
-  x.t = t; x.lane = t & 63; x.wid = t >> 6; x.myrow = r; x.M = M; x.j0 = j0; x.jb = jb; x.pivot = p.pivot;
-  x.piv = p.piv + (long long)w * p.ld;
+  x.t = t; x.myrow = r; x.M = M; x.j0 = j0; x.jb = jb;
   PanelColumns<NT, 0>::run(a, x, sh);
-  const int myrow = x.myrow;
-  if (myrow < M && !p.gj) {
+  if (r < M) {
 #pragma unroll
     for (int c = 0; c < NB; ++c)
-      if (c < jb) aug[(long long)myrow * lda + j0 + c] = a[c];
+      if (c < jb) aug[(long long)r * lda + j0 + c] = a[c];
   }
-  // logical rows j0..j0+jb hold L11 in their strictly lower part and U11 in the rest
-  if (myrow >= j0 && myrow < j0 + NB) {
-    const int i = myrow - j0;
+  // rows j0..j0+jb hold L11 in their strictly lower part; rows beyond jb are the identity
+  if (r >= j0 && r < j0 + NB) {
+    const int i = r - j0;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      sh.Ls[i][c] = (c < i && i < jb) ? a[c] : make_double2(0.0, 0.0);
-      sh.Us[i][c] = (c >= i && i < jb && c < jb) ? a[c] : make_double2(0.0, 0.0);
-    }
+    for (int c = 0; c < NB; ++c) sh.Ls[i][c] = (c < i && i < jb) ? a[c] : make_double2(0.0, 0.0);
   }
-  // rows of the pivot block beyond jb (last panel) are the identity
   for (int i = jb + t; i < NB; i += NT)
-    for (int c = 0; c < NB; ++c) {
-      sh.Ls[i][c] = make_double2(0.0, 0.0);
-      sh.Us[i][c] = make_double2(c == i ? 1.0 : 0.0, 0.0);
-    }
+    for (int c = 0; c < NB; ++c) sh.Ls[i][c] = make_double2(0.0, 0.0);
   __syncthreads();
   // ln det contribution and pivot checks (wave 0 holds all jb <= 32 pivots)
-  double lx = 0.0, ly = 0.0, nsw = 0.0, badv = 0.0;
+  double lx = 0.0, ly = 0.0, badv = 0.0;
   if (t < jb) {
     const double2 pv = sh.pivv[t];
     const double2 lg = clog(pv);
     lx = lg.x;
     ly = lg.y;
-    nsw = sh.swapped[t] ? 1.0 : 0.0;
     if (!(cabs2(pv) > 0.0) || !isfinite(pv.x) || !isfinite(pv.y)) badv = 1.0;
   }
-  if (x.wid == 0) {
-    lx = wave_sum(lx); ly = wave_sum(ly); nsw = wave_sum(nsw); badv = wave_sum(badv);
+  if (t < 64) {
+    lx = wave_sum(lx); ly = wave_sum(ly); badv = wave_sum(badv);
   }
   // column t of L11^{-1} by forward substitution on e_t
   double2* tri = p.tri + (long long)w * NB * NB;
@@ -213,40 +148,218 @@ __global__ __launch_bounds__(NT) void panel_kernel(PanelParams p) {
       for (int k = 0; k < i; ++k) v = cfnms(v, sh.Ls[i][k], xcol[k]);
       xcol[i] = v;
     }
-    if (!p.gj) {
 #pragma unroll
-      for (int i = 0; i < NB; ++i) tri[i * NB + t] = xcol[i];
-    } else {
-      // threads 0..NB-1 are one wave: every read of Ls above precedes these writes
+    for (int i = 0; i < NB; ++i) tri[i * NB + t] = xcol[i];
+  }
+  if (t == 0) {
+    if (p.lndet) {
+      double2 acc = j0 == 0 ? make_double2(0.0, 0.0) : p.lndet[w];
+      acc.x += lx;
+      acc.y += ly;
+      p.lndet[w] = acc;
+    }
+    if (badv > 0.0 && p.status) p.status[w] = 2;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Gauss-Jordan panel: the pivot block's inverse by in-place elimination inside the column loop.
+//
+// One thread per row holds the row's NB panel entries in registers.  Column C (a runtime
+// loop, so the loop body stays in the instruction cache) picks the pivot p among the rows not
+// yet chosen, then every other row r takes
+//     g = a_r[C] / a_p[C],   a_r[i] -= g a_p[i]  (i != C),   a_r[C] = -g,
+// and the pivot row keeps its entries except a_p[C] = 1.  This is Gauss-Jordan on
+// [A11 | I] stored in place with the pivot rows left unnormalised: after the last column the
+// row chosen for column c holds pv_c times row c of A11^{-1} (A11 = the chosen rows in the
+// order chosen, pv_c its pivot), so one division per row finishes the inverse.  Rows never
+// chosen carry the same updates and are discarded.  The pivots equal those of LU with the
+// same partial pivoting.
+
+// Maximum over the wave, uniform: row maxima by DPP, then the four row results by readlane.
+FT_DEV double wave_max_uniform(double v) {
+  v = fmax(v, dpp_d<0xB1>(v));
+  v = fmax(v, dpp_d<0x4E>(v));
+  v = fmax(v, dpp_d<0x124>(v));
+  v = fmax(v, dpp_d<0x128>(v));
+  double r[4];
 #pragma unroll
-      for (int i = 0; i < NB; ++i) sh.Ls[i][t] = xcol[i];
-      sh.rpiv[t] = cdiv(make_double2(1.0, 0.0), sh.Us[t][t]);
+  for (int q = 0; q < 4; ++q)
+    r[q] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 16 * q),
+                            __builtin_amdgcn_readlane(__double2loint(v), 16 * q));
+  return fmax(fmax(r[0], r[1]), fmax(r[2], r[3]));
+}
+
+constexpr int GJ_CH = 8;              // panel columns staged through LDS per step of the load
+
+template <int NT>
+struct GjShared {
+  double2 stage[NT][GJ_CH];         // coalesced load of the panel
+  double2 candRow[2][NT / 64][NB];  // each wave's best row, double-buffered by column parity
+  double candVal[2][NT / 64];
+  int candIdx[2][NT / 64];
+  double2 pivv[NB];                 // pivots of this panel
+  int swapped[NB];
+};
+
+// 1 / b by Smith's scaling (two real divisions), for the one pivot of a column.
+FT_DEV double2 crecip(double2 b) {
+  if (fabs(b.x) >= fabs(b.y)) {
+    const double r = b.y / b.x, s = 1.0 / (b.x + b.y * r);
+    return make_double2(s, -r * s);
+  } else {
+    const double r = b.x / b.y, s = 1.0 / (b.y + b.x * r);
+    return make_double2(r * s, -s);
+  }
+}
+
+// One workgroup per walker: rows [j0, M) x panel columns [j0, j0+jb).  Writes the pivot rows
+// (piv), A11^{-1} (tri, [NB][NB], the leading jb x jb used), ln det and the status; the panel
+// columns in memory are left as they are.
+template <int NT>
+__global__ __launch_bounds__(NT) void panel_gj_kernel(PanelParams p) {
+  __shared__ GjShared<NT> sh;
+  const int w = blockIdx.x;
+  if (w >= p.W) return;
+  double2* aug = p.aug + (long long)w * p.stride;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int M = p.M, j0 = p.j0, jb = p.jb, lda = p.lda;
+  const int r = j0 + t;                    // M - j0 <= NT
+  // a[k] holds panel column (C + k) mod NB while column C is processed: the row rotates by one
+  // entry per column, so every register index is static; after NB steps it is back in order.
+  double2 a[NB];
+  {
+    // the panel goes through LDS GJ_CH columns at a time: consecutive lanes read consecutive
+    // entries of a row (coalesced), then every thread takes its own row from LDS
+    const int rows = M - j0;
+#pragma unroll
+    for (int q = 0; q < NB / GJ_CH; ++q) {
+#pragma unroll
+      for (int e0 = 0; e0 < GJ_CH; ++e0) {
+        const int e = t + e0 * NT, rr = e / GJ_CH, c = q * GJ_CH + e % GJ_CH;
+        sh.stage[rr][e % GJ_CH] = (rr < rows && c < jb) ? aug[(long long)(j0 + rr) * lda + j0 + c] : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < GJ_CH; ++c) a[q * GJ_CH + c] = sh.stage[t][c];
+      __syncthreads();
     }
   }
-  if (p.gj) {
+  int* piv = p.piv + (long long)w * p.ld;
+  int myrow = r;
+  bool chosen = false;
+  double2 mypv = make_double2(1.0, 0.0);
+  // one column: a[0] is column C on entry; the row rotates by one entry on exit
+  auto column = [&](int C) {
+    const int col = j0 + C, buf = C & 1;
+    const double2 f = a[0];
+    const bool cand = myrow >= col && myrow < M;
+    double bv = cand ? cabs2(f) : -1.0;
+    if (!(bv == bv)) bv = -1.0;            // a NaN entry never wins the search
+    const double mv = wave_max_uniform(bv);
+    const unsigned long long hit = __ballot(cand && bv == mv && mv >= 0.0);
+    if (hit) {
+      const int lead = __ffsll((long long)hit) - 1;   // lowest lane among the maxima
+      if (lane == lead) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) sh.candRow[buf][wid][i] = a[i];
+        sh.candVal[buf][wid] = mv;
+        sh.candIdx[buf][wid] = myrow;
+      }
+    } else if (lane == 0) {
+      sh.candVal[buf][wid] = -1.0;
+      sh.candIdx[buf][wid] = INT_MAX;
+    }
     __syncthreads();
-    // column t of U11^{-1} by back substitution on e_t (again one wave, in place)
-    if (t < NB) {
-      double2 xcol[NB];
+    double bvv = sh.candVal[buf][0];
+    int bi = sh.candIdx[buf][0], win = 0;
 #pragma unroll
-      for (int i = NB - 1; i >= 0; --i) {
-        double2 v = make_double2(i == t ? 1.0 : 0.0, 0.0);
+    for (int k = 1; k < NT / 64; ++k) {
+      const double v = sh.candVal[buf][k];
+      const int ix = sh.candIdx[buf][k];
+      if (v > bvv || (v == bvv && ix < bi)) { bvv = v; bi = ix; win = k; }
+    }
+    // no usable pivot (every candidate NaN): the walker is marked failed and the column keeps
+    // its row, so that the row exchanges stay a valid permutation; nothing is updated
+    const bool ok = bvv >= 0.0;
+    const double2* pr = sh.candRow[buf][win];
+    const int prow = ok ? bi : col;
+    const double2 pv = ok ? pr[0] : make_double2(NAN, NAN);
+    if (t == 0) {
+      piv[col] = prow;
+      sh.pivv[C] = pv;
+      sh.swapped[C] = prow != col;
+    }
+    const bool ispiv = ok && myrow == prow;
+    if (ispiv) { myrow = col; chosen = true; mypv = pv; }
+    else if (ok && myrow == col) myrow = prow;
+    // branch-free: the pivot row and padding rows take g = 0 and keep their entries (a failed
+    // column leaves garbage in a walker that is marked failed)
+    const bool upd = ok && r < M && !ispiv;
+    const double2 q = cmul(f, crecip(pv));
+    const double2 g = upd ? q : make_double2(0.0, 0.0);
+    // eight entries at a time, the reads of the next eight in flight during the updates (the
+    // pivot row's reads are not all hoisted at once)
+    double2 pb[2][8];
 #pragma unroll
-        for (int k = i + 1; k < NB; ++k) v = cfnms(v, sh.Us[i][k], xcol[k]);
-        xcol[i] = cmul(v, sh.rpiv[i]);
+    for (int i = 0; i < 8; ++i) pb[0][i] = pr[1 + i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k < 3) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (9 + 8 * k + i < NB) pb[(k + 1) & 1][i] = pr[9 + 8 * k + i];
       }
 #pragma unroll
-      for (int i = 0; i < NB; ++i) sh.Us[i][t] = xcol[i];
+      for (int i = 0; i < 8; ++i)
+        if (1 + 8 * k + i < NB) a[1 + 8 * k + i] = cfnms(a[1 + 8 * k + i], g, pb[k & 1][i]);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    __syncthreads();
-    // A11^{-1} = U11^{-1} L11^{-1}
-    for (int e = t; e < NB * NB; e += NT) {
-      const int i = e / NB, j = e - i * NB;
-      double2 acc = make_double2(0.0, 0.0);
-      for (int k = (i > j ? i : j); k < NB; ++k) acc = cadd(acc, cmul(sh.Us[i][k], sh.Ls[k][j]));
-      tri[e] = acc;
-    }
+    const double2 a0 = upd ? make_double2(-g.x, -g.y) : (ispiv ? make_double2(1.0, 0.0) : f);
+#pragma unroll
+    for (int i = 0; i < NB - 1; ++i) a[i] = a[i + 1];
+    a[NB - 1] = a0;
+  };
+  int C = 0;
+#pragma unroll 1
+  for (; C + 4 <= jb; C += 4) {
+    column(C);
+    column(C + 1);
+    column(C + 2);
+    column(C + 3);
   }
+#pragma unroll 1
+  for (; C < jb; ++C) column(C);
+#pragma unroll 1
+  for (; C < NB; ++C) {                   // the zero columns beyond jb only rotate
+    const double2 a0 = a[0];
+#pragma unroll
+    for (int i = 0; i < NB - 1; ++i) a[i] = a[i + 1];
+    a[NB - 1] = a0;
+  }
+  // the row chosen for column c holds pv_c times row c of A11^{-1}
+  double2* tri = p.tri + (long long)w * NB * NB;
+  if (chosen) {
+    const int c = myrow - j0;
+    const double2 s = crecip(mypv);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) tri[c * NB + i] = i < jb ? cmul(a[i], s) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();                         // pivv / swapped of the last column
+  // ln det contribution and pivot checks (wave 0 holds all jb <= 32 pivots)
+  double lx = 0.0, ly = 0.0, nsw = 0.0, badv = 0.0;
+  if (t < jb) {
+    const double2 pv = sh.pivv[t];
+    const double2 lg = clog(pv);
+    lx = lg.x;
+    ly = lg.y;
+    nsw = sh.swapped[t] ? 1.0 : 0.0;
+    if (!(cabs2(pv) > 0.0) || !isfinite(pv.x) || !isfinite(pv.y)) badv = 1.0;
+  }
+  if (wid == 0) {
+    lx = wave_sum(lx); ly = wave_sum(ly); nsw = wave_sum(nsw); badv = wave_sum(badv);
+  }
+  const bool bad = badv > 0.0;
   if (t == 0) {
     if (p.lndet) {
       double2 acc = j0 == 0 ? make_double2(0.0, 0.0) : p.lndet[w];
@@ -254,7 +367,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(PanelParams p) {
       acc.y += ly + 3.14159265358979323846 * nsw;
       p.lndet[w] = acc;
     }
-    if (badv > 0.0 && p.status) p.status[w] = 2;
+    if (bad && p.status) p.status[w] = 2;
   }
 }
 
@@ -319,6 +432,7 @@ size_t elim_tri_elems(int) { return (size_t)NB * NB; }
 hipError_t launch_elim(const ElimParams& e, hipStream_t s) {
   if (e.W <= 0 || e.M <= 0) return hipSuccess;
   if (e.M > 512 || !e.tri) return hipErrorInvalidValue;
+  if ((e.pivot != 0) != (e.backsub != 0)) return hipErrorInvalidValue;   // the two modes built
   const int M = e.M;
   const int cend = e.rhs_off + e.nrhs;   // trailing columns run up to the end of the right-hand sides
   const bool gj = e.backsub != 0;        // a solve: Gauss-Jordan, no back substitution
@@ -330,10 +444,17 @@ hipError_t launch_elim(const ElimParams& e, hipStream_t s) {
   for (int j0 = 0; j0 < M; j0 += NB) {
     const int jb = M - j0 < NB ? M - j0 : NB;
     p.j0 = j0; p.jb = jb;
-    if (M - j0 <= 64) panel_kernel<64><<<e.W, 64, 0, s>>>(p);
-    else if (M - j0 <= 128) panel_kernel<128><<<e.W, 128, 0, s>>>(p);
-    else if (M - j0 <= 256) panel_kernel<256><<<e.W, 256, 0, s>>>(p);
-    else panel_kernel<512><<<e.W, 512, 0, s>>>(p);
+    if (gj) {
+      if (M - j0 <= 64) panel_gj_kernel<64><<<e.W, 64, 0, s>>>(p);
+      else if (M - j0 <= 128) panel_gj_kernel<128><<<e.W, 128, 0, s>>>(p);
+      else if (M - j0 <= 256) panel_gj_kernel<256><<<e.W, 256, 0, s>>>(p);
+      else panel_gj_kernel<512><<<e.W, 512, 0, s>>>(p);
+    } else {
+      if (M - j0 <= 64) panel_kernel<64><<<e.W, 64, 0, s>>>(p);
+      else if (M - j0 <= 128) panel_kernel<128><<<e.W, 128, 0, s>>>(p);
+      else if (M - j0 <= 256) panel_kernel<256><<<e.W, 256, 0, s>>>(p);
+      else panel_kernel<512><<<e.W, 512, 0, s>>>(p);
+    }
     if ((err = hipGetLastError()) != hipSuccess) return err;
     const int c0 = j0 + jb;
     const int ncols = cend - c0;

@@ -243,6 +243,8 @@ typedef Tile<32, 32, 16, 16, 16> T32x32;     // 4 waves of 16 x 16
 // 64-row / 64- or 128-column workgroup tile still shares every LDS-staged operand.
 typedef Tile<64, 64, 16, 16, 16> T64x64w16;
 typedef Tile<64, 128, 16, 16, 32> T64x128w16;
+// dense linear algebra with at most 32 result rows (the pivot-block products): 8 waves
+typedef Tile<32, 64, 16, 16, 16> T32x64w8;
 
 template <typename TA, typename TB, typename TC, typename ACC, int ROLE, typename TL>
 hipError_t launch_tile(GemmParams p, hipStream_t s) {
@@ -279,6 +281,7 @@ hipError_t launch_zgemm(const GemmParams& p, int prec, hipStream_t s) {
     case 2 * GEMM_Z64:       // complex128 in and out, FP64 MFMA (propagator chain)
       return launch_shape<double2, double2, double2, double, 0>(p, s);
     case 2 * GEMM_Z64 + 1:   // the same for the dense linear algebra (64 x 64 tiles, 16 waves)
+      if (p.mpad <= 32) return launch_tile<double2, double2, double2, double, 1, T32x64w8>(p, s);
       return launch_tile<double2, double2, double2, double, 1, T64x64w16>(p, s);
     case 2 * GEMM_C32:       // complex64 in and out, FP32 MFMA
       return launch_shape<float2, float2, float2, float, 0>(p, s);

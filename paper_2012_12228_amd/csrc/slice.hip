@@ -159,19 +159,37 @@ __global__ __launch_bounds__(NT) void greens_post_kernel(SysDev s, int k) {
   }
 }
 
-// r_Q = sum over pairs K_p - K_r = Q of P_pr = -G_rp; ln det(I + A_k); phaseless weight.
+// r_Q = sum over pairs K_p - K_r = Q of P_pr = -G_rp: one Q per thread, NT Q per workgroup, the
+// workgroups of a walker on one XCD (its G stays in that L2); four partial sums keep several
+// gathers in flight.
+__global__ __launch_bounds__(NT) void rq_kernel(SysDev s, int chunks) {
+  int w, c;
+  if (!xcd_walker_tile(blockIdx.x, s.W, chunks, &w, &c)) return;
+  const int q = c * NT + threadIdx.x;
+  if (q >= s.NQ) return;
+  const double2* G = s.G + (long long)w * s.mat_stride;
+  const int e0 = s.qptr[q], e1 = s.qptr[q + 1];
+  double2 a0 = zero2(), a1 = zero2(), a2 = zero2(), a3 = zero2();
+  int e = e0;
+  for (; e + 4 <= e1; e += 4) {
+    const int i0 = s.qpair[e], i1 = s.qpair[e + 1], i2 = s.qpair[e + 2], i3 = s.qpair[e + 3];
+    a0 = csub(a0, G[i0]); a1 = csub(a1, G[i1]); a2 = csub(a2, G[i2]); a3 = csub(a3, G[i3]);
+  }
+  for (; e < e1; ++e) a0 = csub(a0, G[s.qpair[e]]);
+  s.r[(long long)w * s.NQ + q] = cadd(cadd(a0, a1), cadd(a2, a3));
+}
+
+// ln det(I + A_k) and the phaseless weight (after rq_kernel).
 __global__ __launch_bounds__(NT) void weight_kernel(SysDev s, int k, double sum_lnLb, int init) {
   __shared__ double red[8];
   const int w = blockIdx.x;
   if (w >= s.W) return;
   const double2* G = s.G + (long long)w * s.mat_stride;
-  double2* r = s.r + (long long)w * s.NQ;
+  const double2* r = s.r + (long long)w * s.NQ;
   double bad = 0.0;
   for (int q = threadIdx.x; q < s.NQ; q += NT) {
-    double2 acc = zero2();
-    for (int e = s.qptr[q]; e < s.qptr[q + 1]; ++e) acc = csub(acc, G[s.qpair[e]]);
-    r[q] = acc;
-    if (!isfinite(acc.x) || !isfinite(acc.y)) bad = 1.0;
+    const double2 v = r[q];
+    if (!isfinite(v.x) || !isfinite(v.y)) bad = 1.0;
   }
   double sdb = 0.0;
   const double* D = s.D + (long long)w * s.ld;
@@ -549,6 +567,10 @@ hipError_t launch_greens_post(const SysDev& s, int k, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_weight(const SysDev& s, int k, double sum_lnLb, int init, hipStream_t st) {
+  const int chunks = (s.NQ + NT - 1) / NT;
+  rq_kernel<<<tiles_blocks(s, chunks), NT, 0, st>>>(s, chunks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   weight_kernel<<<s.W, NT, 0, st>>>(s, k, sum_lnLb, init);
   return hipGetLastError();
 }
