@@ -40,8 +40,15 @@ struct PanelParams {
   int gj;         // Gauss-Jordan: keep the panel columns, return A11^{-1} instead of L11^{-1}
   int* piv; int ld;
   double2* lndet; int* status;
-  double2* tri;   // [W][NB][NB] L11^{-1} (forward) or A11^{-1} (Gauss-Jordan) of this panel
+  double2* tri;   // [W][tri_stride]: NB x NB L11^{-1} (forward) or A11^{-1} (Gauss-Jordan) at tri
+  long long tri_stride;
 };
+
+// Per-walker pivot-block workspace (complex entries from the walker's start): the inverses of
+// the two 32-column sub-panels of a 64-column Gauss-Jordan step, then the combined operator.
+constexpr long long TRI_T1 = 0, TRI_T2 = NB * NB, TRI_TL = 2 * NB * NB;
+constexpr long long TRI_ELEMS = 2 * NB * NB + 4 * NB * NB;
+constexpr int GJ_WIDE_MIN_M = 256;      // 64-column Gauss-Jordan steps above this order (measured)
 
 template <int NT>
 struct PanelShared {
@@ -138,7 +145,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(PanelParams p) {
     lx = wave_sum(lx); ly = wave_sum(ly); badv = wave_sum(badv);
   }
   // column t of L11^{-1} by forward substitution on e_t
-  double2* tri = p.tri + (long long)w * NB * NB;
+  double2* tri = p.tri + (long long)w * p.tri_stride;
   if (t < NB) {
     double2 xcol[NB];
 #pragma unroll
@@ -338,7 +345,7 @@ __global__ __launch_bounds__(NT) void panel_gj_kernel(PanelParams p) {
     a[NB - 1] = a0;
   }
   // the row chosen for column c holds pv_c times row c of A11^{-1}
-  double2* tri = p.tri + (long long)w * NB * NB;
+  double2* tri = p.tri + (long long)w * p.tri_stride;
   if (chosen) {
     const int c = myrow - j0;
     const double2 s = crecip(mypv);
@@ -368,6 +375,59 @@ __global__ __launch_bounds__(NT) void panel_gj_kernel(PanelParams p) {
       p.lndet[w] = acc;
     }
     if (bad && p.status) p.status[w] = 2;
+  }
+}
+
+// Combined operator of a 64-column Gauss-Jordan step from its two 32-column halves.  With the
+// first half's pivot block A11 (inverse T1), the second half's pivot rows A21 (original values
+// in the first half's columns) and the inverse T2 of the second half's block after the first
+// half's step, the pivot rows' trailing entries R1, R2 become
+//     X = [[T1, 0], [-T2 A21 T1, T2]] [R1; R2]
+// (X1 = T1 R1 is the first half's result, X2 the second's); every other row takes
+// row -= A_i,[j0, j0+kb) X, and the first half's rows then take X1 - P1 X2 with P1 = T1 A12.
+// One workgroup per walker; writes the kb x kb operator (row stride 2 NB) at TRI_TL.
+struct CombineParams {
+  const double2* aug; long long stride; int lda;
+  double2* tri; long long tri_stride;
+  int j0, jb2, W;
+};
+
+__global__ __launch_bounds__(256) void gj_combine_kernel(CombineParams c) {
+  __shared__ double2 T1[NB][NB + 1], A21[NB][NB + 1], T2[NB][NB + 1], M21[NB][NB + 1];
+  const int w = blockIdx.x;
+  if (w >= c.W) return;
+  double2* tri = c.tri + (long long)w * c.tri_stride;
+  const double2* aug = c.aug + (long long)w * c.stride;
+  const int t = threadIdx.x, jb2 = c.jb2, j0 = c.j0;
+  for (int e = t; e < NB * NB; e += 256) {
+    const int i = e / NB, j = e - i * NB;
+    T1[i][j] = tri[TRI_T1 + e];
+    T2[i][j] = (i < jb2 && j < jb2) ? tri[TRI_T2 + e] : make_double2(0.0, 0.0);
+    A21[i][j] = i < jb2 ? aug[(long long)(j0 + NB + i) * c.lda + j0 + j] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int e = t; e < NB * NB; e += 256) {   // M21 = A21 T1
+    const int i = e / NB, j = e - i * NB;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int k = 0; k < NB; ++k) acc = cadd(acc, cmul(A21[i][k], T1[k][j]));
+    M21[i][j] = acc;
+  }
+  __syncthreads();
+  double2* tl = tri + TRI_TL;
+  for (int e = t; e < 4 * NB * NB; e += 256) {
+    const int i = e / (2 * NB), j = e - i * (2 * NB);
+    double2 v = make_double2(0.0, 0.0);
+    if (i < NB) {
+      if (j < NB) v = T1[i][j];
+    } else if (i - NB < jb2) {
+      const int ii = i - NB;
+      if (j < NB) {
+        for (int k = 0; k < jb2; ++k) v = cfnms(v, T2[ii][k], M21[k][j]);
+      } else if (j - NB < jb2) {
+        v = T2[ii][j - NB];
+      }
+    }
+    tl[e] = v;
   }
 }
 
@@ -415,9 +475,9 @@ GemmParams update_params(const ElimParams& e, int row0, int nrows, int k0, int k
 }
 
 // aug[row0..row0+kb, col0..] <- T aug[row0..row0+kb, col0..] with a per-walker kb x kb T (in place)
-GemmParams tri_params(const ElimParams& e, const double2* T, long long sT, int row0, int kb, int col0, int ncols) {
+GemmParams tri_params(const ElimParams& e, const double2* T, int ldT, int row0, int kb, int col0, int ncols) {
   GemmParams g = aug_params(e);
-  g.A = T; g.sA = sT; g.lda = NB;
+  g.A = T; g.sA = TRI_ELEMS; g.lda = ldT;
   g.B = e.aug + (long long)row0 * e.lda + col0;
   g.C = e.aug + (long long)row0 * e.lda + col0;
   g.m = kb; g.n = ncols; g.k = kb; g.mpad = kb; g.npad = ncols;
@@ -427,7 +487,92 @@ GemmParams tri_params(const ElimParams& e, const double2* T, long long sT, int r
 
 }  // namespace
 
-size_t elim_tri_elems(int) { return (size_t)NB * NB; }
+size_t elim_tri_elems(int) { return (size_t)TRI_ELEMS; }
+
+namespace {
+
+template <typename K64, typename K128, typename K256, typename K512>
+hipError_t launch_panel(int rows, int W, const PanelParams& p, hipStream_t s, K64 k64, K128 k128, K256 k256, K512 k512) {
+  if (rows <= 64) k64<<<W, 64, 0, s>>>(p);
+  else if (rows <= 128) k128<<<W, 128, 0, s>>>(p);
+  else if (rows <= 256) k256<<<W, 256, 0, s>>>(p);
+  else k512<<<W, 512, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+hipError_t gj_panel(const PanelParams& p, int M, int W, hipStream_t s) {
+  return launch_panel(M - p.j0, W, p, s, panel_gj_kernel<64>, panel_gj_kernel<128>, panel_gj_kernel<256>,
+                      panel_gj_kernel<512>);
+}
+
+hipError_t swap_rows(const PanelParams& p, int W, int c0, int c1, hipStream_t s) {
+  const int chunks = (c1 - c0 + 255) / 256;
+  swap_kernel<<<W * chunks, 256, 0, s>>>(p, c0, c1, chunks);
+  return hipGetLastError();
+}
+
+// Gauss-Jordan with row pivoting over the augmented matrix.  With `wide`, 64 columns per step
+// where two 32-column panels fit: one trailing update with K = 64 instead of two with K = 32
+// halves the passes over the right-hand columns, for a small combine kernel and two 32-row
+// products.  That pays where the updates are bound by memory traffic (large M); for small M
+// they are bound by the FP64 matrix cores and 32-column steps are faster.
+hipError_t launch_gj(const ElimParams& e, PanelParams p, int cend, bool wide, hipStream_t s) {
+  const int M = e.M;
+  hipError_t err;
+  for (int j0 = 0; j0 < M;) {
+    if (!wide || M - j0 <= NB) {
+      const int jb = M - j0 < NB ? M - j0 : NB, c0 = j0 + jb, ncols = cend - c0;
+      p.j0 = j0; p.jb = jb; p.tri = e.tri + TRI_T1;
+      if ((err = gj_panel(p, M, e.W, s)) != hipSuccess) return err;
+      if ((err = swap_rows(p, e.W, j0, cend, s)) != hipSuccess) return err;   // panel columns too
+      if (ncols > 0) {
+        if ((err = launch_zgemm(tri_params(e, e.tri + TRI_T1, NB, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess) return err;
+        GemmParams g = update_params(e, 0, M, j0, jb, c0, ncols);   // every row but the pivot rows
+        g.skip0 = j0;
+        g.skip1 = j0 + jb;
+        if ((err = launch_zgemm(g, GEMM_Z64, s)) != hipSuccess) return err;
+      }
+      j0 += jb;
+      continue;
+    }
+    const int jb2 = M - j0 - NB < NB ? M - j0 - NB : NB, kb = NB + jb2;
+    const int c2 = j0 + NB;               // the second half's columns [c2, c2 + jb2)
+    // first half: pivots, T1, its step on the second half's columns only
+    p.j0 = j0; p.jb = NB; p.tri = e.tri + TRI_T1;
+    if ((err = gj_panel(p, M, e.W, s)) != hipSuccess) return err;
+    if ((err = swap_rows(p, e.W, j0, cend, s)) != hipSuccess) return err;
+    if ((err = launch_zgemm(tri_params(e, e.tri + TRI_T1, NB, j0, NB, c2, jb2), GEMM_Z64, s)) != hipSuccess) return err;
+    {
+      GemmParams g = update_params(e, 0, M, j0, NB, c2, jb2);
+      g.skip0 = j0;
+      g.skip1 = j0 + NB;
+      if ((err = launch_zgemm(g, GEMM_Z64, s)) != hipSuccess) return err;
+    }
+    // second half: pivots among rows [c2, M), T2; its exchanges cover the first half's columns
+    p.j0 = c2; p.jb = jb2; p.tri = e.tri + TRI_T2;
+    if ((err = gj_panel(p, M, e.W, s)) != hipSuccess) return err;
+    if ((err = swap_rows(p, e.W, j0, cend, s)) != hipSuccess) return err;
+    CombineParams cp;
+    cp.aug = e.aug; cp.stride = e.stride; cp.lda = e.lda; cp.tri = e.tri; cp.tri_stride = TRI_ELEMS;
+    cp.j0 = j0; cp.jb2 = jb2; cp.W = e.W;
+    gj_combine_kernel<<<e.W, 256, 0, s>>>(cp);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    const int c0 = j0 + kb, ncols = cend - c0;
+    if (ncols > 0) {
+      if ((err = launch_zgemm(tri_params(e, e.tri + TRI_TL, 2 * NB, j0, kb, c0, ncols), GEMM_Z64, s)) != hipSuccess) return err;
+      GemmParams g = update_params(e, 0, M, j0, kb, c0, ncols);
+      g.skip0 = j0;
+      g.skip1 = j0 + kb;
+      if ((err = launch_zgemm(g, GEMM_Z64, s)) != hipSuccess) return err;
+      // first half's rows: X1 - P1 X2 (P1 in their second-half columns, X2 in the second half's rows)
+      if ((err = launch_zgemm(update_params(e, j0, NB, c2, jb2, c0, ncols), GEMM_Z64, s)) != hipSuccess) return err;
+    }
+    j0 += kb;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
 
 hipError_t launch_elim(const ElimParams& e, hipStream_t s) {
   if (e.W <= 0 || e.M <= 0) return hipSuccess;
@@ -435,46 +580,26 @@ hipError_t launch_elim(const ElimParams& e, hipStream_t s) {
   if ((e.pivot != 0) != (e.backsub != 0)) return hipErrorInvalidValue;   // the two modes built
   const int M = e.M;
   const int cend = e.rhs_off + e.nrhs;   // trailing columns run up to the end of the right-hand sides
-  const bool gj = e.backsub != 0;        // a solve: Gauss-Jordan, no back substitution
   PanelParams p;
   p.aug = e.aug; p.stride = e.stride; p.lda = e.lda; p.M = M; p.W = e.W; p.pivot = e.pivot;
-  p.piv = e.piv; p.ld = e.ld; p.lndet = e.lndet; p.status = e.status; p.gj = gj ? 1 : 0;
-  p.tri = e.tri;                          // [W][NB][NB]: L11^{-1} (forward) or A11^{-1} (Gauss-Jordan)
+  p.piv = e.piv; p.ld = e.ld; p.lndet = e.lndet; p.status = e.status; p.gj = e.backsub != 0 ? 1 : 0;
+  p.tri = e.tri;
+  p.tri_stride = TRI_ELEMS;
+  if (e.backsub) return launch_gj(e, p, cend, M > GJ_WIDE_MIN_M, s);   // a solve: Gauss-Jordan
   hipError_t err;
   for (int j0 = 0; j0 < M; j0 += NB) {
     const int jb = M - j0 < NB ? M - j0 : NB;
     p.j0 = j0; p.jb = jb;
-    if (gj) {
-      if (M - j0 <= 64) panel_gj_kernel<64><<<e.W, 64, 0, s>>>(p);
-      else if (M - j0 <= 128) panel_gj_kernel<128><<<e.W, 128, 0, s>>>(p);
-      else if (M - j0 <= 256) panel_gj_kernel<256><<<e.W, 256, 0, s>>>(p);
-      else panel_gj_kernel<512><<<e.W, 512, 0, s>>>(p);
-    } else {
-      if (M - j0 <= 64) panel_kernel<64><<<e.W, 64, 0, s>>>(p);
-      else if (M - j0 <= 128) panel_kernel<128><<<e.W, 128, 0, s>>>(p);
-      else if (M - j0 <= 256) panel_kernel<256><<<e.W, 256, 0, s>>>(p);
-      else panel_kernel<512><<<e.W, 512, 0, s>>>(p);
-    }
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if ((err = launch_panel(M - j0, e.W, p, s, panel_kernel<64>, panel_kernel<128>, panel_kernel<256>,
+                            panel_kernel<512>)) != hipSuccess)
+      return err;
     const int c0 = j0 + jb;
     const int ncols = cend - c0;
     if (ncols <= 0) continue;
-    if (e.pivot) {
-      const int s0 = gj ? j0 : c0;        // Gauss-Jordan keeps the panel columns in memory: swap them too
-      const int chunks = (cend - s0 + 255) / 256;
-      swap_kernel<<<e.W * chunks, 256, 0, s>>>(p, s0, cend, chunks);
-      if ((err = hipGetLastError()) != hipSuccess) return err;
-    }
-    if ((err = launch_zgemm(tri_params(e, e.tri, (long long)NB * NB, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
+    if ((err = launch_zgemm(tri_params(e, e.tri + TRI_T1, NB, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
       return err;
-    if (gj) {
-      GemmParams g = update_params(e, 0, M, j0, jb, c0, ncols);   // every row but the pivot rows
-      g.skip0 = j0;
-      g.skip1 = j0 + jb;
-      if ((err = launch_zgemm(g, GEMM_Z64, s)) != hipSuccess) return err;
-    } else if (M - c0 > 0 && (err = launch_zgemm(update_params(e, c0, M - c0, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess) {
+    if (M - c0 > 0 && (err = launch_zgemm(update_params(e, c0, M - c0, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
       return err;
-    }
   }
   return hipSuccess;
 }

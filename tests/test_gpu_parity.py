@@ -127,6 +127,24 @@ def test_ragged_m57_every_slice_stabilised_and_kscale_mu():
         check_walker(rec["trace"].cpu().numpy()[:, w], rec["logw"].cpu().numpy()[:, w], G[w], ref, label=w)
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_m257_wide_gauss_jordan_steps(precision):
+    """M = 257: above the order where the Green's function solve takes 64-column Gauss-Jordan
+    steps (two 32-column panels, one K = 64 update); the last step is 32 + 1 columns."""
+    F = _F()
+    sd = dict(n_elec=66, rs=1.0, theta=0.5, nmax2=16, dtau=0.1, stab_every=4, walkers=2, precision=precision)
+    s = oracle_system(sd)
+    assert s.M == 257
+    flds = si.fields(2571, sd["walkers"], s.n_slices, s.NQ)
+    ctx, _ = gpu_run(F, [sd], [flds])
+    rec = ctx.records()
+    G = ctx.greens().cpu().numpy()
+    for w in range(sd["walkers"]):
+        ref = path.run_walker(s, flds[w], energy_fn=energy.local_energy)
+        check_walker(rec["trace"].cpu().numpy()[:, w], rec["logw"].cpu().numpy()[:, w], G[w], ref,
+                     mixed=precision == 1, label=w)
+
+
 def test_single_walker_stabilised_only_at_the_end():
     F = _F()
     sd = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=1000, walkers=1)
