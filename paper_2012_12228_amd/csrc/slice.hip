@@ -413,39 +413,58 @@ __global__ __launch_bounds__(NT) void stab_finish_b_kernel(SysDev s) {
 
 // ---------------------------------------------------------------- energy ---
 // Exchange: sum_Q v_Q Lambda_Q = sum_{a != d} v(K_a - K_d) sum_b P_ab P_cd with
-// K_c = K_b - (K_a - K_d), P = I - G^T.  One workgroup per (walker, a).
+// K_c = K_b - (K_a - K_d), P = I - G^T.  One workgroup per (walker, a), the d shared over the
+// waves, b over the lanes; the lookup tables sit in LDS and each lane's (at most 8) gathers
+// of row d are issued together.
+template <int EX_B>                                 // b per lane: M <= 64 EX_B
 __global__ __launch_bounds__(NT) void exchange_kernel(SysDev s) {
   extern __shared__ char dyn[];
+  const int M = s.M, ld = s.ld;
   double2* pcol = (double2*)dyn;                    // [M]: P_ab = delta_ab - G_ba
-  short* grid = (short*)(pcol + s.M);               // [grid_dim^3]
+  int* flat = (int*)(pcol + M);                     // [M]
+  short* grid = (short*)(flat + M);                 // [grid_dim^3]
   __shared__ double red[8];
   int w, a;
   if (!xcd_walker_tile(blockIdx.x, s.W, s.M, &w, &a)) return;
   const double2* G = s.G + (long long)w * s.mat_stride;
-  const int M = s.M, ld = s.ld;
   const int g3 = s.grid_dim * s.grid_dim * s.grid_dim;
   for (int e = threadIdx.x; e < g3; e += NT) grid[e] = s.grid[e];
   for (int b = threadIdx.x; b < M; b += NT) {
     double2 v = cscale(G[(long long)b * ld + a], -1.0);
     if (b == a) v.x += 1.0;
     pcol[b] = v;
+    flat[b] = s.flat[b];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // this lane's b and their grid offsets do not depend on d
+  int fb[EX_B];
+  double2 pb[EX_B];
+#pragma unroll
+  for (int k = 0; k < EX_B; ++k) {
+    const int b = lane + 64 * k;
+    fb[k] = b < M ? flat[b] - flat[a] + s.grid_c0 : -1;
+    pb[k] = b < M ? pcol[b] : zero2();
+  }
   double2 acc = zero2();
-  for (int d = wid; d < M; d += 4) {
+  for (int d = wid; d < M; d += NT / 64) {
     if (d == a) continue;
     const double v = s.vq[s.idx[a * M + d]];
     const double2* Gd = G + (long long)d * ld;
-    // grid index of K_b - K_a + K_d is flat[b] + flat[d] - flat[a] + grid_c0
-    const int off = s.flat[d] - s.flat[a] + s.grid_c0;
+    const int fd = flat[d];
+    int c[EX_B];
+    double2 g[EX_B];
+#pragma unroll
+    for (int k = 0; k < EX_B; ++k) c[k] = fb[k] >= 0 ? grid[fb[k] + fd] : -1;   // K_b - K_a + K_d
+#pragma unroll
+    for (int k = 0; k < EX_B; ++k) g[k] = c[k] >= 0 ? Gd[c[k]] : zero2();
     double2 part = zero2();
-    for (int b = lane; b < M; b += 64) {
-      const int c = grid[s.flat[b] + off];
-      if (c >= 0) {
-        double2 pcd = cscale(Gd[c], -1.0);      // P_cd = delta_cd - G_dc
-        if (c == d) pcd.x += 1.0;
-        const double2 pr = cmul(pcol[b], pcd);
+#pragma unroll
+    for (int k = 0; k < EX_B; ++k) {
+      if (c[k] >= 0) {
+        double2 pcd = cscale(g[k], -1.0);           // P_cd = delta_cd - G_dc
+        if (c[k] == d) pcd.x += 1.0;
+        const double2 pr = cmul(pb[k], pcd);
         part.x += pr.x;
         part.y += pr.y;
       }
@@ -598,9 +617,12 @@ hipError_t launch_stab_finish_b(const SysDev& s, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_energy(const SysDev& s, int rec, hipStream_t st) {
-  const size_t shm = (size_t)s.M * sizeof(double2) +
+  const size_t shm = (size_t)s.M * (sizeof(double2) + sizeof(int)) +
                      (size_t)s.grid_dim * s.grid_dim * s.grid_dim * sizeof(short) + 16;
-  exchange_kernel<<<tiles_blocks(s, s.M), NT, shm, st>>>(s);
+  if (s.M <= 64 * 2) exchange_kernel<2><<<tiles_blocks(s, s.M), NT, shm, st>>>(s);
+  else if (s.M <= 64 * 4) exchange_kernel<4><<<tiles_blocks(s, s.M), NT, shm, st>>>(s);
+  else if (s.M <= 64 * 8) exchange_kernel<8><<<tiles_blocks(s, s.M), NT, shm, st>>>(s);
+  else return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   energy_finish_kernel<<<s.W, NT, 0, st>>>(s, rec);

@@ -321,7 +321,7 @@ def test_every_gemm_tile_shape_gives_the_same_path(precision, monkeypatch):
     probe = F.Context([dict(sd, walkers=1)])
     n_tiles = probe.info()["gemm_tile_shapes"]
     probe.close()
-    assert n_tiles >= 7
+    assert n_tiles >= 8
     for tile in range(n_tiles):
         monkeypatch.setenv("FTAFQMC_GEMM_TILE", str(tile))
         ctx, _ = gpu_run(F, [sd], [flds])
