@@ -183,18 +183,30 @@ __global__ __launch_bounds__(NT) void panel_kernel(PanelParams p) {
 // chosen carry the same updates and are discarded.  The pivots equal those of LU with the
 // same partial pivoting.
 
-// Maximum over the wave, uniform: row maxima by DPP, then the four row results by readlane.
-FT_DEV double wave_max_uniform(double v) {
-  v = fmax(v, dpp_d<0xB1>(v));
-  v = fmax(v, dpp_d<0x4E>(v));
-  v = fmax(v, dpp_d<0x124>(v));
-  v = fmax(v, dpp_d<0x128>(v));
-  double r[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    r[q] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 16 * q),
-                            __builtin_amdgcn_readlane(__double2loint(v), 16 * q));
-  return fmax(fmax(r[0], r[1]), fmax(r[2], r[3]));
+// Maximum of an int over the wave, uniform: row maxima by DPP, then the four rows by readlane.
+template <int CTRL> FT_DEV int dpp_i(int v) { return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false); }
+FT_DEV int wave_max_int(int v) {
+  v = max(v, dpp_i<0xB1>(v));     // quad_perm [1,0,3,2]
+  v = max(v, dpp_i<0x4E>(v));     // quad_perm [2,3,0,1]
+  v = max(v, dpp_i<0x124>(v));    // row_ror:4
+  v = max(v, dpp_i<0x128>(v));    // row_ror:8
+  const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+  const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+  return max(max(r0, r1), max(r2, r3));
+}
+
+// 1 / b = conj(b) / |b|^2 with b scaled by a power of two (|b|^2 stays in range) and the
+// hardware reciprocal estimate refined by two Newton steps (quadratic convergence: full double
+// precision).  Zero or non-finite b gives NaN or Inf entries.
+FT_DEV double2 crecip_newton(double2 b) {
+  int e;
+  (void)frexp(fmax(fabs(b.x), fabs(b.y)), &e);
+  const double xs = ldexp(b.x, -e), ys = ldexp(b.y, -e);
+  const double d = xs * xs + ys * ys;
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return make_double2(ldexp(xs * r, -e), ldexp(-ys * r, -e));
 }
 
 constexpr int GJ_CH = 8;              // panel columns staged through LDS per step of the load
@@ -203,7 +215,7 @@ template <int NT>
 struct GjShared {
   double2 stage[NT][GJ_CH];         // coalesced load of the panel
   double2 candRow[2][NT / 64][NB];  // each wave's best row, double-buffered by column parity
-  double candVal[2][NT / 64];
+  int candKey[2][NT / 64];
   int candIdx[2][NT / 64];
   double2 pivv[NB];                 // pivots of this panel
   int swapped[NB];
@@ -261,34 +273,37 @@ __global__ __launch_bounds__(NT) void panel_gj_kernel(PanelParams p) {
     const int col = j0 + C, buf = C & 1;
     const double2 f = a[0];
     const bool cand = myrow >= col && myrow < M;
-    double bv = cand ? cabs2(f) : -1.0;
-    if (!(bv == bv)) bv = -1.0;            // a NaN entry never wins the search
-    const double mv = wave_max_uniform(bv);
-    const unsigned long long hit = __ballot(cand && bv == mv && mv >= 0.0);
+    // search key: the high word of |a|^2 (orders non-negative doubles; candidates equal in their
+    // leading 20 mantissa bits count as ties); -1 for non-candidates and NaN entries
+    const double bv = cabs2(f);
+    const int key = (cand && bv == bv) ? __double2hiint(bv) : -1;
+    const int mk = wave_max_int(key);
+    const unsigned long long hit = __ballot(cand && key == mk && mk >= 0);
     if (hit) {
       const int lead = __ffsll((long long)hit) - 1;   // lowest lane among the maxima
       if (lane == lead) {
 #pragma unroll
         for (int i = 0; i < NB; ++i) sh.candRow[buf][wid][i] = a[i];
-        sh.candVal[buf][wid] = mv;
+        sh.candKey[buf][wid] = mk;
         sh.candIdx[buf][wid] = myrow;
       }
     } else if (lane == 0) {
-      sh.candVal[buf][wid] = -1.0;
+      sh.candKey[buf][wid] = -1;
       sh.candIdx[buf][wid] = INT_MAX;
     }
     __syncthreads();
-    double bvv = sh.candVal[buf][0];
-    int bi = sh.candIdx[buf][0], win = 0;
+    int bk = sh.candKey[buf][0], bi = sh.candIdx[buf][0], win = 0;
 #pragma unroll
     for (int k = 1; k < NT / 64; ++k) {
-      const double v = sh.candVal[buf][k];
-      const int ix = sh.candIdx[buf][k];
-      if (v > bvv || (v == bvv && ix < bi)) { bvv = v; bi = ix; win = k; }
+      const int v = sh.candKey[buf][k], ix = sh.candIdx[buf][k];
+      const bool better = v > bk || (v == bk && ix < bi);
+      bk = better ? v : bk;
+      bi = better ? ix : bi;
+      win = better ? k : win;
     }
     // no usable pivot (every candidate NaN): the walker is marked failed and the column keeps
     // its row, so that the row exchanges stay a valid permutation; nothing is updated
-    const bool ok = bvv >= 0.0;
+    const bool ok = bk >= 0;
     const double2* pr = sh.candRow[buf][win];
     const int prow = ok ? bi : col;
     const double2 pv = ok ? pr[0] : make_double2(NAN, NAN);
@@ -303,7 +318,7 @@ __global__ __launch_bounds__(NT) void panel_gj_kernel(PanelParams p) {
     // branch-free: the pivot row and padding rows take g = 0 and keep their entries (a failed
     // column leaves garbage in a walker that is marked failed)
     const bool upd = ok && r < M && !ispiv;
-    const double2 q = cmul(f, crecip(pv));
+    const double2 q = cmul(f, crecip_newton(pv));
     const double2 g = upd ? q : make_double2(0.0, 0.0);
     // eight entries at a time, the reads of the next eight in flight during the updates (the
     // pivot row's reads are not all hoisted at once)

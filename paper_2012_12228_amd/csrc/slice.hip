@@ -160,7 +160,7 @@ __global__ __launch_bounds__(NT) void greens_post_kernel(SysDev s, int k) {
 }
 
 // r_Q = sum over pairs K_p - K_r = Q of P_pr = -G_rp: one Q per thread, NT Q per workgroup, the
-// workgroups of a walker on one XCD (its G stays in that L2); four partial sums keep several
+// workgroups of a walker on one XCD (its G stays in that L2); eight partial sums keep eight
 // gathers in flight.
 __global__ __launch_bounds__(NT) void rq_kernel(SysDev s, int chunks) {
   int w, c;
@@ -169,14 +169,23 @@ __global__ __launch_bounds__(NT) void rq_kernel(SysDev s, int chunks) {
   if (q >= s.NQ) return;
   const double2* G = s.G + (long long)w * s.mat_stride;
   const int e0 = s.qptr[q], e1 = s.qptr[q + 1];
-  double2 a0 = zero2(), a1 = zero2(), a2 = zero2(), a3 = zero2();
+  double2 acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = zero2();
   int e = e0;
-  for (; e + 4 <= e1; e += 4) {
-    const int i0 = s.qpair[e], i1 = s.qpair[e + 1], i2 = s.qpair[e + 2], i3 = s.qpair[e + 3];
-    a0 = csub(a0, G[i0]); a1 = csub(a1, G[i1]); a2 = csub(a2, G[i2]); a3 = csub(a3, G[i3]);
+  for (; e + 8 <= e1; e += 8) {
+    int ix[8];
+    double2 g[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ix[k] = s.qpair[e + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) g[k] = G[ix[k]];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = csub(acc[k], g[k]);
   }
-  for (; e < e1; ++e) a0 = csub(a0, G[s.qpair[e]]);
-  s.r[(long long)w * s.NQ + q] = cadd(cadd(a0, a1), cadd(a2, a3));
+  for (; e < e1; ++e) acc[0] = csub(acc[0], G[s.qpair[e]]);
+  s.r[(long long)w * s.NQ + q] =
+      cadd(cadd(cadd(acc[0], acc[1]), cadd(acc[2], acc[3])), cadd(cadd(acc[4], acc[5]), cadd(acc[6], acc[7])));
 }
 
 // ln det(I + A_k) and the phaseless weight (after rq_kernel).
