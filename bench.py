@@ -84,7 +84,8 @@ def run_precision(F, torch, systems, fields, steps, warmup):
         for i in range(len(systems)):
             ctx.energy(i)
     torch.cuda.synchronize()
-    ctx.profile(True)
+    # the timed steps carry HIP events around the propagator GEMMs only (the roofline's kernel)
+    ctx.profile(True, classes=["gemm"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -95,10 +96,17 @@ def run_precision(F, torch, systems, fields, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile(False)
+    # one more, untimed step with events around every launch: the per-class breakdown
+    ctx.profile(True)
+    ctx.reset()
+    ctx.propagate(fields)
+    for i in range(len(systems)):
+        ctx.energy(i)
+    classes = ctx.profile(False)
     ws = sum(inf["n_walkers"] * inf["n_slices"] for inf in infos)
     out = {"seconds": t1 - t0, "walker_slices_per_s": ws * steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
-           "profile_ms_per_step": {k: v[0] / steps for k, v in prof.items()},
-           "launches_per_step": {k: v[1] // steps for k, v in prof.items()}}
+           "profile_ms_per_step": {k: v[0] for k, v in classes.items()},
+           "launches_per_step": {k: v[1] for k, v in classes.items()}}
     gemm_ms, gemm_n = prof["gemm"]
     # Propagator products per slice: V^2, V^3, V^4 (with the Taylor blocks), the Horner steps and
     # the apply; 7 in FP64 (degree 16), 6 in mixed (degree 12).  Each walker group of a system

@@ -184,15 +184,18 @@ int ftafqmc_backward(ftafqmc_t h, int sys, int mode, const double* d_cot, void* 
                      double* d_grad, void* d_walker, void* stream);
 
 /* Kernel-class timing with HIP events recorded on the caller's stream around every
- * launch (instrumentation).  enable = 1 starts recording; enable = 0 stops, waits for
- * the recorded events and writes, per class, the summed milliseconds into
- * h_ms[FTAFQMC_PROF_CLASSES] and the launch counts into h_count (host arrays, may be
- * NULL).  Classes: the propagator GEMMs, the Green's-function elimination, the
- * transposes around it, the weight/force-bias kernel, the coefficient/V gather,
+ * launch (instrumentation).  enable = 1 starts recording every class;
+ * enable = FTAFQMC_PROFILE_ONLY | (bit c for each class c) records only those classes (fewer
+ * events in flight: the other launches run as without profiling); any other nonzero value is
+ * E_ARG.  enable = 0 stops, waits for the recorded events and writes, per class, the summed
+ * milliseconds into h_ms[FTAFQMC_PROF_CLASSES] and the launch counts into h_count (host
+ * arrays, may be NULL).  Classes: the propagator GEMMs, the Green's-function elimination,
+ * the transposes around it, the weight/force-bias kernel, the coefficient/V gather,
  * the stabilisation, the energy, the derivative replay (ftafqmc_backward). */
 enum { FTAFQMC_PROF_GEMM = 0, FTAFQMC_PROF_ELIM = 1, FTAFQMC_PROF_GREENS = 2, FTAFQMC_PROF_WEIGHT = 3,
        FTAFQMC_PROF_COEF = 4, FTAFQMC_PROF_STAB = 5, FTAFQMC_PROF_ENERGY = 6, FTAFQMC_PROF_BACKWARD = 7,
        FTAFQMC_PROF_CLASSES = 8 };
+#define FTAFQMC_PROFILE_ONLY 256
 int ftafqmc_profile(ftafqmc_t h, int enable, double* h_ms, long long* h_count);
 
 /* Message of the last error on this handle ("" if none); valid until the next call. */

@@ -22,6 +22,7 @@ WALKER_ALIVE, WALKER_KILLED, WALKER_NUMERIC = 0, 1, 2
 FTAFQMC_CHECKPOINT = 1     # params flag: record the path for ftafqmc_backward
 FTAFQMC_OVERLAP = 2        # params flag: two walker groups on two streams
 FTAFQMC_GRAPH = 4          # params flag: replay whole-path propagation from a captured HIP graph
+FTAFQMC_PROFILE_ONLY = 256  # ftafqmc_profile: record only the classes in the low bits
 FROZEN_PATH = 0            # ftafqmc_backward mode
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NUMERIC", -4: "E_STATE", -5: "E_UNSUPPORTED"}
 
@@ -161,12 +162,20 @@ def ftafqmc_backward(handle, sys, mode, cot, jac, grad, walker, device):
                                            _stream(device)), handle)
 
 
-def ftafqmc_profile(handle, enable):
-    """enable=True starts event timing; enable=False stops and returns {class: (ms, launches)}."""
+def ftafqmc_profile(handle, enable, classes=None):
+    """enable=True starts event timing (every class, or only the class names in `classes`);
+    enable=False stops and returns {class: (ms, launches)}."""
     n = len(PROF_CLASSES)
     ms = (ctypes.c_double * n)()
     cnt = (ctypes.c_longlong * n)()
-    _check(load_library().ftafqmc_profile(handle, 1 if enable else 0, ms, cnt), handle)
+    code = 0
+    if enable:
+        code = 1
+        if classes is not None:
+            code = FTAFQMC_PROFILE_ONLY
+            for c in classes:
+                code |= 1 << PROF_CLASSES.index(c)
+    _check(load_library().ftafqmc_profile(handle, code, ms, cnt), handle)
     if enable:
         return None
     return {PROF_CLASSES[i]: (ms[i], cnt[i]) for i in range(n)}
@@ -250,8 +259,8 @@ class Context:
         ftafqmc_backward(self.handle, sys, FROZEN_PATH, cot, jac, grad, walker, self.device)
         return dict(jac=jac, walker=walker, grad=grad)
 
-    def profile(self, enable):
-        return ftafqmc_profile(self.handle, enable)
+    def profile(self, enable, classes=None):
+        return ftafqmc_profile(self.handle, enable, classes)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -322,6 +322,7 @@ struct ftafqmc_ctx {
   size_t ws_bytes = 0;
   std::string err;
   bool prof = false;
+  unsigned prof_mask = 0;                 // classes recorded while prof is set
   std::vector<ProfEvent> events;
   int groups = 1;                       // streams in use: the caller's and groups - 1 side streams
   static constexpr int MAX_GROUPS = 4;
@@ -347,7 +348,7 @@ namespace {
 
 // Launch f on st; with profiling on, bracket it with two events of class cls.
 template <typename F> hipError_t timed(ftafqmc_ctx* h, int cls, hipStream_t st, F f) {
-  if (!h->prof) return f();
+  if (!h->prof || !((h->prof_mask >> cls) & 1u)) return f();
   ProfEvent ev{cls, nullptr, nullptr};
   hipError_t e = hipEventCreate(&ev.a);
   if (e == hipSuccess) e = hipEventCreate(&ev.b);
@@ -904,7 +905,15 @@ int ftafqmc_backward(ftafqmc_t h, int sys, int mode, const double* d_cot, void* 
 int ftafqmc_profile(ftafqmc_t h, int enable, double* h_ms, long long* h_count) {
   if (!h) return FTAFQMC_E_ARG;
   if (enable) {
+    const unsigned all = (1u << FTAFQMC_PROF_CLASSES) - 1u;
+    unsigned mask;
+    if (enable == 1) mask = all;
+    else if ((enable & ~(int)(FTAFQMC_PROFILE_ONLY | all)) == 0 && (enable & FTAFQMC_PROFILE_ONLY) && (enable & all))
+      mask = (unsigned)enable & all;
+    else
+      return h->set(FTAFQMC_E_ARG, "profile: enable is 1 or FTAFQMC_PROFILE_ONLY with a non-empty class mask");
     h->prof = true;
+    h->prof_mask = mask;
     return FTAFQMC_OK;
   }
   h->prof = false;

@@ -64,7 +64,8 @@ def test_invalid_flags_are_rejected(bad):
 def test_flag_values_match_the_header():
     text = open(HEADER).read()
     for name, val in (("FTAFQMC_CHECKPOINT", F.FTAFQMC_CHECKPOINT), ("FTAFQMC_OVERLAP", F.FTAFQMC_OVERLAP),
-                      ("FTAFQMC_GRAPH", F.FTAFQMC_GRAPH), ("FTAFQMC_FROZEN_PATH", F.FROZEN_PATH)):
+                      ("FTAFQMC_GRAPH", F.FTAFQMC_GRAPH), ("FTAFQMC_FROZEN_PATH", F.FROZEN_PATH),
+                      ("FTAFQMC_PROFILE_ONLY", F.FTAFQMC_PROFILE_ONLY)):
         m = re.search(r"#define\s+%s\s+(\d+)" % name, text)
         assert m and int(m.group(1)) == val, name
 

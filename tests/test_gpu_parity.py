@@ -145,6 +145,32 @@ def test_m257_wide_gauss_jordan_steps(precision):
                      mixed=precision == 1, label=w)
 
 
+def test_profile_class_mask():
+    """Profiling only the GEMM class records only GEMM launches (same count as with every class);
+    values other than 1 or FTAFQMC_PROFILE_ONLY | mask are rejected."""
+    F = _F()
+    sd = dict(si.WORKLOADS["ueg_n14_m19"]["systems"][0], walkers=4)
+    s = oracle_system(sd)
+    flds = torch.from_numpy(si.fields(3, 4, s.n_slices, s.NQ)).cuda()
+    ctx = F.Context(sd)
+    ctx.profile(True)
+    ctx.propagate(flds)
+    full = ctx.profile(False)
+    ctx.reset()
+    ctx.profile(True, classes=["gemm"])
+    ctx.propagate(flds)
+    only = ctx.profile(False)
+    assert only["gemm"][1] == full["gemm"][1] > 0
+    assert all(v[1] == 0 for k, v in only.items() if k != "gemm")
+    assert full["elim"][1] > 0
+    lib = F.load_library()
+    ms = (F.ctypes.c_double * len(F.PROF_CLASSES))()
+    cnt = (F.ctypes.c_longlong * len(F.PROF_CLASSES))()
+    for bad in (2, F.FTAFQMC_PROFILE_ONLY, F.FTAFQMC_PROFILE_ONLY | (1 << 12)):
+        assert lib.ftafqmc_profile(ctx.handle, bad, ms, cnt) != 0
+    ctx.close()
+
+
 def test_single_walker_stabilised_only_at_the_end():
     F = _F()
     sd = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=1000, walkers=1)
