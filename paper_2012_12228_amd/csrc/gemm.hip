@@ -50,8 +50,11 @@ template <> struct Mfma<float> {
 
 template <typename T> FT_DEV double2 ld_c(const T* p) { return to_d2(*p); }
 
+// The 16-wave 64 x 64 propagator tile is held to 8 waves per SIMD (two workgroups per CU): in FP64
+// that costs a few spilled registers and gains 7-10% (M = 171, 485); the dense linear algebra
+// keeps its registers (a spilling update kernel was 24% slower).
 template <typename TA, typename TB, typename TC, typename ACC, int ROLE, typename TL>
-__global__ __launch_bounds__(TL::NT) void zgemm_kernel(GemmParams p) {
+__global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 16 && TL::WN == 16) ? 8 : 1) void zgemm_kernel(GemmParams p) {
   typedef typename cplx_of<ACC>::type cacc;
   typedef typename Mfma<ACC>::acc_t acc_t;
   constexpr int BM = TL::BM, BN = TL::BN, BK = TL::BK, FM = TL::FM, FN = TL::FN, NT = TL::NT;
