@@ -213,6 +213,7 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.piv = (int*)take(sizeof(int) * ld * W);
   d.tri = (double2*)take(sizeof(double2) * elim_tri_elems(M) * W);
   d.r = (double2*)take(sizeof(double2) * (size_t)NQ * W);
+  d.cq = (double2*)take(sizeof(double2) * (size_t)NQ * W);
   d.expo = (double2*)take(sizeof(double2) * W);
   d.ell = (double2*)take(sizeof(double2) * W);
   d.lndetT = (double2*)take(sizeof(double2) * W);
@@ -303,6 +304,7 @@ SysDev walker_view(const HostSys& s, int w0, int nw) {
   v.D += w * ld; v.Dpi += w * ld; v.perm += w * ld; v.piv += w * ld;
   v.tri += w * (long long)elim_tri_elems(s.M);
   v.r += w * s.NQ;
+  v.cq += w * s.NQ;
   v.expo += w; v.ell += w; v.lndetT += w; v.lndetX += w; v.logw += w; v.status += w;
   v.slice_lnS += w * s.n; v.slice_theta += w * s.n;
   v.exch += w * ld; v.local += w * 4; v.scratch += w * ld;

@@ -68,6 +68,7 @@ struct SysDev {
   double* D; double* Dpi; int* perm; int* piv;
   double2* tri;           // [W][elim_tri_elems(M)]
   double2* r;             // [W][NQ] <rho_Q> per spin of the current G
+  double2* cq;            // [W][NQ] shifted coefficients c_Q of the current slice
   double2* expo;          // [W] weight exponent of the current slice
   double2* ell;           // [W] ln det(I + A_k)
   double2* lndetT;        // [W] ln det T

@@ -42,14 +42,14 @@ __global__ __launch_bounds__(NT) void init_state_kernel(SysDev s) {
 // c_Q = i s_Q (z_Q + conj z_{-Q}) - 2 dtau v_Q r_{-Q}: the coefficient of rho(Q) in
 // sqrt(dtau) (x - xbar).v with xbar_A = -2i s_Q (r_Q + r_{-Q}), xbar_B = 2 s_Q (r_Q - r_{-Q}),
 // r_Q = <rho(Q)> per spin; the weight exponent is sum_Q [x.xbar - xbar.xbar/2].
-template <typename TV>
-__global__ __launch_bounds__(NT) void coef_v_kernel(SysDev s, const double2* fields, int k, TV* V) {
-  extern __shared__ double2 csh[];
+// One workgroup per walker: c_Q into cq (and the path record) and the weight exponent.
+__global__ __launch_bounds__(NT) void coef_kernel(SysDev s, const double2* fields, int k) {
   __shared__ double red[8];
   const int w = blockIdx.x;
   if (w >= s.W) return;
   const double2* z = fields + ((long long)w * s.n + k) * s.NQ;
   const double2* r = s.r + (long long)w * s.NQ;
+  double2* cq = s.cq + (long long)w * s.NQ;
   double2 ex = zero2();
   for (int q = threadIdx.x; q < s.NQ; q += NT) {
     const int nq = s.neg[q];
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(NT) void coef_v_kernel(SysDev s, const double2* fie
     double2 c = make_double2(-sqv * u.y, sqv * u.x);
     c.x -= 2.0 * s.dtau * vqv * rn.x;
     c.y -= 2.0 * s.dtau * vqv * rn.y;
-    csh[q] = c;
+    cq[q] = c;
     if (s.rec_c) s.rec_c[((long long)w * s.n + k) * s.NQ + q] = c;
     // xbar_A = -2i s (r_q + r_-q), xbar_B = 2 s (r_q - r_-q)
     const double2 sp = make_double2(rq.x + rn.x, rq.y + rn.y), sm = make_double2(rq.x - rn.x, rq.y - rn.y);
@@ -72,14 +72,24 @@ __global__ __launch_bounds__(NT) void coef_v_kernel(SysDev s, const double2* fie
   }
   ex = block_csum_256(ex, red);
   if (threadIdx.x == 0) s.expo[w] = ex;
-  __syncthreads();
+}
+
+// V_ij = c_{Q = K_i - K_j} (zero on the diagonal and in the padding), V_ROWS rows per
+// workgroup, the workgroups of a walker on one XCD (its c_Q stay in that L2).
+constexpr int V_ROWS = 16;
+template <typename TV>
+__global__ __launch_bounds__(NT) void fill_v_kernel(SysDev s, TV* V, int chunks) {
+  int w, c;
+  if (!xcd_walker_tile(blockIdx.x, s.W, chunks, &w, &c)) return;
+  const double2* cq = s.cq + (long long)w * s.NQ;
   TV* Vw = V + (long long)w * s.mat_stride;
-  const int ld = s.ld, M = s.M;
-  for (int e = threadIdx.x; e < ld * ld; e += NT) {
-    const int i = e / ld, j = e - i * ld;
+  const int ld = s.ld, M = s.M, i0 = c * V_ROWS;
+  for (int e = threadIdx.x; e < V_ROWS * ld; e += NT) {
+    const int i = i0 + e / ld, j = e - (e / ld) * ld;
+    if (i >= ld) break;
     double2 v = zero2();
-    if (i < M && j < M && i != j) v = csh[s.idx[i * M + j]];
-    store_c(Vw + e, v);
+    if (i < M && j < M && i != j) v = cq[s.idx[i * M + j]];
+    store_c(Vw + (long long)i * ld + j, v);
   }
 }
 
@@ -581,9 +591,12 @@ hipError_t launch_init_state(const SysDev& s, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_coef_v(const SysDev& s, const double2* fields, int k, int mixed, hipStream_t st) {
-  const size_t shm = (size_t)s.NQ * sizeof(double2);
-  if (mixed) coef_v_kernel<float2><<<s.W, NT, shm, st>>>(s, fields, k, (float2*)s.V);
-  else coef_v_kernel<double2><<<s.W, NT, shm, st>>>(s, fields, k, (double2*)s.V);
+  coef_kernel<<<s.W, NT, 0, st>>>(s, fields, k);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int chunks = (s.ld + V_ROWS - 1) / V_ROWS;
+  if (mixed) fill_v_kernel<float2><<<tiles_blocks(s, chunks), NT, 0, st>>>(s, (float2*)s.V, chunks);
+  else fill_v_kernel<double2><<<tiles_blocks(s, chunks), NT, 0, st>>>(s, (double2*)s.V, chunks);
   return hipGetLastError();
 }
 hipError_t launch_greens_form(const SysDev& s, int k, hipStream_t st) {
