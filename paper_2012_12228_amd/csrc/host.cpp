@@ -243,6 +243,7 @@ size_t layout(HostSys& s, char* base, size_t off) {
     t.dd.Y = (double2*)take(sizeof(double2) * mat2 * W);
     t.dd.D = (double*)take(sizeof(double) * ld2 * W);
     t.dd.Dpi = (double*)take(sizeof(double) * ld2 * W);
+    t.dd.scratch = (double*)take(sizeof(double) * ld2 * W);   // column norms of the doubled Y
     t.dd.perm = (int*)take(sizeof(int) * ld2 * W);
     t.dd.piv = (int*)take(sizeof(int) * ld2 * W);
     t.dd.tri = (double2*)take(sizeof(double2) * elim_tri_elems(s.M2) * W);

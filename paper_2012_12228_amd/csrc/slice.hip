@@ -249,21 +249,38 @@ __global__ __launch_bounds__(NT) void weight_kernel(SysDev s, int k, double sum_
 }
 
 // ------------------------------------------------------- stabilisation ---
-// Pre-pivoting: order the columns of Y diag(D) by decreasing norm.
+// Column norms |Y e_j| |D_j| into scratch: 64 columns per workgroup, the rows shared by the 4
+// waves; a NaN norm becomes -1 (it ranks last, so ranks stay a permutation).
+__global__ __launch_bounds__(NT) void stab_norm_kernel(SysDev s, int chunks) {
+  __shared__ double part[NT / 64][64];
+  int w, c;
+  if (!xcd_walker_tile(blockIdx.x, s.W, chunks, &w, &c)) return;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int M = s.M, ld = s.ld, j = c * 64 + lane;
+  const double2* Y = s.Y + (long long)w * s.mat_stride;
+  double a = 0.0;
+  if (j < M)
+    for (int i = wid; i < M; i += NT / 64) a += cabs2(Y[(long long)i * ld + j]);
+  part[wid][lane] = a;
+  __syncthreads();
+  if (wid == 0 && j < M) {
+    const double t = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    const double v = sqrt(t) * fabs(s.D[(long long)w * ld + j]);
+    s.scratch[(long long)w * ld + j] = (v == v) ? v : -1.0;
+  }
+}
+
+// Pre-pivoting: order the columns of Y diag(D) by decreasing norm (ties by index); the parity of
+// the permutation (from its inversions) goes into ln det T.
 __global__ __launch_bounds__(NT) void stab_perm_kernel(SysDev s) {
-  extern __shared__ double nrm[];           // [M]
-  __shared__ int parity_sh;
+  extern __shared__ double nrm[];           // [M], then perm [M] as int
+  __shared__ double red[8];
   const int w = blockIdx.x;
   if (w >= s.W) return;
-  const double2* Y = s.Y + (long long)w * s.mat_stride;
   const double* D = s.D + (long long)w * s.ld;
   const int M = s.M, ld = s.ld;
-  for (int j = threadIdx.x; j < M; j += NT) {
-    double a = 0.0;
-    for (int i = 0; i < M; ++i) a += cabs2(Y[(long long)i * ld + j]);
-    const double v = sqrt(a) * fabs(D[j]);
-    nrm[j] = (v == v) ? v : -1.0;   // a NaN norm ranks last, so ranks stay a permutation
-  }
+  int* psh = (int*)(nrm + M);
+  for (int j = threadIdx.x; j < M; j += NT) nrm[j] = s.scratch[(long long)w * ld + j];
   __syncthreads();
   int* perm = s.perm + (long long)w * ld;
   double* Dpi = s.Dpi + (long long)w * ld;
@@ -275,23 +292,19 @@ __global__ __launch_bounds__(NT) void stab_perm_kernel(SysDev s) {
       rank += (u > v || (u == v && i < j)) ? 1 : 0;
     }
     perm[rank] = j;
+    psh[rank] = j;
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < M; j += NT) Dpi[j] = D[perm[j]];
-  if (threadIdx.x == 0) {
-    // parity by counting cycles; visited flags reuse the norm array
-    int par = 0;
-    for (int i = 0; i < M; ++i) nrm[i] = 0.0;
-    for (int i = 0; i < M; ++i) {
-      if (nrm[i] != 0.0) continue;
-      int j = i, len = 0;
-      while (j >= 0 && j < M && nrm[j] == 0.0) { nrm[j] = 1.0; j = perm[j]; ++len; }
-      par += len - 1;
-    }
-    parity_sh = par & 1;
+  double inv = 0.0;
+  for (int j = threadIdx.x; j < M; j += NT) {
+    Dpi[j] = D[psh[j]];
+    const int pj = psh[j];
+    int c = 0;
+    for (int i = 0; i < j; ++i) c += psh[i] > pj ? 1 : 0;
+    inv += (double)c;
   }
-  __syncthreads();
-  if (threadIdx.x == 0 && parity_sh) s.lndetT[w].y += PI;
+  inv = block_sum_256(inv, red);
+  if (threadIdx.x == 0 && ((long long)inv & 1)) s.lndetT[w].y += PI;
 }
 
 // E0 = Y[:, perm]; aug right block = E0^H
@@ -616,7 +629,11 @@ hipError_t launch_weight(const SysDev& s, int k, double sum_lnLb, int init, hipS
   return hipGetLastError();
 }
 hipError_t launch_stab_perm(const SysDev& s, hipStream_t st) {
-  stab_perm_kernel<<<s.W, NT, (size_t)s.M * sizeof(double), st>>>(s);
+  const int chunks = (s.M + 63) / 64;
+  stab_norm_kernel<<<tiles_blocks(s, chunks), NT, 0, st>>>(s, chunks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  stab_perm_kernel<<<s.W, NT, (size_t)s.M * (sizeof(double) + sizeof(int)), st>>>(s);
   return hipGetLastError();
 }
 hipError_t launch_stab_gather(const SysDev& s, hipStream_t st) {

@@ -38,20 +38,19 @@ FT_DEV void split_D(double d, double* db, double* ds) {
 }
 
 // V[w] from the recorded coefficients of slice k (the gather of the forward path).
-__global__ __launch_bounds__(NT) void coef_replay_kernel(SysDev s, int k) {
-  extern __shared__ double2 csh[];
-  const int w = blockIdx.x;
-  if (w >= s.W) return;
+constexpr int RV_ROWS = 16;               // rows of V per workgroup
+__global__ __launch_bounds__(NT) void coef_replay_kernel(SysDev s, int k, int chunks) {
+  int w, ch;
+  if (!xcd_walker_tile(blockIdx.x, s.W, chunks, &w, &ch)) return;
   const double2* c = s.rec_c + ((long long)w * s.n + k) * s.NQ;
-  for (int q = threadIdx.x; q < s.NQ; q += NT) csh[q] = c[q];
-  __syncthreads();
   double2* Vw = (double2*)s.V + (long long)w * s.mat_stride;
-  const int ld = s.ld, M = s.M;
-  for (int e = threadIdx.x; e < ld * ld; e += NT) {
-    const int i = e / ld, j = e - i * ld;
+  const int ld = s.ld, M = s.M, i0 = ch * RV_ROWS;
+  for (int e = threadIdx.x; e < RV_ROWS * ld; e += NT) {
+    const int i = i0 + e / ld, j = e - (e / ld) * ld;
+    if (i >= ld) break;
     double2 v = zero2();
-    if (i < M && j < M && i != j) v = csh[s.idx[i * M + j]];
-    Vw[e] = v;
+    if (i < M && j < M && i != j) v = c[s.idx[i * M + j]];
+    Vw[(long long)i * ld + j] = v;
   }
 }
 
@@ -377,7 +376,8 @@ int grid_for(long long total) {
 }  // namespace
 
 hipError_t launch_coef_replay(const SysDev& s, int k, hipStream_t st) {
-  coef_replay_kernel<<<s.W, NT, (size_t)s.NQ * sizeof(double2), st>>>(s, k);
+  const int chunks = (s.ld + RV_ROWS - 1) / RV_ROWS;
+  coef_replay_kernel<<<((s.W + 7) / 8) * 8 * chunks, NT, 0, st>>>(s, k, chunks);
   return hipGetLastError();
 }
 hipError_t launch_tan_init(const SysDev& s, const TanDev& t, hipStream_t st) {
