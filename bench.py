@@ -150,6 +150,30 @@ def time_graph(F, torch, systems, fields, steps):
     return {"walker_slices_per_s": ws * steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps}
 
 
+def time_overlap(F, torch, systems, fields, steps):
+    """Whole paths with FTAFQMC_OVERLAP (each system's walkers in two groups on two streams, one
+    group's eliminations beside the other's GEMMs), eager, without profiling events.  Reported
+    beside the one-stream value: its per-launch GEMM durations include the other group's
+    kernels, so the roofline stays on the one-stream schedule."""
+    ctx = F.Context([dict(sd, flags=sd.get("flags", 0) | F.FTAFQMC_OVERLAP) for sd in systems])
+    infos = [ctx.info(i) for i in range(len(systems))]
+    ctx.reset()
+    ctx.propagate(fields)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.reset()
+        ctx.propagate(fields)
+        for i in range(len(systems)):
+            ctx.energy(i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.close()
+    ws = sum(inf["n_walkers"] * inf["n_slices"] for inf in infos)
+    return {"walker_slices_per_s": ws * steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
+            "walker_groups": [inf["walker_groups"] for inf in infos]}
+
+
 def time_backward(F, torch, workload="ueg_n38_m123"):
     """Wall time of one frozen-path derivative pass (ftafqmc_backward) on the derivative
     workload, beside the FP64 forward path it differentiates (both with inputs in HBM)."""
@@ -195,6 +219,8 @@ def main():
                     help="also time whole paths replayed from a captured HIP graph (no profiling events)")
     ap.add_argument("--overlap", action="store_true",
                     help="propagate with FTAFQMC_OVERLAP (two walker groups on two streams)")
+    ap.add_argument("--no-overlap-schedule", action="store_true",
+                    help="skip the extra timing of the mixed path with FTAFQMC_OVERLAP")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -234,6 +260,8 @@ def main():
         torch.cuda.empty_cache()
         if args.graph:
             out["graph_replay"] = time_graph(F, torch, systems, fields, args.steps)
+        if p == "mixed" and not args.overlap and not args.no_overlap_schedule:
+            out["overlap_schedule"] = time_overlap(F, torch, systems, fields, args.steps)
     err = None
     if "fp64" in energies and "mixed" in energies:
         errs, nerrs, werrs = [], [], []
