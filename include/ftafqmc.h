@@ -110,10 +110,13 @@ typedef struct {
   int n_measure;    /* energy records so far (one per stabilisation boundary and at slice n) */
   int ld;           /* padded leading dimension used internally */
   double beta, dtau, L, omega, mu_T, mu, e_madelung;
-  int gemm_tile_chain;   /* propagator GEMM tile shape chosen by the start-up autotuner */
+  int gemm_tile_chain;   /* tile shape of the plain Taylor-chain products (V^2, V^3), chosen by
+                            the start-up autotuner */
   int gemm_tile_apply;   /* tile shape of the product that applies e^V */
   int gemm_tile_shapes;  /* number of tile shapes built (valid values of FTAFQMC_GEMM_TILE) */
   int walker_groups;     /* walker groups whose eliminations overlap on separate streams */
+  int gemm_tile_epilogue; /* tile shape of the chain products with epilogue operands (V^4 with
+                             the Taylor blocks, the Horner steps) */
 } ftafqmc_info;
 
 /* Bytes of device workspace needed for the n_sys systems listed in p[0..n_sys-1]

@@ -5,7 +5,8 @@
 // epilogue builds the Paterson-Stockmeyer blocks of the Taylor series of e^V and applies
 // the half-step kinetic factors of the symmetric Trotter propagator (eq. B) without
 // extra passes over memory.  A single epilogue operand is prefetched during the last
-// k-tile; 16 x 16 blocks outside the m x n result issue no MFMAs.
+// k-tile (tiles of at most 4 blocks per wave); 16 x 16 blocks outside the m x n result issue no
+// MFMAs.
 //
 // Tiling: a BM x BN output tile per workgroup of (BM/WM) x (BN/WN) waves, each wave a WM x WN
 // tile of 16 x 16 MFMA blocks; K staged through LDS BK at a time, double-buffered.  Several
@@ -132,11 +133,13 @@ __global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 1
   const TC* P3 = p.P3 ? (const TC*)p.P3 + (long long)w * p.sP : nullptr;
   // One epilogue operand (P1 alone, or C when beta != 0) is loaded during the last k-tile
   // so that its latency overlaps the MFMAs.
-  const bool pre_p1 = P1 && !P2 && !P3 && p.beta == 0.0;
-  const bool pre_c = !P1 && p.beta != 0.0;
+  // (tiles of more than 4 blocks per wave keep no prefetched operand: it would not fit in registers)
+  constexpr bool PREF = FM * FN <= 4;
+  const bool pre_p1 = PREF && P1 && !P2 && !P3 && p.beta == 0.0;
+  const bool pre_c = PREF && !P1 && p.beta != 0.0;
   const TC* PRE = pre_p1 ? P1 : (pre_c ? (const TC*)C : nullptr);
   const int pre_ld = pre_p1 ? p.ldp : p.ldc;
-  TC pre[FM][FN][4];                     // kept in the output precision (complex64 in the mixed path)
+  TC pre[PREF ? FM : 1][PREF ? FN : 1][4];   // kept in the output precision (complex64 in the mixed path)
   const int li = lane & 15, lk = lane >> 4;
   // 16 x 16 blocks entirely outside the m x n result are skipped (uniform per wave)
   bool live[FM][FN];
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 1
           for (int v = 0; v < 4; ++v) {
             const int gi = m0 + wr * TL::WM + i * 16 + Mfma<ACC>::row(lane, v);
             const int gj = n0 + wc * TL::WN + j * 16 + li;
-            pre[i][j][v] = (gi < Mr && gj < Nc) ? PRE[(long long)gi * pre_ld + gj] : TC{};
+            if constexpr (PREF) pre[i][j][v] = (gi < Mr && gj < Nc) ? PRE[(long long)gi * pre_ld + gj] : TC{};
           }
     }
 #pragma unroll
@@ -204,11 +207,11 @@ __global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 1
         double2 q1 = make_double2(0.0, 0.0), q2 = q1, q3 = q1, qc = q1;
         if (in) {
           const long long offp = (long long)gi * p.ldp + gj;
-          if (pre_p1) q1 = to_d2(pre[i][j][v]);
+          if (pre_p1) { if constexpr (PREF) q1 = to_d2(pre[i][j][v]); }
           else if (P1) q1 = ld_c(P1 + offp);
           if (P2) q2 = ld_c(P2 + offp);
           if (P3) q3 = ld_c(P3 + offp);
-          if (pre_c) qc = to_d2(pre[i][j][v]);
+          if (pre_c) { if constexpr (PREF) qc = to_d2(pre[i][j][v]); }
           else if (p.beta != 0.0) qc = ld_c(C + off);
         }
         const double di = (gi == gj) ? 1.0 : 0.0;
@@ -250,6 +253,10 @@ typedef Tile<64, 128, 16, 16, 32> T64x128w16;
 typedef Tile<32, 64, 16, 16, 16> T32x64w8;
 // 8 waves of 16 x 32: fewer workgroup barriers per MFMA (the FP64 products at M ~ 170 prefer it)
 typedef Tile<64, 64, 16, 16, 32> T64x64w8;
+// One walker's whole product at M <= 192 (complex64 only: 101 KB of LDS, 128 VGPRs): 16 waves of
+// 48 x 48 (3 x 3 blocks), nine times the MFMAs per k-tile barrier of the 64 x 64 tile, one
+// workgroup per walker and CU; the 16 x 16 blocks beyond M issue no MFMAs.
+typedef Tile<192, 192, 16, 48, 48> T192w16;
 
 template <typename TA, typename TB, typename TC, typename ACC, int ROLE, typename TL>
 hipError_t launch_tile(GemmParams p, hipStream_t s) {
@@ -272,13 +279,20 @@ hipError_t launch_shape(const GemmParams& p, hipStream_t s) {
     case 5: return launch_tile<TA, TB, TC, ACC, ROLE, T64x64w16>(p, s);
     case 6: return launch_tile<TA, TB, TC, ACC, ROLE, T64x128w16>(p, s);
     case 7: return launch_tile<TA, TB, TC, ACC, ROLE, T64x64w8>(p, s);
+    case 8:
+      if constexpr (sizeof(ACC) == 4) return launch_tile<TA, TB, TC, ACC, ROLE, T192w16>(p, s);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
-int gemm_tile_count() { return 8; }
+int gemm_tile_count() { return 9; }
+bool gemm_tile_supported(int tile, int prec) {
+  if (tile < 0 || tile >= gemm_tile_count()) return false;
+  return tile != 8 || prec == GEMM_C32 || prec == GEMM_C32_Z64B;   // the 192 x 192 tile: FP32 MFMA only
+}
 
 hipError_t launch_zgemm(const GemmParams& p, int prec, hipStream_t s) {
   if (p.m <= 0 || p.n <= 0) return hipSuccess;

@@ -45,7 +45,7 @@ struct HostSys {
   double2* mean = nullptr;
   int k = 0, nrec = 0;
   std::vector<int> rec_slice;
-  int tile_chain = 0, tile_apply = 0;   // GEMM tile shapes chosen by the start-up autotuner
+  int tile_chain = 0, tile_apply = 0, tile_epi = 0;   // GEMM tile shapes chosen by the start-up autotuner
   bool ckpt = false;                    // path recorded for the frozen-path derivative
   int groups = 1;                       // walker groups (streams) of ftafqmc_propagate
   double2* Y0 = nullptr;                // the buffers Y and Ynew start as at every reset
@@ -399,6 +399,7 @@ int form_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st, void*
   g.A = d.V2; g.B = d.V; g.C = d.V3;
   HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));   // V^3
   g.A = d.V2; g.B = d.V2; g.C = d.V4;                                                  // V^4 and the blocks
+  g.tile = s.tile_epi;
   g.P1 = d.V; g.P2 = d.V2; g.P3 = d.V3;
   g.nextra = nb;
   {
@@ -412,7 +413,7 @@ int form_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st, void*
   void* nxt = d.E1;
   for (int k = nb - 2; k >= 0; --k) {
     GemmParams e = gp_base(s, d);
-    e.tile = s.tile_chain;
+    e.tile = s.tile_epi;
     e.A = cur; e.B = d.V4; e.C = nxt;
     e.P1 = d.Bk[k]; e.c1 = 1.0;
     if (k == 0) { e.rs = d.kh; e.cs = d.kh; }            // K e^V K
@@ -479,16 +480,24 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   const size_t velem = mixed ? sizeof(float2) : sizeof(double2);
   const size_t mat = (size_t)s.ld * s.ld * s.p.n_walkers;
   if (const char* env = std::getenv("FTAFQMC_GEMM_TILE")) {
+    // a shape not built for this precision falls back to the timed choice
     const int t = std::atoi(env);
-    if (t >= 0 && t < gemm_tile_count()) { s.tile_chain = s.tile_apply = t; return FTAFQMC_OK; }
+    if (gemm_tile_supported(t, mixed ? GEMM_C32 : GEMM_Z64) && (!mixed || gemm_tile_supported(t, GEMM_C32_Z64B))) {
+      s.tile_chain = s.tile_apply = s.tile_epi = t;
+      return FTAFQMC_OK;
+    }
   }
   HIPCHK(hipMemsetAsync(d.V, 0, velem * mat, st));
+  HIPCHK(hipMemsetAsync(d.V2, 0, velem * mat, st));
+  HIPCHK(hipMemsetAsync(d.V3, 0, velem * mat, st));
   HIPCHK(hipMemsetAsync(d.Ynew, 0, sizeof(double2) * mat, st));
   hipEvent_t a = nullptr, b = nullptr;
   HIPCHK(hipEventCreate(&a));
   HIPCHK(hipEventCreate(&b));
   int rc = FTAFQMC_OK;
-  for (int kind = 0; kind < 2 && rc == FTAFQMC_OK; ++kind) {
+  // kind 0: a plain chain product; 1: the apply; 2: the V^4 product with its three addends and
+  // Taylor-block outputs (the heaviest epilogue, timed for all chain products with addends)
+  for (int kind = 0; kind < 3 && rc == FTAFQMC_OK; ++kind) {
     float best = 1e30f;
     int besti = 0;
     for (int t = 0; t < gemm_tile_count(); ++t) {
@@ -496,7 +505,15 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
       g.tile = t;
       int prec = mixed ? GEMM_C32 : GEMM_Z64;
       if (kind == 0) { g.A = d.V; g.B = d.V; g.C = d.V2; }
-      else { g.A = d.V; g.B = d.Ynew; g.C = d.E1; if (mixed) prec = GEMM_C32_Z64B; }
+      else if (kind == 1) { g.A = d.V; g.B = d.Ynew; g.C = d.E1; if (mixed) prec = GEMM_C32_Z64B; }
+      else {
+        g.A = d.V2; g.B = d.V2; g.C = d.V4; g.P1 = d.V; g.P2 = d.V2; g.P3 = d.V3; g.c1 = 1.0;
+        const int nb = mixed ? 3 : 4;
+        g.nextra = nb;
+        g.extra[0] = GemmOut{d.E0, 1.0, 1.0, 1.0, 1.0, 1.0};
+        for (int k = nb - 2, e = 1; k >= 0; --k, ++e) g.extra[e] = GemmOut{d.Bk[k], 0.0, 1.0, 1.0, 1.0, 1.0};
+      }
+      if (!gemm_tile_supported(t, prec)) continue;
       hipError_t e = launch_zgemm(g, prec, st);                 // warm-up
       if (e == hipSuccess) e = hipEventRecord(a, st);
       for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_zgemm(g, prec, st);
@@ -507,7 +524,9 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
       if (e != hipSuccess) { rc = h->set(FTAFQMC_E_HIP, std::string("autotune: ") + hipGetErrorString(e)); break; }
       if (ms < best) { best = ms; besti = t; }
     }
-    if (kind == 0) s.tile_chain = besti; else s.tile_apply = besti;
+    if (kind == 0) s.tile_chain = besti;
+    else if (kind == 1) s.tile_apply = besti;
+    else s.tile_epi = besti;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
@@ -803,7 +822,7 @@ int ftafqmc_query(ftafqmc_t h, int sys, ftafqmc_info* out) {
   out->slice = s.k; out->n_measure = s.nrec; out->ld = s.ld;
   out->beta = s.beta; out->dtau = s.dtau; out->L = s.L; out->omega = s.omega;
   out->mu_T = s.muT; out->mu = s.mu; out->e_madelung = s.EM;
-  out->gemm_tile_chain = s.tile_chain; out->gemm_tile_apply = s.tile_apply;
+  out->gemm_tile_chain = s.tile_chain; out->gemm_tile_apply = s.tile_apply; out->gemm_tile_epilogue = s.tile_epi;
   out->gemm_tile_shapes = gemm_tile_count();
   out->walker_groups = (int)make_views(s, s.groups).size();
   return FTAFQMC_OK;

@@ -26,6 +26,7 @@ struct GemmParams {
 };
 hipError_t launch_zgemm(const GemmParams& p, int prec, hipStream_t s);
 int gemm_tile_count();
+bool gemm_tile_supported(int tile, int prec);   // shapes built for this precision
 
 // Blocked Gaussian elimination on a per-walker augmented matrix [A | R] (M x M
 // left block, nrhs right-hand sides starting at column rhs_off, row stride lda).
