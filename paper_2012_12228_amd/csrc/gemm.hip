@@ -289,6 +289,7 @@ hipError_t launch_shape(const GemmParams& p, hipStream_t s) {
 }  // namespace
 
 int gemm_tile_count() { return 9; }
+bool gemm_tile_walker_sized(int tile) { return tile == 8; }
 bool gemm_tile_supported(int tile, int prec) {
   if (tile < 0 || tile >= gemm_tile_count()) return false;
   return tile != 8 || prec == GEMM_C32 || prec == GEMM_C32_Z64B;   // the 192 x 192 tile: FP32 MFMA only

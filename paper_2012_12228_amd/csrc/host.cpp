@@ -474,6 +474,8 @@ int greens(ftafqmc_ctx* h, HostSys& s, SysDev& d, int k, int init, hipStream_t s
 // Start-up autotuner: time every GEMM tile shape on this system's real size (W walkers of
 // M x M x M products) for the propagator chain and for the final apply, keep the fastest.
 // FTAFQMC_GEMM_TILE=<index> in the environment forces one shape (for experiments).
+std::vector<SysDev> make_views(const HostSys& s, int ngroups);
+
 int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   SysDev& d = s.dev;
   const bool mixed = s.p.precision == FTAFQMC_MIXED;
@@ -495,6 +497,9 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   HIPCHK(hipEventCreate(&a));
   HIPCHK(hipEventCreate(&b));
   int rc = FTAFQMC_OK;
+  // With walker groups the groups' kernels run side by side; a tile of one workgroup per walker
+  // leaves the other group no room (measured: overlap gains 8.6% with 64 x 64 tiles, 1.4% with it).
+  const bool grouped = make_views(s, s.groups).size() > 1;
   // kind 0: a plain chain product; 1: the apply; 2: the V^4 product with its three addends and
   // Taylor-block outputs (the heaviest epilogue, timed for all chain products with addends)
   for (int kind = 0; kind < 3 && rc == FTAFQMC_OK; ++kind) {
@@ -513,7 +518,7 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
         g.extra[0] = GemmOut{d.E0, 1.0, 1.0, 1.0, 1.0, 1.0};
         for (int k = nb - 2, e = 1; k >= 0; --k, ++e) g.extra[e] = GemmOut{d.Bk[k], 0.0, 1.0, 1.0, 1.0, 1.0};
       }
-      if (!gemm_tile_supported(t, prec)) continue;
+      if (!gemm_tile_supported(t, prec) || (grouped && gemm_tile_walker_sized(t))) continue;
       hipError_t e = launch_zgemm(g, prec, st);                 // warm-up
       if (e == hipSuccess) e = hipEventRecord(a, st);
       for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_zgemm(g, prec, st);

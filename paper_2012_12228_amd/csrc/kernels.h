@@ -27,6 +27,7 @@ struct GemmParams {
 hipError_t launch_zgemm(const GemmParams& p, int prec, hipStream_t s);
 int gemm_tile_count();
 bool gemm_tile_supported(int tile, int prec);   // shapes built for this precision
+bool gemm_tile_walker_sized(int tile);           // one workgroup per walker (fills every CU at W >= 256)
 
 // Blocked Gaussian elimination on a per-walker augmented matrix [A | R] (M x M
 // left block, nrhs right-hand sides starting at column rhs_off, row stride lda).
