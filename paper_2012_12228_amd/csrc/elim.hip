@@ -13,7 +13,7 @@
 //           in-place Gauss-Jordan inversion of the pivot block inside the column loop (a
 //           runtime loop over columns with the row rotated in registers, so the loop body is
 //           small and stays in the instruction cache);
-//   swap    column-parallel row exchanges;
+//   swap    the panel's row exchanges composed into one permutation of at most 2 NB rows;
 // Forward elimination (LU, right-looking):
 //   trsm    U12 = L11^{-1} A12 as a small in-place MFMA GEMM (each workgroup owns whole
 //           columns and reads them completely before it writes);
@@ -446,24 +446,60 @@ __global__ __launch_bounds__(256) void gj_combine_kernel(CombineParams c) {
   }
 }
 
-// Row exchanges of panel j0 for columns [c0, c1), one column per thread.
+// Row exchanges of panel j0 for columns [c0, c1).  The jb exchanges compose into one
+// permutation that moves at most 2 jb rows: the workgroup first finds, for every moved row, the
+// row whose contents it receives (tracing the exchanges backwards), then each thread reads its
+// column of all moved rows into registers (every load in flight at once), and after a barrier
+// writes them to their new places.  64 columns per workgroup, one per lane, four row groups.
+constexpr int SWAP_COLS = 64, SWAP_GROUPS = 4, SWAP_PER = 2 * NB / SWAP_GROUPS;
 __global__ __launch_bounds__(256) void swap_kernel(PanelParams p, int c0, int c1, int chunks) {
   __shared__ int pv[NB];
+  __shared__ int src[2 * NB], dst[2 * NB];
+  __shared__ int nmov;
   const int w = blockIdx.x / chunks, ch = blockIdx.x - w * chunks;
   if (w >= p.W) return;
   const int t = threadIdx.x, j0 = p.j0, jb = p.jb, lda = p.lda;
   if (t < NB) pv[t] = t < jb ? p.piv[(long long)w * p.ld + j0 + t] : j0 + t;
+  if (t == 0) nmov = 0;
   __syncthreads();
-  const int col = c0 + ch * 256 + t;
-  if (col >= c1) return;
-  double2* aug = p.aug + (long long)w * p.stride;
-  for (int c = 0; c < jb; ++c) {
-    const int pr = pv[c];
-    if (pr != j0 + c) {
-      const double2 u = aug[(long long)(j0 + c) * lda + col];
-      aug[(long long)(j0 + c) * lda + col] = aug[(long long)pr * lda + col];
-      aug[(long long)pr * lda + col] = u;
+  if (t < 2 * jb) {
+    // candidate position: a pivot row of the panel or the row it was exchanged with
+    const int pos = t < jb ? j0 + t : pv[t - jb];
+    bool first = true;
+    if (t >= jb) {
+      if (pos < j0 + jb) first = false;                     // listed by the first half
+      for (int u = 0; u < t - jb; ++u) first = first && pv[u] != pos;
     }
+    int from = pos;
+    for (int c = jb - 1; c >= 0; --c) {
+      const int a = j0 + c, b = pv[c];
+      from = from == a ? b : (from == b ? a : from);
+    }
+    if (first && from != pos) {
+      const int k = atomicAdd(&nmov, 1);
+      src[k] = from;
+      dst[k] = pos;
+    }
+  }
+  __syncthreads();
+  const int n = nmov, lane = t & (SWAP_COLS - 1);
+  const int g = __builtin_amdgcn_readfirstlane(t / SWAP_COLS);   // row group = wave
+  if (n == 0) return;                                     // uniform over the workgroup
+  // lanes past c1 repeat the last column: the same value to the same address, no predicate
+  const int cc = c0 + ch * SWAP_COLS + lane, col = cc < c1 ? cc : c1 - 1;
+  double2* aug = p.aug + (long long)w * p.stride + col;
+  double2 v[SWAP_PER];
+#pragma unroll
+  for (int i = 0; i < SWAP_PER; ++i) {
+    const int r = g + i * SWAP_GROUPS;
+    v[i] = r < n ? aug[(long long)src[r] * lda] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();   // a moved row may be the source of another row in the same column
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): every load has returned before the stores
+#pragma unroll
+  for (int i = 0; i < SWAP_PER; ++i) {
+    const int r = g + i * SWAP_GROUPS;
+    if (r < n) aug[(long long)dst[r] * lda] = v[i];
   }
 }
 
@@ -521,8 +557,8 @@ hipError_t gj_panel(const PanelParams& p, int M, int W, hipStream_t s) {
 }
 
 hipError_t swap_rows(const PanelParams& p, int W, int c0, int c1, hipStream_t s) {
-  const int chunks = (c1 - c0 + 255) / 256;
-  swap_kernel<<<W * chunks, 256, 0, s>>>(p, c0, c1, chunks);
+  const int chunks = (c1 - c0 + SWAP_COLS - 1) / SWAP_COLS;
+  swap_kernel<<<W * chunks, SWAP_COLS * SWAP_GROUPS, 0, s>>>(p, c0, c1, chunks);
   return hipGetLastError();
 }
 
