@@ -124,7 +124,8 @@ def run_precision(F, torch, systems, fields, steps, warmup):
         e = ctx.energy(i)
         energies.append((e["local"].cpu().numpy(), e["logw"].cpu().numpy()))
         status.append(e["status"].cpu().numpy())
-    out["gemm_tiles"] = [(inf["gemm_tile_chain"], inf["gemm_tile_epilogue"], inf["gemm_tile_apply"]) for inf in infos]
+    out["gemm_tiles"] = [(inf["gemm_tile_chain"], inf["gemm_tile_epilogue"], inf["gemm_tile_horner"],
+                          inf["gemm_tile_apply"]) for inf in infos]
     return ctx, out, energies, status
 
 

@@ -115,8 +115,9 @@ typedef struct {
   int gemm_tile_apply;   /* tile shape of the product that applies e^V */
   int gemm_tile_shapes;  /* number of tile shapes built (valid values of FTAFQMC_GEMM_TILE) */
   int walker_groups;     /* walker groups whose eliminations overlap on separate streams */
-  int gemm_tile_epilogue; /* tile shape of the chain products with epilogue operands (V^4 with
-                             the Taylor blocks, the Horner steps) */
+  int gemm_tile_epilogue; /* tile shape of the V^4 product, whose epilogue adds V, V^2, V^3 and
+                             writes the Taylor blocks */
+  int gemm_tile_horner;   /* tile shape of the Horner steps (one addend, one output) */
 } ftafqmc_info;
 
 /* Bytes of device workspace needed for the n_sys systems listed in p[0..n_sys-1]

@@ -48,7 +48,7 @@ class Info(ctypes.Structure):
                 ("mu", ctypes.c_double), ("e_madelung", ctypes.c_double),
                 ("gemm_tile_chain", ctypes.c_int), ("gemm_tile_apply", ctypes.c_int),
                 ("gemm_tile_shapes", ctypes.c_int), ("walker_groups", ctypes.c_int),
-                ("gemm_tile_epilogue", ctypes.c_int)]
+                ("gemm_tile_epilogue", ctypes.c_int), ("gemm_tile_horner", ctypes.c_int)]
 
 
 _lib_handle = None

@@ -45,7 +45,7 @@ struct HostSys {
   double2* mean = nullptr;
   int k = 0, nrec = 0;
   std::vector<int> rec_slice;
-  int tile_chain = 0, tile_apply = 0, tile_epi = 0;   // GEMM tile shapes chosen by the start-up autotuner
+  int tile_chain = 0, tile_apply = 0, tile_epi = 0, tile_horner = 0;   // GEMM tile shapes chosen by the start-up autotuner
   bool ckpt = false;                    // path recorded for the frozen-path derivative
   int groups = 1;                       // walker groups (streams) of ftafqmc_propagate
   double2* Y0 = nullptr;                // the buffers Y and Ynew start as at every reset
@@ -413,7 +413,7 @@ int form_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st, void*
   void* nxt = d.E1;
   for (int k = nb - 2; k >= 0; --k) {
     GemmParams e = gp_base(s, d);
-    e.tile = s.tile_epi;
+    e.tile = s.tile_horner;
     e.A = cur; e.B = d.V4; e.C = nxt;
     e.P1 = d.Bk[k]; e.c1 = 1.0;
     if (k == 0) { e.rs = d.kh; e.cs = d.kh; }            // K e^V K
@@ -472,7 +472,8 @@ int greens(ftafqmc_ctx* h, HostSys& s, SysDev& d, int k, int init, hipStream_t s
 }
 
 // Start-up autotuner: time every GEMM tile shape on this system's real size (W walkers of
-// M x M x M products) for the propagator chain and for the final apply, keep the fastest.
+// M x M x M products) for each kind of product in the propagator (plain chain product, V^4 with
+// the Taylor blocks, Horner step, apply), keep the fastest for each.
 // FTAFQMC_GEMM_TILE=<index> in the environment forces one shape (for experiments).
 std::vector<SysDev> make_views(const HostSys& s, int ngroups);
 
@@ -485,7 +486,7 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
     // a shape not built for this precision falls back to the timed choice
     const int t = std::atoi(env);
     if (gemm_tile_supported(t, mixed ? GEMM_C32 : GEMM_Z64) && (!mixed || gemm_tile_supported(t, GEMM_C32_Z64B))) {
-      s.tile_chain = s.tile_apply = s.tile_epi = t;
+      s.tile_chain = s.tile_apply = s.tile_epi = s.tile_horner = t;
       return FTAFQMC_OK;
     }
   }
@@ -501,8 +502,8 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   // leaves the other group no room (measured: overlap gains 8.6% with 64 x 64 tiles, 1.4% with it).
   const bool grouped = make_views(s, s.groups).size() > 1;
   // kind 0: a plain chain product; 1: the apply; 2: the V^4 product with its three addends and
-  // Taylor-block outputs (the heaviest epilogue, timed for all chain products with addends)
-  for (int kind = 0; kind < 3 && rc == FTAFQMC_OK; ++kind) {
+  // Taylor-block outputs; 3: a Horner step (one addend, one output)
+  for (int kind = 0; kind < 4 && rc == FTAFQMC_OK; ++kind) {
     float best = 1e30f;
     int besti = 0;
     for (int t = 0; t < gemm_tile_count(); ++t) {
@@ -511,6 +512,7 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
       int prec = mixed ? GEMM_C32 : GEMM_Z64;
       if (kind == 0) { g.A = d.V; g.B = d.V; g.C = d.V2; }
       else if (kind == 1) { g.A = d.V; g.B = d.Ynew; g.C = d.E1; if (mixed) prec = GEMM_C32_Z64B; }
+      else if (kind == 3) { g.A = d.V2; g.B = d.V4; g.C = d.V3; g.P1 = d.V; g.c1 = 1.0; }
       else {
         g.A = d.V2; g.B = d.V2; g.C = d.V4; g.P1 = d.V; g.P2 = d.V2; g.P3 = d.V3; g.c1 = 1.0;
         const int nb = mixed ? 3 : 4;
@@ -531,7 +533,8 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
     }
     if (kind == 0) s.tile_chain = besti;
     else if (kind == 1) s.tile_apply = besti;
-    else s.tile_epi = besti;
+    else if (kind == 2) s.tile_epi = besti;
+    else s.tile_horner = besti;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
@@ -828,6 +831,7 @@ int ftafqmc_query(ftafqmc_t h, int sys, ftafqmc_info* out) {
   out->beta = s.beta; out->dtau = s.dtau; out->L = s.L; out->omega = s.omega;
   out->mu_T = s.muT; out->mu = s.mu; out->e_madelung = s.EM;
   out->gemm_tile_chain = s.tile_chain; out->gemm_tile_apply = s.tile_apply; out->gemm_tile_epilogue = s.tile_epi;
+  out->gemm_tile_horner = s.tile_horner;
   out->gemm_tile_shapes = gemm_tile_count();
   out->walker_groups = (int)make_views(s, s.groups).size();
   return FTAFQMC_OK;

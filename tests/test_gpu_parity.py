@@ -353,11 +353,11 @@ def test_every_gemm_tile_shape_gives_the_same_path(precision, monkeypatch):
         monkeypatch.setenv("FTAFQMC_GEMM_TILE", str(tile))
         ctx, _ = gpu_run(F, [sd], [flds])
         inf = ctx.info()
-        chosen = (inf["gemm_tile_chain"], inf["gemm_tile_epilogue"], inf["gemm_tile_apply"])
+        chosen = (inf["gemm_tile_chain"], inf["gemm_tile_epilogue"], inf["gemm_tile_horner"], inf["gemm_tile_apply"])
         if precision == 0 and tile in fp32_only:
             assert not set(chosen) & fp32_only   # falls back to a timed choice
         else:
-            assert chosen == (tile, tile, tile)
+            assert chosen == (tile, tile, tile, tile)
         G = ctx.greens().cpu().numpy()
         E = ctx.records()["trace"].cpu().numpy()
         if ref is None:
