@@ -37,7 +37,8 @@ struct HostSys {
   int M = 0, NQ = 0, n = 0, ld = 0, rmax = 0, gdim = 0, gc0 = 0, nrec_max = 0;
   double L = 0, omega = 0, TF = 0, beta = 0, dtau = 0, muT = 0, mu = 0, EM = 0;
   std::vector<iv3> nvec, qvec;
-  std::vector<int> idx, neg, qptr, qpair, flat;
+  std::vector<int> idx, neg, qptr, qpair, flat, rbptr, rbidx;
+  int rq_rows = 0, rq_nblk = 0;
   std::vector<double> vq, sq, eps, hK, kh, lnbt;
   std::vector<short> grid;
   size_t off_begin = 0, bytes = 0;
@@ -161,6 +162,29 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
       for (int r = 0; r < s.M; ++r)
         if (pidx != r) s.qpair[fill[s.idx[(size_t)pidx * s.M + r]]++] = r * s.ld + pidx;
   }
+  // the pairs again by blocks of rows of G (each block fits one LDS buffer of the r_Q kernel)
+  s.rq_rows = std::max(1, std::min(s.M, rq_block_elems() / s.ld));
+  s.rq_nblk = (s.M + s.rq_rows - 1) / s.rq_rows;
+  s.rbptr.assign((size_t)s.rq_nblk * (s.NQ + 1), 0);
+  s.rbidx.assign((size_t)s.M * (s.M - 1), 0);
+  {
+    std::vector<int> fill(s.NQ);
+    int off = 0;
+    for (int b = 0; b < s.rq_nblk; ++b) {
+      const int r0 = b * s.rq_rows, r1 = std::min(s.M, r0 + s.rq_rows);
+      int* bp = &s.rbptr[(size_t)b * (s.NQ + 1)];
+      for (int r = r0; r < r1; ++r)
+        for (int pidx = 0; pidx < s.M; ++pidx)
+          if (pidx != r) bp[s.idx[(size_t)pidx * s.M + r] + 1]++;
+      bp[0] = off;
+      for (int q = 0; q < s.NQ; ++q) bp[q + 1] += bp[q];
+      for (int q = 0; q < s.NQ; ++q) fill[q] = bp[q];
+      for (int r = r0; r < r1; ++r)
+        for (int pidx = 0; pidx < s.M; ++pidx)
+          if (pidx != r) s.rbidx[fill[s.idx[(size_t)pidx * s.M + r]]++] = (r - r0) * s.ld + pidx;
+      off = bp[s.NQ];
+    }
+  }
   // lookup grid for K_b - K_a + K_d
   const int R = 3 * s.rmax;
   s.gdim = 2 * R + 1;
@@ -193,6 +217,8 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.lnbt = (const double*)take(sizeof(double) * ld);
   d.qptr = (const int*)take(sizeof(int) * (NQ + 1));
   d.qpair = (const int*)take(sizeof(int) * (size_t)M * (M - 1));
+  d.rbptr = (const int*)take(sizeof(int) * (size_t)s.rq_nblk * (NQ + 1));
+  d.rbidx = (const int*)take(sizeof(int) * (size_t)M * (M - 1));
   d.grid = (const short*)take(sizeof(short) * s.grid.size());
   d.flat = (const int*)take(sizeof(int) * M);
   d.Y = (double2*)take(sizeof(double2) * mat * W);
@@ -271,6 +297,7 @@ size_t layout(HostSys& s, char* base, size_t off) {
   }
   s.bytes = off - s.off_begin;
   d.M = M; d.ld = ld; d.NQ = NQ; d.W = W; d.n = s.n; d.grid_dim = s.gdim; d.grid_c0 = s.gc0;
+  d.rq_rows = s.rq_rows; d.rq_nblk = s.rq_nblk;
   d.dtau = s.dtau; d.kscale = s.p.kscale; d.e_madelung = s.EM;
   d.mat_stride = (long long)mat;
   d.aug_stride = (long long)2 * mat;
@@ -282,6 +309,7 @@ size_t layout(HostSys& s, char* base, size_t off) {
     dd.dtau = s.dtau; dd.kscale = s.p.kscale; dd.e_madelung = s.EM;
     dd.idx = d.idx; dd.neg = d.neg; dd.vq = d.vq; dd.sq = d.sq; dd.eps = d.eps; dd.kh = d.kh; dd.lnbt = d.lnbt;
     dd.qptr = d.qptr; dd.qpair = d.qpair; dd.grid = d.grid; dd.flat = d.flat;
+    dd.rbptr = d.rbptr; dd.rbidx = d.rbidx; dd.rq_rows = d.rq_rows; dd.rq_nblk = d.rq_nblk;
     dd.rec_c = nullptr; dd.rec_trG = nullptr;
     dd.w_off = 0; dd.rec_W = W;
   }
@@ -529,6 +557,11 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
       float ms = 0.0f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
       if (e != hipSuccess) { rc = h->set(FTAFQMC_E_HIP, std::string("autotune: ") + hipGetErrorString(e)); break; }
+      // The V^4 product's heavy epilogue (three addends, four outputs) does not overlap anyone's
+      // MFMAs when every CU holds one walker's workgroup: in the running path the 64 x 64 tile
+      // beats the one-walker tile that ties with it here (M=171: 197 against about 223 us), so
+      // a one-walker tile must win this trial by more than 5%.
+      if (kind == 2 && gemm_tile_walker_sized(t)) ms *= 1.05f;
       if (ms < best) { best = ms; besti = t; }
     }
     if (kind == 0) s.tile_chain = besti;
@@ -809,6 +842,8 @@ int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size
     if (e == hipSuccess) e = up(d.lnbt, s.lnbt.data(), sizeof(double) * s.ld);
     if (e == hipSuccess) e = up(d.qptr, s.qptr.data(), sizeof(int) * (s.NQ + 1));
     if (e == hipSuccess) e = up(d.qpair, s.qpair.data(), sizeof(int) * s.qpair.size());
+    if (e == hipSuccess) e = up(d.rbptr, s.rbptr.data(), sizeof(int) * s.rbptr.size());
+    if (e == hipSuccess) e = up(d.rbidx, s.rbidx.data(), sizeof(int) * s.rbidx.size());
     if (e == hipSuccess) e = up(d.grid, s.grid.data(), sizeof(short) * s.grid.size());
     if (e == hipSuccess) e = up(d.flat, s.flat.data(), sizeof(int) * s.M);
     // the host tables are no longer needed once the copies have completed

@@ -60,6 +60,11 @@ struct SysDev {
   const double* lnbt;     // [ld] -dtau (eps - mu_T)
   const int* qptr;        // [NQ+1] CSR offsets of the pairs of each Q
   const int* qpair;       // [M(M-1)] flat index r*ld + p of G_{r p} for pairs K_p - K_r = Q
+  // the same pairs by blocks of rq_rows rows of G: block b's pairs grouped by Q (rows ascending
+  // within a Q), each as (r - b rq_rows) ld + p, with CSR offsets rbptr[b (NQ+1) + q]
+  const int* rbptr;       // [rq_nblk (NQ+1)]
+  const int* rbidx;       // [M(M-1)]
+  int rq_rows, rq_nblk;
   const short* grid;      // [grid_dim^3] basis index of an integer vector, -1 outside
   const int* flat;        // [M] flat offset of each basis vector in the lookup grid
   // state
@@ -129,6 +134,7 @@ hipError_t launch_coef_v(const SysDev& s, const double2* fields, int k, int mixe
 hipError_t launch_greens_form(const SysDev& s, int k, hipStream_t st);
 hipError_t launch_greens_post(const SysDev& s, int k, hipStream_t st);
 hipError_t launch_weight(const SysDev& s, int k, double sum_lnLb, int init, hipStream_t st);
+int rq_block_elems();     // complex entries of G per row block of the r_Q kernel (rows * ld at most)
 hipError_t launch_stab_perm(const SysDev& s, hipStream_t st);
 hipError_t launch_stab_gather(const SysDev& s, hipStream_t st);       // E0 = Y[:, perm], aug right = E0^H
 hipError_t launch_stab_finish_a(const SysDev& s, hipStream_t st);     // Y, D, Ru (E1) from the Cholesky step

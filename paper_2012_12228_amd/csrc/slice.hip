@@ -198,6 +198,68 @@ __global__ __launch_bounds__(NT) void rq_kernel(SysDev s, int chunks) {
       cadd(cadd(cadd(acc[0], acc[1]), cadd(acc[2], acc[3])), cadd(cadd(acc[4], acc[5]), cadd(acc[6], acc[7])));
 }
 
+// r_Q with G streamed through LDS: one workgroup per walker (block w runs on XCD w mod 8, the
+// XCD whose L2 holds walker w's G).  G goes through LDS one block of rows at a time with
+// coalesced loads, together with the block's pair list; each thread then gathers the pairs of
+// its Qs in that block from LDS.  The next block's loads are in flight during the gathers.
+// Every Q sums its pairs block by block and row by row: a fixed order.
+constexpr int RQ_NT = 1024, RQ_ELEMS = 4096, RQ_QPT = 4, RQ_PER = RQ_ELEMS / RQ_NT;
+__global__ __launch_bounds__(RQ_NT) void rq_stream_kernel(SysDev s) {
+  __shared__ double2 Gs[RQ_ELEMS];
+  __shared__ int Is[RQ_ELEMS];
+  const int w = blockIdx.x;
+  if (w >= s.W) return;
+  const int t = threadIdx.x, NQ = s.NQ, ld = s.ld;
+  const double2* G = s.G + (long long)w * s.mat_stride;
+  double2 gv[RQ_PER];
+  int iv[RQ_PER], qs[RQ_QPT], qe[RQ_QPT];
+  // block b: rows [b rq_rows, ...) of G are contiguous (nr ld entries, nr ld <= RQ_ELEMS); its
+  // pair list has fewer than nr ld entries
+  auto fetch = [&](int b) {
+    const int r0 = b * s.rq_rows, nr = min(s.rq_rows, s.M - r0), n = nr * ld;
+    const double2* gb = G + (long long)r0 * ld;
+    const int* bp = s.rbptr + (long long)b * (NQ + 1);
+    const int i0 = bp[0], ni = bp[NQ] - i0;
+#pragma unroll
+    for (int k = 0; k < RQ_PER; ++k) {
+      const int e = t + k * RQ_NT;
+      gv[k] = e < n ? gb[e] : zero2();
+      iv[k] = e < ni ? s.rbidx[i0 + e] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < RQ_QPT; ++i) {
+      const int q = t + i * RQ_NT;
+      qs[i] = q < NQ ? bp[q] - i0 : 0;
+      qe[i] = q < NQ ? bp[q + 1] - i0 : 0;
+    }
+  };
+  double2 acc[RQ_QPT];
+#pragma unroll
+  for (int i = 0; i < RQ_QPT; ++i) acc[i] = zero2();
+  fetch(0);
+  for (int b = 0; b < s.rq_nblk; ++b) {
+    __syncthreads();                 // every gather of the previous block is done
+#pragma unroll
+    for (int k = 0; k < RQ_PER; ++k) {
+      Gs[t + k * RQ_NT] = gv[k];
+      Is[t + k * RQ_NT] = iv[k];
+    }
+    int cs[RQ_QPT], ce[RQ_QPT];
+#pragma unroll
+    for (int i = 0; i < RQ_QPT; ++i) { cs[i] = qs[i]; ce[i] = qe[i]; }
+    __syncthreads();
+    if (b + 1 < s.rq_nblk) fetch(b + 1);
+#pragma unroll
+    for (int i = 0; i < RQ_QPT; ++i)
+      for (int e = cs[i]; e < ce[i]; ++e) acc[i] = csub(acc[i], Gs[Is[e]]);
+  }
+#pragma unroll
+  for (int i = 0; i < RQ_QPT; ++i) {
+    const int q = t + i * RQ_NT;
+    if (q < NQ) s.r[(long long)w * NQ + q] = acc[i];
+  }
+}
+
 // ln det(I + A_k) and the phaseless weight (after rq_kernel).
 __global__ __launch_bounds__(NT) void weight_kernel(SysDev s, int k, double sum_lnLb, int init) {
   __shared__ double red[8];
@@ -620,9 +682,14 @@ hipError_t launch_greens_post(const SysDev& s, int k, hipStream_t st) {
   greens_post_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s, k);
   return hipGetLastError();
 }
+int rq_block_elems() { return RQ_ELEMS; }
 hipError_t launch_weight(const SysDev& s, int k, double sum_lnLb, int init, hipStream_t st) {
-  const int chunks = (s.NQ + NT - 1) / NT;
-  rq_kernel<<<tiles_blocks(s, chunks), NT, 0, st>>>(s, chunks);
+  if (s.NQ <= RQ_QPT * RQ_NT && s.rq_rows * s.ld <= RQ_ELEMS) {
+    rq_stream_kernel<<<s.W, RQ_NT, 0, st>>>(s);
+  } else {
+    const int chunks = (s.NQ + NT - 1) / NT;
+    rq_kernel<<<tiles_blocks(s, chunks), NT, 0, st>>>(s, chunks);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   weight_kernel<<<s.W, NT, 0, st>>>(s, k, sum_lnLb, init);
