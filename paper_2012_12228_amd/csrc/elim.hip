@@ -250,13 +250,28 @@ __global__ __launch_bounds__(NT) void panel_gj_kernel(PanelParams p) {
   {
     // the panel goes through LDS GJ_CH columns at a time: consecutive lanes read consecutive
     // entries of a row (coalesced), then every thread takes its own row from LDS
+    // (every load is unconditional, so that all GJ_CH of them are in flight at once: entries
+    // outside the panel read the pivot block's corner, which always exists, and become zero;
+    // the next chunk's loads are issued before this chunk goes through LDS)
     const int rows = M - j0;
-#pragma unroll
-    for (int q = 0; q < NB / GJ_CH; ++q) {
+    double2 v[2][GJ_CH];
+    auto load = [&](int q, double2 (&dst)[GJ_CH]) {
 #pragma unroll
       for (int e0 = 0; e0 < GJ_CH; ++e0) {
         const int e = t + e0 * NT, rr = e / GJ_CH, c = q * GJ_CH + e % GJ_CH;
-        sh.stage[rr][e % GJ_CH] = (rr < rows && c < jb) ? aug[(long long)(j0 + rr) * lda + j0 + c] : make_double2(0.0, 0.0);
+        const bool in = rr < rows && c < jb;
+        dst[e0] = aug[(long long)(j0 + (in ? rr : 0)) * lda + j0 + (in ? c : 0)];
+        if (!in) dst[e0] = make_double2(0.0, 0.0);
+      }
+    };
+    load(0, v[0]);
+#pragma unroll
+    for (int q = 0; q < NB / GJ_CH; ++q) {
+      if (q + 1 < NB / GJ_CH) load(q + 1, v[(q + 1) & 1]);
+#pragma unroll
+      for (int e0 = 0; e0 < GJ_CH; ++e0) {
+        const int e = t + e0 * NT;
+        sh.stage[e / GJ_CH][e % GJ_CH] = v[q & 1][e0];
       }
       __syncthreads();
 #pragma unroll
