@@ -19,6 +19,7 @@
 // every load is bounds-guarded against M, every store against Mpad.
 #include "common.h"
 #include "kernels.h"
+#include <type_traits>
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -64,6 +65,8 @@ __global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 1
   __shared__ cacc Bs[2][BK][BN + PAD];
   // the propagator products use A and B as stored; only the dense linear algebra takes A^H
   const int opA = ROLE == 1 ? p.opA : 0, opB = ROLE == 1 ? p.opB : 0;
+  // unconditional tile and epilogue loads (below) for the FP32-MFMA propagator products
+  constexpr bool UNCOND = ROLE == 0 && sizeof(ACC) == 4;
 
   int w, tile;
   if (!xcd_walker_tile(blockIdx.x, p.W, p.tiles_m * p.tiles_n, &w, &tile)) return;
@@ -84,9 +87,59 @@ __global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 1
 #pragma unroll
       for (int v = 0; v < 4; ++v) { accR[i][j][v] = 0; accI[i][j][v] = 0; }
 
-  cacc ra[TL::EA], rb[TL::EB];
-  // global -> registers for k-tile kt; consecutive threads read consecutive addresses
+  // FP32-MFMA propagator products (A and B as stored): tile entries are kept as stored
+  // (complex64, or complex128 converted at once).  Every load is unconditional, at a clamped address (an entry outside the matrix
+  // reads its first element), so that all the loads of a k-tile are in flight together during
+  // the MFMAs; the bounds select and the conversion to the MFMA type happen when the tile is
+  // staged in LDS.  (A load behind a bounds branch was waited for at once: the k-tile's loads
+  // ran one after another before the MFMAs.)
+  // Operands stored wider than the MFMA type (the complex128 Y of the mixed apply) would hold
+  // twice the registers across the MFMAs; those are converted right after their loads instead
+  // (all of the tile's loads are issued first, so they still wait only once).
+  typedef typename std::conditional<sizeof(TA) == sizeof(cacc), TA, cacc>::type RA;
+  typedef typename std::conditional<sizeof(TB) == sizeof(cacc), TB, cacc>::type RB;
+  RA ra[TL::EA];
+  RB rb[TL::EB];
+  bool oka[TL::EA], okb[TL::EB];
   auto load_tile = [&](int kt) {
+    const int k0 = kt * BK;
+    TA ta[TL::EA];
+    TB tb[TL::EB];
+#pragma unroll
+    for (int q = 0; q < TL::EA; ++q) {
+      const int e = t + q * NT;
+      int gm, gk;
+      if (opA == 0) { gm = m0 + e / BK; gk = k0 + e % BK; }
+      else            { gk = k0 + e / BM; gm = m0 + e % BM; }
+      oka[q] = gm < Mr && gk < Kd;
+      const long long off = opA == 0 ? (long long)gm * p.lda + gk : (long long)gk * p.lda + gm;
+      ta[q] = A[oka[q] ? off : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < TL::EB; ++q) {
+      const int e = t + q * NT;
+      int gk, gn;
+      if (opB == 0) { gk = k0 + e / BN; gn = n0 + e % BN; }
+      else            { gn = n0 + e / BK; gk = k0 + e % BK; }
+      okb[q] = gn < Nc && gk < Kd;
+      const long long off = opB == 0 ? (long long)gk * p.ldb + gn : (long long)gn * p.ldb + gk;
+      tb[q] = B[okb[q] ? off : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < TL::EA; ++q) {
+      if constexpr (sizeof(TA) == sizeof(cacc)) ra[q] = ta[q];
+      else ra[q] = cvt<ACC>(ta[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < TL::EB; ++q) {
+      if constexpr (sizeof(TB) == sizeof(cacc)) rb[q] = tb[q];
+      else rb[q] = cvt<ACC>(tb[q]);
+    }
+  };
+  // The FP64 tiles (the FP64 propagator and the dense linear algebra) load behind the bounds
+  // test, converting and conjugating at the load: there the unconditional form above was 3-7%
+  // slower (FP64 update tile 90.6 -> 93.4 us, FP64 propagator tile 226 -> 241 us at M=171).
+  auto load_tile_la = [&](int kt) {
     const int k0 = kt * BK;
 #pragma unroll
     for (int q = 0; q < TL::EA; ++q) {
@@ -98,6 +151,7 @@ __global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 1
       if (gm < Mr && gk < Kd)
         v = opA == 0 ? ld_c(A + (long long)gm * p.lda + gk) : cconj(ld_c(A + (long long)gk * p.lda + gm));
       ra[q] = cvt<ACC>(v);
+      oka[q] = true;
     }
 #pragma unroll
     for (int q = 0; q < TL::EB; ++q) {
@@ -109,20 +163,28 @@ __global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 1
       if (gn < Nc && gk < Kd)
         v = opB == 0 ? ld_c(B + (long long)gk * p.ldb + gn) : cconj(ld_c(B + (long long)gn * p.ldb + gk));
       rb[q] = cvt<ACC>(v);
+      okb[q] = true;
     }
+  };
+  auto staged = [&](auto raw, bool ok) {
+    cacc v = cvt<ACC>(raw);
+    if (!ok) { v.x = 0; v.y = 0; }
+    return v;
   };
   auto store_tile = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < TL::EA; ++q) {
       const int e = t + q * NT;
-      if (opA == 0) As[buf][e / BK][e % BK] = ra[q];
-      else          As[buf][e % BM][e / BM] = ra[q];
+      const cacc v = staged(ra[q], oka[q]);
+      if (opA == 0) As[buf][e / BK][e % BK] = v;
+      else          As[buf][e % BM][e / BM] = v;
     }
 #pragma unroll
     for (int q = 0; q < TL::EB; ++q) {
       const int e = t + q * NT;
-      if (opB == 0) Bs[buf][e / BN][e % BN] = rb[q];
-      else          Bs[buf][e % BK][e / BK] = rb[q];
+      const cacc v = staged(rb[q], okb[q]);
+      if (opB == 0) Bs[buf][e / BN][e % BN] = v;
+      else          Bs[buf][e % BK][e / BK] = v;
     }
   };
 
@@ -148,12 +210,16 @@ __global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 1
 #pragma unroll
     for (int j = 0; j < FN; ++j) live[i][j] = (m0 + wr * TL::WM + i * 16 < Mr) && (n0 + wc * TL::WN + j * 16 < Nc);
 
-  load_tile(0);
+  auto load = [&](int kt) {
+    if constexpr (UNCOND) load_tile(kt);
+    else load_tile_la(kt);
+  };
+  load(0);
   store_tile(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) load_tile(kt + 1);
+    if (kt + 1 < nk) load(kt + 1);
     if (kt + 1 == nk && PRE) {
 #pragma unroll
       for (int i = 0; i < FM; ++i)
@@ -190,54 +256,125 @@ __global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 1
     __syncthreads();
   }
 
-  // epilogue
+  if constexpr (UNCOND) {
+    // epilogue: the operand loads of EV entries (the addends, C when beta != 0, the row and
+    // column factors) are issued together, unconditionally at a clamped address for entries
+    // outside the result, before any of them is used.  One entry at a time: batching a block's
+    // four entries made the register-capped tiles spill.
+    constexpr int EV = 1;
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
+      for (int j = 0; j < FN; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int gi = m0 + wr * TL::WM + i * 16 + Mfma<ACC>::row(lane, v);
-        const int gj = n0 + wc * TL::WN + j * 16 + li;
-        if (gi >= p.mpad || gj >= p.npad) continue;
-        if (ROLE == 1 && gi >= p.skip0 && gi < p.skip1) continue;   // rows left untouched
-        const long long off = (long long)gi * p.ldc + gj;
-        const bool in = gi < Mr && gj < Nc;
-        const double2 acc = make_double2((double)accR[i][j][v], (double)accI[i][j][v]);
-        double2 q1 = make_double2(0.0, 0.0), q2 = q1, q3 = q1, qc = q1;
-        if (in) {
-          const long long offp = (long long)gi * p.ldp + gj;
-          if (pre_p1) { if constexpr (PREF) q1 = to_d2(pre[i][j][v]); }
-          else if (P1) q1 = ld_c(P1 + offp);
-          if (P2) q2 = ld_c(P2 + offp);
-          if (P3) q3 = ld_c(P3 + offp);
-          if (pre_c) { if constexpr (PREF) qc = to_d2(pre[i][j][v]); }
-          else if (p.beta != 0.0) qc = ld_c(C + off);
-        }
-        const double di = (gi == gj) ? 1.0 : 0.0;
-        double2 out = make_double2(0.0, 0.0);
-        if (in) {
-          out = cscale(acc, p.alpha);
-          if (p.beta != 0.0) out = cadd(out, cscale(qc, p.beta));
-          out.x += p.cI * di;
-          out = cadd(out, cadd(cscale(q1, p.c1), cadd(cscale(q2, p.c2), cscale(q3, p.c3))));
-          if (p.rs) out = cscale(out, p.rs[gi]);
-          if (p.cs) out = cscale(out, p.cs[gj]);
-        }
-        store_c(C + off, out);
+        for (int v0 = 0; v0 < 4; v0 += EV) {
+          const int gj = n0 + wc * TL::WN + j * 16 + li;
+          int gi[EV];
+          bool in[EV];
+          TC q1r[EV], q2r[EV], q3r[EV], qcr[EV];
+          double rsv[EV], csv = 1.0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (e >= p.nextra) break;
-          const GemmOut& o = p.extra[e];
-          double2 x = make_double2(0.0, 0.0);
-          if (in) {
-            x = cscale(acc, o.cacc);
-            x.x += o.cI * di;
-            x = cadd(x, cadd(cscale(q1, o.c1), cadd(cscale(q2, o.c2), cscale(q3, o.c3))));
+          for (int u = 0; u < EV; ++u) {
+            gi[u] = m0 + wr * TL::WM + i * 16 + Mfma<ACC>::row(lane, v0 + u);
+            in[u] = gi[u] < Mr && gj < Nc;
+            const long long offp = in[u] ? (long long)gi[u] * p.ldp + gj : 0;
+            const long long off = in[u] ? (long long)gi[u] * p.ldc + gj : 0;
+            q1r[u] = q2r[u] = q3r[u] = qcr[u] = TC{};
+            rsv[u] = 1.0;
+            if (P1 && !pre_p1) q1r[u] = P1[offp];
+            if (P2) q2r[u] = P2[offp];
+            if (P3) q3r[u] = P3[offp];
+            if (!pre_c && p.beta != 0.0) qcr[u] = C[off];
+            if (p.rs) rsv[u] = p.rs[in[u] ? gi[u] : 0];
           }
-          store_c((TC*)o.ptr + (long long)w * p.sC + off, x);
+          if (p.cs) csv = p.cs[gj < Nc ? gj : 0];
+#pragma unroll
+          for (int u = 0; u < EV; ++u) {
+            const int v = v0 + u;
+            if (gi[u] >= p.mpad || gj >= p.npad) continue;
+            if (ROLE == 1 && gi[u] >= p.skip0 && gi[u] < p.skip1) continue;   // rows left untouched
+            const long long off = (long long)gi[u] * p.ldc + gj;
+            const double2 acc = make_double2((double)accR[i][j][v], (double)accI[i][j][v]);
+            double2 q1 = to_d2(q1r[u]), q2 = to_d2(q2r[u]), q3 = to_d2(q3r[u]), qc = to_d2(qcr[u]);
+            if constexpr (PREF) {
+              if (pre_p1) q1 = to_d2(pre[i][j][v]);
+              if (pre_c) qc = to_d2(pre[i][j][v]);
+            }
+            const double di = (gi[u] == gj) ? 1.0 : 0.0;
+            double2 out = make_double2(0.0, 0.0);
+            if (in[u]) {
+              out = cscale(acc, p.alpha);
+              if (p.beta != 0.0) out = cadd(out, cscale(qc, p.beta));
+              out.x += p.cI * di;
+              out = cadd(out, cadd(cscale(q1, p.c1), cadd(cscale(q2, p.c2), cscale(q3, p.c3))));
+              if (p.rs) out = cscale(out, rsv[u]);
+              if (p.cs) out = cscale(out, csv);
+            }
+            store_c(C + off, out);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              if (e >= p.nextra) break;
+              const GemmOut& o = p.extra[e];
+              double2 x = make_double2(0.0, 0.0);
+              if (in[u]) {
+                x = cscale(acc, o.cacc);
+                x.x += o.cI * di;
+                x = cadd(x, cadd(cscale(q1, o.c1), cadd(cscale(q2, o.c2), cscale(q3, o.c3))));
+              }
+              store_c((TC*)o.ptr + (long long)w * p.sC + off, x);
+            }
+          }
         }
-      }
+  } else {
+    // the FP64 tiles keep the plain per-entry epilogue
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int gi = m0 + wr * TL::WM + i * 16 + Mfma<ACC>::row(lane, v);
+          const int gj = n0 + wc * TL::WN + j * 16 + li;
+          if (gi >= p.mpad || gj >= p.npad) continue;
+          if (ROLE == 1 && gi >= p.skip0 && gi < p.skip1) continue;   // rows left untouched
+          const long long off = (long long)gi * p.ldc + gj;
+          const bool in = gi < Mr && gj < Nc;
+          const double2 acc = make_double2((double)accR[i][j][v], (double)accI[i][j][v]);
+          double2 q1 = make_double2(0.0, 0.0), q2 = q1, q3 = q1, qc = q1;
+          if (in) {
+            const long long offp = (long long)gi * p.ldp + gj;
+            if (pre_p1) { if constexpr (PREF) q1 = to_d2(pre[i][j][v]); }
+            else if (P1) q1 = ld_c(P1 + offp);
+            if (P2) q2 = ld_c(P2 + offp);
+            if (P3) q3 = ld_c(P3 + offp);
+            if (pre_c) { if constexpr (PREF) qc = to_d2(pre[i][j][v]); }
+            else if (p.beta != 0.0) qc = ld_c(C + off);
+          }
+          const double di = (gi == gj) ? 1.0 : 0.0;
+          double2 out = make_double2(0.0, 0.0);
+          if (in) {
+            out = cscale(acc, p.alpha);
+            if (p.beta != 0.0) out = cadd(out, cscale(qc, p.beta));
+            out.x += p.cI * di;
+            out = cadd(out, cadd(cscale(q1, p.c1), cadd(cscale(q2, p.c2), cscale(q3, p.c3))));
+            if (p.rs) out = cscale(out, p.rs[gi]);
+            if (p.cs) out = cscale(out, p.cs[gj]);
+          }
+          store_c(C + off, out);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if (e >= p.nextra) break;
+            const GemmOut& o = p.extra[e];
+            double2 x = make_double2(0.0, 0.0);
+            if (in) {
+              x = cscale(acc, o.cacc);
+              x.x += o.cI * di;
+              x = cadd(x, cadd(cscale(q1, o.c1), cadd(cscale(q2, o.c2), cscale(q3, o.c3))));
+            }
+            store_c((TC*)o.ptr + (long long)w * p.sC + off, x);
+          }
+        }
+  }
 }
 
 typedef Tile<64, 64, 16, 32, 32> T64x64;     // 4 waves of 32 x 32
