@@ -9,7 +9,9 @@
 // MFMAs.
 //
 // Tiling: a BM x BN output tile per workgroup of (BM/WM) x (BN/WN) waves, each wave a WM x WN
-// tile of 16 x 16 MFMA blocks; K staged through LDS BK at a time, double-buffered.  Several
+// tile of 16 x 16 MFMA blocks; K staged through LDS BK at a time, double-buffered: the next
+// k-tile's global loads are in flight during the current k-tile's MFMAs (for the FP32-MFMA
+// propagator products every load is unconditional, so that none of them is waited for early).  Several
 // tile shapes are built; the library times them on the real problem size at start-up and
 // keeps the fastest per system and precision (see gemm_tile_count / the tile field).
 // Complex products use four real MFMAs: re += a.re b.re - a.im b.im,
