@@ -209,34 +209,37 @@ __global__ __launch_bounds__(RQ_NT) void rq_stream_kernel(SysDev s) {
   __shared__ int Is[RQ_ELEMS];
   const int w = blockIdx.x;
   if (w >= s.W) return;
-  const int t = threadIdx.x, NQ = s.NQ, ld = s.ld;
+  const int t = threadIdx.x, NQ = s.NQ, ld = s.ld, npair = s.M * (s.M - 1);
   const double2* G = s.G + (long long)w * s.mat_stride;
+  // Block b's rows of G are contiguous (nr ld <= RQ_ELEMS entries).  Its pair list starts where
+  // block b-1's ends (so no load waits for another) and has fewer than nr ld entries.  The index
+  // loads are unconditional, at a clamped index: entries of Is past the block's own are loaded
+  // but never read.
   double2 gv[RQ_PER];
-  int iv[RQ_PER], qs[RQ_QPT], qe[RQ_QPT];
-  // block b: rows [b rq_rows, ...) of G are contiguous (nr ld entries, nr ld <= RQ_ELEMS); its
-  // pair list has fewer than nr ld entries
-  auto fetch = [&](int b) {
+  int iv[RQ_PER], qs[RQ_QPT], qe[RQ_QPT], iend = 0;
+  auto fetch = [&](int b, int i0) {
     const int r0 = b * s.rq_rows, nr = min(s.rq_rows, s.M - r0), n = nr * ld;
     const double2* gb = G + (long long)r0 * ld;
     const int* bp = s.rbptr + (long long)b * (NQ + 1);
-    const int i0 = bp[0], ni = bp[NQ] - i0;
 #pragma unroll
     for (int k = 0; k < RQ_PER; ++k) {
       const int e = t + k * RQ_NT;
       gv[k] = e < n ? gb[e] : zero2();
-      iv[k] = e < ni ? s.rbidx[i0 + e] : 0;
+      iv[k] = s.rbidx[min(i0 + e, npair - 1)];
     }
 #pragma unroll
     for (int i = 0; i < RQ_QPT; ++i) {
-      const int q = t + i * RQ_NT;
-      qs[i] = q < NQ ? bp[q] - i0 : 0;
-      qe[i] = q < NQ ? bp[q + 1] - i0 : 0;
+      const int q = t + i * RQ_NT, qc = q < NQ ? q : 0;
+      qs[i] = bp[qc];                  // absolute offsets; made relative when used
+      qe[i] = bp[qc + 1];
     }
+    iend = bp[NQ];
   };
   double2 acc[RQ_QPT];
 #pragma unroll
   for (int i = 0; i < RQ_QPT; ++i) acc[i] = zero2();
-  fetch(0);
+  int i0 = 0;                          // start of the current block's pair list
+  fetch(0, 0);
   for (int b = 0; b < s.rq_nblk; ++b) {
     __syncthreads();                 // every gather of the previous block is done
 #pragma unroll
@@ -246,12 +249,18 @@ __global__ __launch_bounds__(RQ_NT) void rq_stream_kernel(SysDev s) {
     }
     int cs[RQ_QPT], ce[RQ_QPT];
 #pragma unroll
-    for (int i = 0; i < RQ_QPT; ++i) { cs[i] = qs[i]; ce[i] = qe[i]; }
+    for (int i = 0; i < RQ_QPT; ++i) {
+      const bool mine = t + i * RQ_NT < NQ;
+      cs[i] = mine ? qs[i] - i0 : 0;
+      ce[i] = mine ? qe[i] - i0 : 0;
+    }
+    const int inext = iend;
     __syncthreads();
-    if (b + 1 < s.rq_nblk) fetch(b + 1);
+    if (b + 1 < s.rq_nblk) fetch(b + 1, inext);
 #pragma unroll
     for (int i = 0; i < RQ_QPT; ++i)
       for (int e = cs[i]; e < ce[i]; ++e) acc[i] = csub(acc[i], Gs[Is[e]]);
+    i0 = inext;
   }
 #pragma unroll
   for (int i = 0; i < RQ_QPT; ++i) {
@@ -684,7 +693,7 @@ hipError_t launch_greens_post(const SysDev& s, int k, hipStream_t st) {
 }
 int rq_block_elems() { return RQ_ELEMS; }
 hipError_t launch_weight(const SysDev& s, int k, double sum_lnLb, int init, hipStream_t st) {
-  if (s.NQ <= RQ_QPT * RQ_NT && s.rq_rows * s.ld <= RQ_ELEMS) {
+  if (s.NQ > 0 && s.NQ <= RQ_QPT * RQ_NT && s.rq_rows * s.ld <= RQ_ELEMS) {
     rq_stream_kernel<<<s.W, RQ_NT, 0, st>>>(s);
   } else {
     const int chunks = (s.NQ + NT - 1) / NT;
