@@ -80,6 +80,17 @@ def force_bias(sys, P):
     return -sdt * vA, -sdt * vB
 
 
+def importance_exponent(xA, xB, xbA, xbB):
+    """Exponent of the exponential factor of the importance function, eq. import.
+
+    Sampling the shifted field x - xbar instead of x multiplies each walker's weight by
+    exp(sum_alpha [x_alpha xbar_alpha - xbar_alpha^2 / 2]) (the Gaussian density ratio of
+    the shift), summed over both fields A(Q) and B(Q) of every momentum transfer.  The
+    shift may be complex; the sum is returned complex (its real part enters |I|).
+    """
+    return np.sum(xA * xbA + xB * xbB - 0.5 * (xbA ** 2 + xbB ** 2))
+
+
 def slice_propagator(sys, yA, yB):
     """B = e^{-dtau/2 (H_1 - mu N)} e^{sqrt(dtau) y.v} e^{-dtau/2 (H_1 - mu N)}, eq. B."""
     V = one_body_matrix(sys, hs_rho_coefficients(sys, yA, yB))
@@ -193,7 +204,7 @@ def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, st
         xbA, xbB = force_bias(sys, P)
         xA, xB = z[k].real, z[k].imag
         V = one_body_matrix(sys, hs_rho_coefficients(sys, xA - xbA, xB - xbB))
-        expo = np.sum(xA * xbA + xB * xbB - 0.5 * (xbA ** 2 + xbB ** 2))
+        expo = importance_exponent(xA, xB, xbA, xbB)
         if record_path:
             Vs.append(V)
             expos.append(expo)

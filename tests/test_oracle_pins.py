@@ -370,3 +370,66 @@ def test_phaseless_kill_keeps_propagating():
     assert killed["logw"] == -np.inf
     assert np.all(np.isfinite(killed["G"]))
     assert all(r["logw"] == -np.inf for r in killed["records"] if r["slice"] > first + 1)
+
+
+# ------------------------------------------------ importance exponent ---
+def _overlap_ratio_of_field(s, right, k, ell_k, comp, q, y):
+    """S(y) = det(I + B_T^{n-k-1} B(y) R_k)^2 / det(I + A_k)^2 for a slice whose only nonzero
+    field is component comp ('A' or 'B') of momentum transfer q, set to the (complex) value y."""
+    yA = np.zeros(s.NQ, dtype=np.complex128)
+    yB = np.zeros(s.NQ, dtype=np.complex128)
+    (yA if comp == "A" else yB)[q] = y
+    B = path.slice_propagator(s, yA, yB)
+    r = path.RightBlock(s.M)
+    r.Q, r.D, r.T = right.Q.copy(), right.D.copy(), right.T.copy()
+    r.push(B)
+    _, ell = path.greens_at(s, r, k + 1)
+    return np.exp(2.0 * (ell - ell_k))
+
+
+@pytest.mark.parametrize("nmax2,real_greens", [(1, True), (1, False), (2, True), (2, False)],
+                         ids=["m7_realG", "m7_complexG", "m19_realG", "m19_complexG"])
+def test_importance_exponent_cameron_martin(nmax2, real_greens):
+    """Cameron-Martin identity for the exponential factor of eq. import.
+
+    For x ~ N(0,1) and any shift xbar (complex allowed), E_x[f(x - xbar) exp(x xbar - xbar^2/2)]
+    = E_y[f(y)], because x xbar - xbar^2/2 - x^2/2 = -(x - xbar)^2/2.  Both sides are taken by
+    60-node Gauss-Hermite quadrature (no sampling) for f = the overlap ratio S of one slice as a
+    function of a single field component, with the force-bias shift of that component taken
+    from a walker's G_k (its real part, or G_k itself).  oracle.path.importance_exponent must
+    reproduce the identity to 1e-10: a dropped -xbar^2/2, a flipped sign of the linear term or
+    an A/B mix-up would break it by |xbar|- or |xbar|^2-sized amounts (|xbar| >= 1e-3 here).
+    """
+    s = ueg.UEGSystem(14 if nmax2 == 2 else 2, 1.0, 0.5, nmax2, 0.05, stab_every=1)
+    z = si.walker_fields(4242, 0, s.n_slices, s.NQ)
+    k = 11
+    out = path.run_walker(s, z, stop_after=k)
+    right = out["right"]
+    G, ell_k = path.greens_at(s, right, k)
+    if real_greens:
+        G = G.real.astype(np.complex128)
+    xbA, xbB = path.force_bias(s, np.eye(s.M) - G.T)
+    t, wgh = np.polynomial.hermite.hermgauss(60)
+    nodes, weights = np.sqrt(2.0) * t, wgh / np.sqrt(np.pi)   # E over N(0,1)
+    checked = 0
+    for comp, xb_all in (("A", xbA), ("B", xbB)):
+        q = int(np.argmax(np.abs(xb_all)))                     # the component with the largest shift
+        xb = xb_all[q]
+        assert abs(xb) > 1e-3
+        rhs = sum(wt * _overlap_ratio_of_field(s, right, k, ell_k, comp, q, y) for y, wt in zip(nodes, weights))
+        lhs = 0.0
+        for x, wt in zip(nodes, weights):
+            xs = np.zeros(s.NQ)
+            xbs = np.zeros(s.NQ, dtype=np.complex128)
+            xs[q], xbs[q] = x, xb
+            zero = np.zeros(s.NQ)
+            expo = (path.importance_exponent(xs, zero, xbs, zero) if comp == "A"
+                    else path.importance_exponent(zero, xs, zero, xbs))
+            lhs += wt * _overlap_ratio_of_field(s, right, k, ell_k, comp, q, x - xb) * np.exp(expo)
+        assert abs(lhs - rhs) < 1e-10 * abs(rhs), (comp, q, xb, lhs, rhs)
+        # the identity is sharp: without the quadratic term it fails by about |xbar|^2 / 2
+        wrong = sum(wt * _overlap_ratio_of_field(s, right, k, ell_k, comp, q, x - xb) * np.exp(x * xb)
+                    for x, wt in zip(nodes, weights))
+        assert abs(wrong - rhs) > 0.1 * abs(xb) ** 2 * abs(rhs)
+        checked += 1
+    assert checked == 2
