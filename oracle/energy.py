@@ -59,3 +59,21 @@ def local_energy_loops(sys, G):
             (4.0 * g1 * g2 - 2.0 * lam)
     N = 2.0 * np.trace(P)
     return dict(E1=E1, E2=E2, E=E1 + E2 + sys.E_M, N=N)
+
+
+def density_correlation(sys, G):
+    """Local estimator of <rho(Q) rho(-Q)> for every momentum transfer Q (both spins), whose
+    ratio to N is the static structure factor S(Q) of Sec. "Results" (structure factor
+    section).  Wick's theorem with P = I - G^T (P_ij = <a^+_i a_j> per spin):
+      <rho(Q) rho(-Q)> = 4 r_Q r_{-Q} + 2 (n_Q - Lambda_Q),
+    r_Q = sum_K P_{K+Q,K} (per spin), n_Q = sum_{K: K, K+Q in basis} P_{K+Q,K+Q} (the contraction
+    of a_K with a^+_{K}), Lambda_Q the exchange sum of local_energy."""
+    P = np.eye(sys.M) - G.T
+    rho = np.array([P[sys.pairs[q]].sum() for q in range(sys.NQ)], dtype=np.complex128)
+    out = np.empty(sys.NQ, dtype=np.complex128)
+    for q in range(sys.NQ):
+        p, r = sys.pairs[q]
+        lam = np.sum(P[np.ix_(p, p)] * P[np.ix_(r, r)].T)
+        nq = np.sum(P[p, p])
+        out[q] = 4.0 * rho[q] * rho[sys.neg[q]] + 2.0 * (nq - lam)
+    return out

@@ -183,6 +183,15 @@ def wrap_angle(x):
 ALIVE, KILLED, NUMERIC = 0, 1, 2
 
 
+def shifted_one_body(sys, G, z_k):
+    """The shifted one-body matrix V = sqrt(dtau) (x - xbar).v of a slice with fields z_k and
+    the force bias from G, and the exponent of eq. import."""
+    xbA, xbB = force_bias(sys, np.eye(sys.M) - G.T)
+    xA, xB = z_k.real, z_k.imag
+    V = one_body_matrix(sys, hs_rho_coefficients(sys, xA - xbA, xB - xbB))
+    return V, importance_exponent(xA, xB, xbA, xbB)
+
+
 def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, stop_after=None,
                record_path=False):
     """Propagate one walker from tau = 0 to tau = beta with fields z[k, q].
@@ -200,11 +209,7 @@ def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, st
     Vs, expos = [], []
 
     def shifted(k, G):
-        P = np.eye(sys.M) - G.T
-        xbA, xbB = force_bias(sys, P)
-        xA, xB = z[k].real, z[k].imag
-        V = one_body_matrix(sys, hs_rho_coefficients(sys, xA - xbA, xB - xbB))
-        expo = importance_exponent(xA, xB, xbA, xbB)
+        V, expo = shifted_one_body(sys, G, z[k])
         if record_path:
             Vs.append(V)
             expos.append(expo)
@@ -227,47 +232,77 @@ def replay_walker(sys, frozen, measure_every=None, energy_fn=None, keep_greens=F
     return _walk(sys, recorded, measure_every, energy_fn, keep_greens, None)
 
 
+class Walker:
+    """One walker at slice k: the QDT factors of its sampled product R_k, G_k and
+    ln det(I + A_k) (A_k = B_T^{n-k} R_k), ln w and its status.  step() inserts the next slice
+    propagator and applies the phaseless weight update; copy() clones the walker (population
+    control copies whole walkers)."""
+
+    def __init__(self, sys):
+        self.sys = sys
+        self.k = 0
+        self.right = RightBlock(sys.M)
+        self.G, self.ell = greens_at(sys, self.right, 0)
+        self.logw, self.status = 0.0, ALIVE
+
+    def copy(self):
+        w = Walker.__new__(Walker)
+        w.sys, w.k = self.sys, self.k
+        w.right = RightBlock(self.sys.M)
+        w.right.Q, w.right.D, w.right.T = self.right.Q.copy(), self.right.D.copy(), self.right.T.copy()
+        w.G, w.ell, w.logw, w.status = self.G.copy(), self.ell, self.logw, self.status
+        return w
+
+    def advance(self, z_k):
+        """One slice with fields z_k (force bias from this walker's G_k)."""
+        return self.step(*shifted_one_body(self.sys, self.G, z_k))
+
+    def step(self, V, expo):
+        """Slice k -> k+1 with B = K e^V K (eq. B); returns (ln S, theta, ln |I|)."""
+        sys, k = self.sys, self.k
+        kh = np.exp(-0.5 * sys.dtau * sys.h1_diag())
+        B = kh[:, None] * sla.expm(V) * kh[None, :]          # eq. B
+        self.right.push(B)
+        self.G, ell_new = greens_at(sys, self.right, k + 1)
+        lnS = 2.0 * (ell_new - self.ell)
+        self.ell = ell_new
+        theta = float(wrap_angle(lnS.imag))
+        lnI = lnS.real + expo.real
+        if self.status == ALIVE:
+            if not (np.all(np.isfinite(self.G)) and np.isfinite(lnI)):
+                self.status, self.logw = NUMERIC, -np.inf
+            elif np.cos(theta) <= 0.0:
+                self.status, self.logw = KILLED, -np.inf
+            else:
+                self.logw += lnI + np.log(np.cos(theta))
+        self.k = k + 1
+        return lnS, theta, lnI
+
+
 def _walk(sys, shifted, measure_every, energy_fn, keep_greens, stop_after):
-    n, M = sys.n_slices, sys.M
+    n = sys.n_slices
     s = sys.stab_every if measure_every is None else measure_every
-    right = RightBlock(M)
-    G, ell = greens_at(sys, right, 0)
-    ell0 = ell
-    logw, status = 0.0, ALIVE
+    wk = Walker(sys)
+    ell0 = wk.ell
     lnS_all = np.zeros(n, dtype=np.complex128)
     theta_all = np.zeros(n)
     lnI_all = np.zeros(n)
     alive_after = np.zeros(n, dtype=bool)
     records, greens = [], []
-    greens_all = [G.copy()] if keep_greens == "all" else None
-    kh = np.exp(-0.5 * sys.dtau * sys.h1_diag())
+    greens_all = [wk.G.copy()] if keep_greens == "all" else None
     for k in range(n if stop_after is None else min(n, int(stop_after))):
-        V, expo = shifted(k, G)
-        B = kh[:, None] * sla.expm(V) * kh[None, :]          # eq. B
-        right.push(B)
-        G, ell_new = greens_at(sys, right, k + 1)
-        lnS = 2.0 * (ell_new - ell)
-        ell = ell_new
-        theta = float(wrap_angle(lnS.imag))
-        lnI = lnS.real + expo.real
-        lnS_all[k], theta_all[k], lnI_all[k] = lnS, theta, lnI
-        if status == ALIVE:
-            if not (np.all(np.isfinite(G)) and np.isfinite(lnI)):
-                status, logw = NUMERIC, -np.inf
-            elif np.cos(theta) <= 0.0:
-                status, logw = KILLED, -np.inf
-            else:
-                logw += lnI + np.log(np.cos(theta))
-        alive_after[k] = status == ALIVE
+        V, expo = shifted(k, wk.G)
+        lnS_all[k], theta_all[k], lnI_all[k] = wk.step(V, expo)
+        alive_after[k] = wk.status == ALIVE
         if greens_all is not None:
-            greens_all.append(G.copy())
+            greens_all.append(wk.G.copy())
         if (k + 1) % s == 0 or k + 1 == n:
-            rec = dict(slice=k + 1, logw=logw, status=status, lndet=ell)
+            rec = dict(slice=k + 1, logw=wk.logw, status=wk.status, lndet=wk.ell)
             if energy_fn is not None:
-                rec.update(energy_fn(sys, G))
+                rec.update(energy_fn(sys, wk.G))
             records.append(rec)
             if keep_greens:
-                greens.append(G.copy())
-    return dict(G=G, lndet=ell, lndet0=ell0, logw=logw, status=status, lnS=lnS_all,
+                greens.append(wk.G.copy())
+    return dict(G=wk.G, lndet=wk.ell, lndet0=ell0, logw=wk.logw, status=wk.status, lnS=lnS_all,
                 theta=theta_all, lnI=lnI_all, alive=alive_after, records=records, greens=greens,
-                greens_all=greens_all, right=right)
+                greens_all=greens_all, right=wk.right)

@@ -48,6 +48,28 @@ def box_length(n_elec, rs):
     return (4.0 * np.pi * n_elec / 3.0) ** (1.0 / 3.0) * rs
 
 
+def thermal_hartree_fock_levels(eps, vmat, beta, n_elec, tol=1e-14, max_iter=10000):
+    """Self-consistent levels of the thermal Hartree-Fock (Mermin) trial, Sec. "Results"
+    (fig. thf): per spin e_K = |K|^2/2 - sum_{K' != K} v(K - K') f_K' with
+    f_K = 1 / (1 + exp(beta (e_K - mu))) and 2 sum_K f_K = N (the Hartree term Q = 0 is
+    removed with the neutralising background; a plane wave is a Hartree-Fock orbital of the
+    uniform gas, so the trial stays diagonal).  vmat[K, K'] = v(K - K'), zero on the diagonal.
+    Plain fixed-point iteration with mixing 1/2 (the map contracts for these sizes).
+    Returns (e [M], mu)."""
+    e = eps.copy()
+    for _ in range(max_iter):
+        mu = trial_chemical_potential(e, beta, n_elec)
+        f = expit(-beta * (e - mu))
+        e_new = eps - vmat @ f
+        if np.max(np.abs(e_new - e)) <= tol * max(1.0, np.max(np.abs(e))):
+            e = e_new
+            break
+        e = 0.5 * (e + e_new)
+    else:
+        raise RuntimeError("thermal Hartree-Fock iteration did not converge")
+    return e, trial_chemical_potential(e, beta, n_elec)
+
+
 def trial_chemical_potential(eps, beta, n_elec):
     """mu_T with 2 sum_K f(eps_K; mu_T) = N by bisection (spin factor 2)."""
     def count(mu):
@@ -78,7 +100,7 @@ class UEGSystem:
     """
 
     def __init__(self, n_elec, rs, theta, nmax2, dtau, stab_every=1, mu=None,
-                 kscale=1.0, walkers=None):
+                 kscale=1.0, walkers=None, trial="fe"):
         self.n_elec, self.rs, self.theta, self.nmax2 = int(n_elec), float(rs), float(theta), int(nmax2)
         self.stab_every = int(stab_every)
         self.kscale = float(kscale)
@@ -122,7 +144,18 @@ class UEGSystem:
         self.hK = np.array([-0.5 * np.sum(self.vq[self.idx[p][self.idx[p] >= 0]])
                             for p in range(self.M)])
 
-        self.mu_T = trial_chemical_potential(self.eps, self.beta, self.n_elec)
+        # trial levels: free-electron |K|^2/2, or thermal Hartree-Fock
+        self.trial = trial
+        if trial == "fe":
+            self.trial_levels = self.eps.copy()
+            self.mu_T = trial_chemical_potential(self.eps, self.beta, self.n_elec)
+        elif trial == "thf":
+            vmat = np.zeros((self.M, self.M))
+            off = self.idx >= 0
+            vmat[off] = self.vq[self.idx[off]]
+            self.trial_levels, self.mu_T = thermal_hartree_fock_levels(self.eps, vmat, self.beta, self.n_elec)
+        else:
+            raise ValueError("trial is 'fe' or 'thf'")
         self.mu = self.mu_T if mu is None or (isinstance(mu, float) and np.isnan(mu)) else float(mu)
         self.E_M = -MADELUNG_CONSTANT * self.n_elec / (2.0 * self.L)
         self.walkers = walkers
@@ -133,8 +166,9 @@ class UEGSystem:
         return self.kscale * self.eps + self.hK - self.mu
 
     def log_trial_diag(self):
-        """log of the diagonal of B_T = exp(-dtau (|K|^2/2 - mu_T))."""
-        return -self.dtau * (self.eps - self.mu_T)
+        """log of the diagonal of B_T = exp(-dtau (e_K - mu_T)), e_K = |K|^2/2 (free-electron
+        trial) or the thermal Hartree-Fock levels."""
+        return -self.dtau * (self.trial_levels - self.mu_T)
 
     def info(self):
         return dict(M=self.M, n_q=self.NQ, n_slices=self.n_slices, beta=self.beta,

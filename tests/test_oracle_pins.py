@@ -173,6 +173,30 @@ def test_trace_equals_det_squared_and_wick_energy():
     assert loops["E2"] == pytest.approx(est["E2"], rel=1e-12)
 
 
+def test_density_correlation_against_fock_space():
+    """<rho(Q) rho(-Q)> (the static structure factor times N) by Wick's theorem against the
+    Fock-space trace with both spins: 2 tr(A rho_Q rho_-Q) / tr A (same spin) plus
+    2 tr(A rho_Q) tr(A rho_-Q) / (tr A)^2 (opposite spins), at M = 7 for every Q."""
+    sysx = _small_system(theta=0.5, rs=3.0, dtau=0.3, kscale=0.9)
+    a = fs.annihilators(sysx.M)
+    g = np.random.default_rng(17)
+    flds = [(g.standard_normal(sysx.NQ) + 0.3j * g.standard_normal(sysx.NQ),
+             g.standard_normal(sysx.NQ) - 0.2j * g.standard_normal(sysx.NQ)) for _ in range(3)]
+    Af = _fock_walker(sysx, flds, a)
+    right = path.RightBlock(sysx.M)
+    for yA, yB in flds:
+        right.push(path.slice_propagator(sysx, yA, yB))
+    G, _ = path.greens_at(sysx, right, sysx.n_slices)
+    tr1 = np.trace(Af)
+    rho = [fs.rho_operator(sysx, q, a) for q in range(sysx.NQ)]
+    est = energy.density_correlation(sysx, G)
+    for q in range(sysx.NQ):
+        qn = sysx.neg[q]
+        brute = (2.0 * np.trace(Af @ rho[q] @ rho[qn]) / tr1
+                 + 2.0 * np.trace(Af @ rho[q]) * np.trace(Af @ rho[qn]) / tr1 ** 2)
+        assert est[q] == pytest.approx(brute, rel=1e-11, abs=1e-12), q
+
+
 def test_expm_of_unshifted_field_is_unitary_and_matches_eigh():
     sysx = ueg.UEGSystem(14, 1.0, 0.5, 2, 0.05)
     g = np.random.default_rng(3)
@@ -433,3 +457,50 @@ def test_importance_exponent_cameron_martin(nmax2, real_greens):
         assert abs(wrong - rhs) > 0.1 * abs(xb) ** 2 * abs(rhs)
         checked += 1
     assert checked == 2
+
+
+# ---------------------------------------------------- thermal HF trial ---
+@pytest.mark.parametrize("args", [(2, 3.0, 1.0, 1), (14, 1.0, 0.5, 2), (38, 2.0, 0.25, 9)])
+def test_thermal_hartree_fock_trial_is_stationary_point_of_mermin_functional(args):
+    """The thermal Hartree-Fock trial (Sec. "Results", fig. thf; Mermin's finite-temperature
+    Hartree-Fock) minimises nothing in particular but must make Mermin's grand potential of
+    spin-restricted plane-wave occupations stationary:
+      Omega(f) = 2 sum_K eps_K f_K - sum_{K != K'} v(K - K') f_K f_K' - 2 mu sum_K f_K
+                 + (2 / beta) sum_K [f_K ln f_K + (1 - f_K) ln(1 - f_K)],
+    written here from its definition (kinetic, same-spin exchange, particle reservoir, entropy).
+    Central differences of Omega at the oracle's occupations vanish, and 2 sum f = N."""
+    n, rs, theta, nmax2 = args
+    s = ueg.UEGSystem(n, rs, theta, nmax2, 0.05, trial="thf")
+    f = 1.0 / (1.0 + np.exp(s.beta * (s.trial_levels - s.mu_T)))
+    assert abs(2.0 * f.sum() - n) < 1e-10 * n
+    v = np.zeros((s.M, s.M))
+    for p in range(s.M):
+        for r in range(s.M):
+            if p != r:
+                v[p, r] = 4.0 * np.pi / (s.omega * np.sum((2 * np.pi / s.L * (s.nvec[p] - s.nvec[r])) ** 2))
+
+    def omega(ff):
+        ent = ff * np.log(ff) + (1.0 - ff) * np.log(1.0 - ff)
+        return (2.0 * s.eps @ ff - ff @ v @ ff - 2.0 * s.mu_T * ff.sum() + 2.0 / s.beta * ent.sum())
+
+    def dOmega_dx(ff, K, h=1e-4):
+        """Central difference in the logit x_K of f_K (f = 1 / (1 + e^-x)): dOmega/df_K f(1-f)."""
+        x = np.log(ff[K] / (1.0 - ff[K]))
+        up, dn = ff.copy(), ff.copy()
+        up[K] = 1.0 / (1.0 + np.exp(-(x + h)))
+        dn[K] = 1.0 / (1.0 + np.exp(-(x - h)))
+        return (omega(up) - omega(dn)) / (2.0 * h)
+
+    scale = np.abs(2.0 * s.eps).max() + 2.0 * np.abs(v).sum(1).max()
+    checked = 0
+    for K in range(s.M):
+        fk = f[K] * (1.0 - f[K])
+        if fk < 1e-3:
+            continue
+        assert abs(dOmega_dx(f, K)) < 1e-7 * scale * fk, K
+        checked += 1
+    assert checked >= 1
+    # the free-electron occupations are not stationary once the exchange is on
+    f0 = 1.0 / (1.0 + np.exp(s.beta * (s.eps - ueg.trial_chemical_potential(s.eps, s.beta, n))))
+    K = int(np.argmin(np.abs(f0 - 0.5)))
+    assert abs(dOmega_dx(f0, K)) > 1e-2 * f0[K] * (1.0 - f0[K])
