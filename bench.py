@@ -61,6 +61,8 @@ def cpu_baseline(name, seconds_target=12.0):
     from oracle import ueg
     sd = si.WORKLOADS[name]["systems"][0]
     s = ueg.UEGSystem(sd["n_elec"], sd["rs"], sd["theta"], sd["nmax2"], sd["dtau"], stab_every=sd["stab_every"])
+    # one process per walker over the host share of one GPU: at most 16 processes, which is the
+    # CPU share a one-GPU machine gives a job whatever os.cpu_count() reports
     nproc = max(1, min(os.cpu_count() or 1, 16, sd["walkers"]))
     # calibrate the slice count so that each process works for about seconds_target
     dt1, n1 = _oracle_worker((name, 0, 0, 2))
@@ -70,63 +72,151 @@ def cpu_baseline(name, seconds_target=12.0):
         res = list(ex.map(_oracle_worker, [(name, 0, w, n_run) for w in range(nproc)]))
     wall = time.time() - t
     ws = sum(r[1] for r in res)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": ws / wall, "unit": "walker*slices/s", "cores": nproc, "kind": "oracle",
+            "os_cpu_count": os.cpu_count(), "cpu_model": model,
             "sample": "%d walkers x first %d of %d slices of %s (one process and one BLAS thread per walker)"
                       % (nproc, n_run, s.n_slices, name)}
 
 
+def _path(ctx, fields, n_sys):
+    ctx.reset()
+    ctx.propagate(fields)
+    for i in range(n_sys):
+        ctx.energy(i)
+
+
 def run_precision(F, torch, systems, fields, steps, warmup):
+    """Time `steps` whole paths with no instrumentation (the throughput), then the same number
+    of paths with HIP events around the propagator GEMMs only (the roofline's per-launch time),
+    then one path with events around every launch (the per-class breakdown)."""
     ctx = F.Context(systems)
-    infos = [ctx.info(i) for i in range(len(systems))]
+    n_sys = len(systems)
+    infos = [ctx.info(i) for i in range(n_sys)]
     for _ in range(warmup):
-        ctx.reset()
-        ctx.propagate(fields)
-        for i in range(len(systems)):
-            ctx.energy(i)
-    torch.cuda.synchronize()
-    # the timed steps carry HIP events around the propagator GEMMs only (the roofline's kernel)
-    ctx.profile(True, classes=["gemm"])
+        _path(ctx, fields, n_sys)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.reset()
-        ctx.propagate(fields)
-        for i in range(len(systems)):
-            ctx.energy(i)
+        _path(ctx, fields, n_sys)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = ctx.profile(False)
-    # one more, untimed step with events around every launch: the per-class breakdown
-    ctx.profile(True)
-    ctx.reset()
-    ctx.propagate(fields)
-    for i in range(len(systems)):
-        ctx.energy(i)
-    classes = ctx.profile(False)
     ws = sum(inf["n_walkers"] * inf["n_slices"] for inf in infos)
-    out = {"seconds": t1 - t0, "walker_slices_per_s": ws * steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
-           "profile_ms_per_step": {k: v[0] for k, v in classes.items()},
-           "launches_per_step": {k: v[1] for k, v in classes.items()}}
+    out = {"seconds": t1 - t0, "walker_slices_per_s": ws * steps / (t1 - t0),
+           "ms_per_step": 1e3 * (t1 - t0) / steps}
+    # the roofline's kernel: events on the library's stream around every propagator GEMM launch
+    ctx.profile(True, classes=["gemm"])
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        _path(ctx, fields, n_sys)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    prof = ctx.profile(False)
+    out["ms_per_step_gemm_events"] = 1e3 * (t3 - t2) / steps
+    ctx.profile(True)
+    _path(ctx, fields, n_sys)
+    classes = ctx.profile(False)
+    out["profile_ms_per_step"] = {k: v[0] for k, v in classes.items()}
+    out["launches_per_step"] = {k: v[1] for k, v in classes.items()}
     gemm_ms, gemm_n = prof["gemm"]
-    # Propagator products per slice: V^2, V^3, V^4 (with the Taylor blocks), the Horner steps and
-    # the apply; 7 in FP64 (degree 16), 6 in mixed (degree 12).  Each walker group of a system
-    # launches them for its own walkers: one complex M x M x M product per walker and launch
-    # (8 M^3 algorithmic flops per walker), so the total does not depend on the grouping.
-    products = 7 if systems[0].get("precision", 0) == 0 else 6
-    assert gemm_n == products * sum(inf["n_slices"] * inf["walker_groups"] for inf in infos) * steps, (gemm_n, products)
-    flops = steps * sum(products * inf["n_slices"] * 8.0 * inf["M"] ** 3 * inf["n_walkers"] for inf in infos)
+    # Propagator products per slice for Taylor degree 4 nb: V^2, V^3, V^4 (with the Taylor
+    # blocks), nb - 1 Horner steps and the apply.  Each walker group of a system launches them
+    # for its own walkers: one complex M x M x M product per walker and launch (8 M^3
+    # algorithmic flops per walker), so the total does not depend on the grouping.
+    prods = [inf["taylor_degree"] // 4 + 3 for inf in infos]
+    want_n = sum(pr * inf["n_slices"] * inf["walker_groups"] for pr, inf in zip(prods, infos)) * steps
+    assert gemm_n == want_n, (gemm_n, want_n)
+    flops = steps * sum(pr * inf["n_slices"] * 8.0 * inf["M"] ** 3 * inf["n_walkers"] for pr, inf in zip(prods, infos))
+    out["taylor_degree"] = [inf["taylor_degree"] for inf in infos]
+    out["gemm_products_per_slice"] = prods
     out["gemm_avg_ms"] = gemm_ms / max(gemm_n, 1)
     out["gemm_flops_per_launch"] = flops / max(gemm_n, 1)
     out["gemm_tflops"] = flops / (gemm_ms * 1e-3) / 1e12
     out["walker_groups"] = [inf["walker_groups"] for inf in infos]
-    energies, status = [], []
-    for i in range(len(systems)):
+    energies = []
+    for i in range(n_sys):
         e = ctx.energy(i)
-        energies.append((e["local"].cpu().numpy(), e["logw"].cpu().numpy()))
-        status.append(e["status"].cpu().numpy())
+        energies.append(dict(local=e["local"].cpu().numpy(), logw=e["logw"].cpu().numpy(),
+                             status=e["status"].cpu().numpy(), mean=e["mean"].cpu().numpy()))
     out["gemm_tiles"] = [(inf["gemm_tile_chain"], inf["gemm_tile_epilogue"], inf["gemm_tile_horner"],
                           inf["gemm_tile_apply"]) for inf in infos]
-    return ctx, out, energies, status
+    return ctx, out, energies
+
+
+def mixed_vs_fp64(en64, enmx):
+    """Errors of the mixed path against the FP64 path on the same fields, per system and over
+    all: status mismatches; per walker alive in both, |(E1+E2)_mx - (E1+E2)_64| / |(E1+E2)_64|,
+    the same over |E1| + |E2|, N and ln w; and the weighted means <E1+E2> and <N> of
+    ftafqmc_energy (over each path's own live walkers and weights)."""
+    per = []
+    for a, b in zip(en64, enmx):
+        ok = (a["status"] == 0) & (b["status"] == 0)
+        la, lb = a["local"][ok], b["local"][ok]
+        e12a, e12b = la[:, 0] + la[:, 1], lb[:, 0] + lb[:, 1]
+        ma, mb = a["mean"], b["mean"]
+        per.append({
+            "status_counts_fp64": [int(np.sum(a["status"] == v)) for v in (0, 1, 2)],
+            "status_counts_mixed": [int(np.sum(b["status"] == v)) for v in (0, 1, 2)],
+            "status_mismatches": int(np.sum(a["status"] != b["status"])),
+            "walkers_compared": int(ok.sum()),
+            "max_rel_err_E1E2": float(np.max(np.abs(e12b - e12a) / np.abs(e12a))),
+            "max_err_E1E2_over_abs_sum": float(np.max(np.abs(e12b - e12a) / (np.abs(la[:, 0]) + np.abs(la[:, 1])))),
+            "max_rel_err_N": float(np.max(np.abs(lb[:, 3] - la[:, 3]) / np.abs(la[:, 3]))),
+            "max_abs_err_logw": float(np.max(np.abs(b["logw"][ok] - a["logw"][ok]))),
+            "rel_err_mean_E1E2": float(abs((mb[0] + mb[1]) - (ma[0] + ma[1])) / abs(ma[0] + ma[1])),
+            "rel_err_mean_N": float(abs(mb[3] - ma[3]) / abs(ma[3])),
+        })
+    tot = {k: (sum(p[k] for p in per) if k in ("status_mismatches", "walkers_compared") else max(p[k] for p in per))
+           for k in per[0] if not k.startswith("status_counts")}
+    tot["per_system"] = per
+    # the gate of the headline: every status equal, every walker's and the weighted mean's
+    # E1 + E2 within MIXED_E_TOL of the FP64 path
+    tot["within_tolerance"] = bool(tot["status_mismatches"] == 0 and tot["max_rel_err_E1E2"] <= MIXED_E_TOL
+                                   and tot["rel_err_mean_E1E2"] <= MIXED_E_TOL)
+    return tot
+
+
+def load_fields(F, torch, workload):
+    wl = si.WORKLOADS[workload]
+    fields = []
+    for i, sd in enumerate(wl["systems"]):
+        probe = F.Context([dict(sd, walkers=1)])     # field shapes (n, N_Q) from the library's tables
+        inf = probe.info()
+        probe.close()
+        f = si.fields(si.system_seed(workload, i), sd["walkers"], inf["n_slices"], inf["n_q"])
+        fields.append(torch.from_numpy(f).cuda())
+        del f
+    torch.cuda.synchronize()
+    return fields
+
+
+def bench_workload(F, torch, workload, precs, steps, warmup, overlap=False):
+    """Both precisions of one workload on the same fields: throughput, GEMM roofline and the
+    mixed path's errors against the FP64 path."""
+    wl = si.WORKLOADS[workload]
+    fields = load_fields(F, torch, workload)
+    results, energies = {}, {}
+    for p in precs:
+        systems = [dict(sd, precision=0 if p == "fp64" else 1, flags=F.FTAFQMC_OVERLAP if overlap else 0)
+                   for sd in wl["systems"]]
+        ctx, out, en = run_precision(F, torch, systems, fields, steps, warmup)
+        print("bench: %s %s %.1f walker*slices/s" % (workload, p, out["walker_slices_per_s"]), file=sys.stderr, flush=True)
+        pk = "f32" if p == "mixed" else "f64"
+        out["gemm_roofline_frac"] = out["gemm_tflops"] / PEAK_TFLOPS[pk]
+        results[p], energies[p] = out, en
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    if "fp64" in energies and "mixed" in energies:
+        results["mixed_vs_fp64"] = mixed_vs_fp64(energies["fp64"], energies["mixed"])
+    return results, fields
 
 
 def time_graph(F, torch, systems, fields, steps):
@@ -193,10 +283,11 @@ def time_backward(F, torch, workload="ueg_n38_m123"):
     ctx.energy()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ctx.profile(True)
     b = ctx.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    ctx.profile(True)                                # per-class breakdown from one more, untimed pass
+    ctx.backward()
     prof = ctx.profile(False)
     jac = b["jac"].cpu().numpy()
     ctx.close()
@@ -222,6 +313,8 @@ def main():
                     help="propagate with FTAFQMC_OVERLAP (two walker groups on two streams)")
     ap.add_argument("--no-overlap-schedule", action="store_true",
                     help="skip the extra timing of the mixed path with FTAFQMC_OVERLAP")
+    ap.add_argument("--no-extra-workloads", action="store_true",
+                    help="skip the one-path timings of the uneven four-system batch and the M=485 workload")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -240,49 +333,22 @@ def main():
         torch.cuda.synchronize()
         del src_t, dst_t
     wl = si.WORKLOADS[args.workload]
-    # field shapes (n slices, N_Q) from the library's own tables
-    fields = []
-    for i, sd in enumerate(wl["systems"]):
-        probe = F.Context([dict(sd, walkers=1)])
-        inf = probe.info()
-        probe.close()
-        f = si.fields(si.system_seed(args.workload, i), sd["walkers"], inf["n_slices"], inf["n_q"])
-        fields.append(torch.from_numpy(f).cuda())
-    torch.cuda.synchronize()
-    results = {}
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
-    energies = {}
+    results, fields = bench_workload(F, torch, args.workload, precs, args.steps, args.warmup, overlap=args.overlap)
     for p in precs:
         systems = [dict(sd, precision=0 if p == "fp64" else 1, flags=F.FTAFQMC_OVERLAP if args.overlap else 0)
                    for sd in wl["systems"]]
-        ctx, out, en, st = run_precision(F, torch, systems, fields, args.steps, args.warmup)
-        results[p], energies[p] = out, (en, st)
-        del ctx
-        torch.cuda.empty_cache()
         if args.graph:
-            out["graph_replay"] = time_graph(F, torch, systems, fields, args.steps)
+            results[p]["graph_replay"] = time_graph(F, torch, systems, fields, args.steps)
         if p == "mixed" and not args.overlap and not args.no_overlap_schedule:
-            out["overlap_schedule"] = time_overlap(F, torch, systems, fields, args.steps)
-    err = None
-    if "fp64" in energies and "mixed" in energies:
-        errs, nerrs, werrs = [], [], []
-        for ((a, la), sa), ((b, lb), sb) in zip(zip(*energies["fp64"]), zip(*energies["mixed"])):
-            ok = (sa == 0) & (sb == 0)
-            e12a, e12b = a[ok, 0] + a[ok, 1], b[ok, 0] + b[ok, 1]
-            errs.append(np.max(np.abs(e12b - e12a) / np.abs(e12a)))
-            scaled = np.max(np.abs(e12b - e12a) / (np.abs(a[ok, 0]) + np.abs(a[ok, 1])))
-            nerrs.append(np.max(np.abs(b[ok, 3] - a[ok, 3]) / np.abs(a[ok, 3])))
-            werrs.append(np.max(np.abs(lb[ok] - la[ok])))
-        err = float(max(errs))
-        results["mixed"]["max_rel_err_E1E2_vs_fp64"] = err
-        results["mixed"]["max_err_E1E2_over_abs_sum_vs_fp64"] = float(scaled)
-        results["mixed"]["max_rel_err_N_vs_fp64"] = float(max(nerrs))
-        results["mixed"]["max_abs_err_logw_vs_fp64"] = float(max(werrs))
-    use = "mixed" if ("mixed" in results and err is not None and err <= MIXED_E_TOL) else precs[0]
+            results[p]["overlap_schedule"] = time_overlap(F, torch, systems, fields, args.steps)
+    del fields
+    torch.cuda.empty_cache()
+    cmp = results.get("mixed_vs_fp64")
+    use = "mixed" if (cmp is not None and cmp["within_tolerance"]) else precs[0]
     if args.precision == "mixed":
         use = "mixed"
     r = results[use]
-    sd0 = wl["systems"][0]
     prec_key = "f32" if use == "mixed" else "f64"
     achieved = r["gemm_tflops"]
     line = {
@@ -300,13 +366,32 @@ def main():
                      "frac": achieved / PEAK_TFLOPS[prec_key],
                      "traffic": measured_traffic(args.workload, use),
                      "avg_launch_ms": r["gemm_avg_ms"]},
-        "fp64": results.get("fp64"), "mixed": results.get("mixed"),
+        "fp64": results.get("fp64"), "mixed": results.get("mixed"), "mixed_vs_fp64": cmp,
     }
+    if not args.no_extra_workloads:
+        extra = {}
+        for name in ("ueg_uneven4", "ueg_n114_m485"):
+            if name == args.workload:
+                continue
+            res, flds = bench_workload(F, torch, name, ["fp64", "mixed"], 1, 1)
+            del flds
+            torch.cuda.empty_cache()
+            extra[name] = {
+                "walker_slices_per_s": {p: res[p]["walker_slices_per_s"] for p in ("fp64", "mixed")},
+                "ms_per_step": {p: res[p]["ms_per_step"] for p in ("fp64", "mixed")},
+                "gemm_roofline_frac": {p: res[p]["gemm_roofline_frac"] for p in ("fp64", "mixed")},
+                "gemm_avg_ms": {p: res[p]["gemm_avg_ms"] for p in ("fp64", "mixed")},
+                "profile_ms_per_step": {p: res[p]["profile_ms_per_step"] for p in ("fp64", "mixed")},
+                "mixed_vs_fp64": res["mixed_vs_fp64"]}
+            print("workload %s done" % name, file=sys.stderr, flush=True)
+        line["extra_workloads"] = extra
     if not args.no_backward:
         torch.cuda.empty_cache()
         line["backward"] = time_backward(F, torch)
+        print("bench: backward done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload)
+        print("bench: cpu baseline done", file=sys.stderr, flush=True)
     print(json.dumps(line))
 
 

@@ -80,7 +80,8 @@ typedef struct {
   double mu;       /* interacting chemical potential; NaN selects mu_T of the trial */
   double kscale;   /* lambda in H_1 = lambda T + h (1 = the physical Hamiltonian) */
   int precision;   /* FTAFQMC_FP64 or FTAFQMC_MIXED */
-  int flags;       /* 0, or any of FTAFQMC_CHECKPOINT, FTAFQMC_OVERLAP, FTAFQMC_GRAPH */
+  int flags;       /* 0, or any of FTAFQMC_CHECKPOINT, FTAFQMC_OVERLAP, FTAFQMC_GRAPH,
+                      FTAFQMC_TRIAL_THF */
 } ftafqmc_params;
 
 /* flags: record the sampled path (the shifted coefficients c_Q and tr G of every slice) so
@@ -97,6 +98,12 @@ typedef struct {
  * same field buffers (their contents may change between calls).  Results are identical to the
  * eager launches; profiling (ftafqmc_profile) runs eagerly. */
 #define FTAFQMC_GRAPH 4
+/* flags: thermal Hartree-Fock trial (Sec. "Results", fig. thf) instead of the free-electron one:
+ * B_T = diag exp(-dtau (e_K - mu_T)) with the self-consistent levels
+ * e_K = |K|^2/2 - sum_{K' != K} v(K - K') f_K', f_K = 1/(1 + exp(beta (e_K - mu_T))) and
+ * 2 sum f = N (plane waves stay Hartree-Fock orbitals of the uniform gas; the Q = 0 Hartree term
+ * cancels against the background).  mu_T (and the default mu) become this trial's. */
+#define FTAFQMC_TRIAL_THF 8
 /* ftafqmc_backward modes */
 #define FTAFQMC_FROZEN_PATH 0
 
@@ -118,6 +125,20 @@ typedef struct {
   int gemm_tile_epilogue; /* tile shape of the V^4 product, whose epilogue adds V, V^2, V^3 and
                              writes the Taylor blocks */
   int gemm_tile_horner;   /* tile shape of the Horner steps (one addend, one output) */
+  int taylor_degree;      /* degree p of the Taylor polynomial of e^V (a multiple of 4): the
+                             smallest of 16, 20, 24 (FP64) or 12, 16, 20, 24 (mixed) whose
+                             leading remainder term at an a-priori norm estimate of V (from
+                             dtau and the Coulomb kernel) is below 1e-14 (FP64) or 1e-8; every
+                             slice checks the remainder bound sum_{j>p} ||V^4||^{j/4} ||V||^{j%4}/j!
+                             (1-norms) on the device and flags a walker FTAFQMC_WALKER_NUMERIC
+                             when it exceeds 1e-11 (FP64) or 1e-6 (mixed: the rounding level of
+                             its FP32 products) */
+  int refactor_every;     /* the product is re-factorised (Sec. "Numerical Stabilization") at
+                             least every refactor_every slices, in addition to every stab_every
+                             slices: the kinetic part of the product between two passes keeps a
+                             condition number below e^6.  A pass whose pivot spread
+                             min_i d_i / |column i|^2 falls below 1e-5 (orthogonality would be
+                             lost) flags the walker FTAFQMC_WALKER_NUMERIC */
 } ftafqmc_info;
 
 /* Bytes of device workspace needed for the n_sys systems listed in p[0..n_sys-1]
@@ -187,6 +208,39 @@ int ftafqmc_records(ftafqmc_t h, int sys, void* d_trace, double* d_logw, int* h_
 int ftafqmc_backward(ftafqmc_t h, int sys, int mode, const double* d_cot, void* d_jac,
                      double* d_grad, void* d_walker, void* stream);
 
+/* Population control of system `sys` (Sec. "Computational Details": the comb method, and pair
+ * branching for Theta <= 0.25), between ftafqmc_propagate calls.  Weights are
+ * w_i = exp(ln w_i - max ln w) over live walkers (0 for killed and numeric ones).
+ *   FTAFQMC_POP_COMB: with T = sum w and one uniform u = d_u[0], teeth at (k + u) T / W,
+ *     k = 0..W-1; walker i receives the teeth in [c_{i-1}, c_i) with the running sums c from
+ *     walker 0 upwards; every copy carries ln(T / W) + max ln w.
+ *   FTAFQMC_POP_PAIR_BRANCH: the p-th heaviest walker pairs with the p-th lightest (ties to the
+ *     lower index) while the heavy one weighs more than 2 T/W or the light one less than
+ *     T/(2W); with probability w_l / (w_l + w_s) (pair p reads d_u[p]) both slots become the
+ *     heavy walker, otherwise the light one, each with weight (w_l + w_s) / 2.
+ * A walker that keeps a copy keeps its slot; further copies go to the slots of walkers that
+ * keep none, in ascending order, in tooth (pair) order.  Copied state: the stratified product
+ * (Y, D, T), G, <rho_Q>, ln det(I + A), ln det T, ln w and the status word; the per-slice and
+ * record histories stay with the slot.
+ * d_u: device double [W] of uniforms in [0, 1) (comb reads one, pair branching up to W/2);
+ * d_parent: device int [W] or NULL, receives the walker copied into each slot.
+ * Errors: E_ARG for an unknown method or more than 2730 walkers; E_STATE for a system
+ * initialised with FTAFQMC_CHECKPOINT (its recorded path would no longer be the walkers'). */
+#define FTAFQMC_POP_COMB 0
+#define FTAFQMC_POP_PAIR_BRANCH 1
+int ftafqmc_population_control(ftafqmc_t h, int sys, int method, const double* d_u, int* d_parent, void* stream);
+
+/* Weighted statistics of the energy records of system `sys` (estimators are weight-averaged
+ * over the walkers, Sec. "Finite-Temperature AFQMC in the Grand Canonical Ensemble"; the
+ * time-slice average is the "Average" estimator of Sec. "Results", fig. averaging).
+ * d_stats: device double [n_rec][8] (n_rec = info.n_measure), per record over live walkers:
+ *   Re<E>, its standard error sqrt(sum w^2 (Re E - Re<E>)^2) / sum w (delta method for the
+ *   ratio estimator), Re<N>, its standard error, sum w / max w, ln max w, the effective walker
+ *   count (sum w)^2 / sum w^2, the number of live walkers (NaN means for a record without any).
+ * d_average: device double [3] or NULL: the average over the records with live walkers of
+ *   Re<E> and of Re<N>, and the number of such records. */
+int ftafqmc_record_stats(ftafqmc_t h, int sys, double* d_stats, double* d_average, void* stream);
+
 /* Kernel-class timing with HIP events recorded on the caller's stream around every
  * launch (instrumentation).  enable = 1 starts recording every class;
  * enable = FTAFQMC_PROFILE_ONLY | (bit c for each class c) records only those classes (fewer
@@ -202,7 +256,8 @@ enum { FTAFQMC_PROF_GEMM = 0, FTAFQMC_PROF_ELIM = 1, FTAFQMC_PROF_GREENS = 2, FT
 #define FTAFQMC_PROFILE_ONLY 256
 int ftafqmc_profile(ftafqmc_t h, int enable, double* h_ms, long long* h_count);
 
-/* Message of the last error on this handle ("" if none); valid until the next call. */
+/* Message of the last error on this handle ("" if none); valid until the next call.  With
+ * h = NULL: the message of the last failed ftafqmc_init_ueg call on this thread. */
 const char* ftafqmc_last_error(ftafqmc_t h);
 
 /* Release the handle (host memory only; the caller frees the workspace). */

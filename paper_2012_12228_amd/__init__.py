@@ -22,13 +22,15 @@ WALKER_ALIVE, WALKER_KILLED, WALKER_NUMERIC = 0, 1, 2
 FTAFQMC_CHECKPOINT = 1     # params flag: record the path for ftafqmc_backward
 FTAFQMC_OVERLAP = 2        # params flag: two walker groups on two streams
 FTAFQMC_GRAPH = 4          # params flag: replay whole-path propagation from a captured HIP graph
+FTAFQMC_TRIAL_THF = 8      # params flag: thermal Hartree-Fock trial instead of the free-electron one
 FTAFQMC_PROFILE_ONLY = 256  # ftafqmc_profile: record only the classes in the low bits
 FROZEN_PATH = 0            # ftafqmc_backward mode
+POP_COMB, POP_PAIR_BRANCH = 0, 1   # ftafqmc_population_control methods
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NUMERIC", -4: "E_STATE", -5: "E_UNSUPPORTED"}
 
-ABI_SYMBOLS = ["ftafqmc_workspace_bytes", "ftafqmc_init_ueg", "ftafqmc_query", "ftafqmc_reset",
-               "ftafqmc_propagate", "ftafqmc_greens", "ftafqmc_energy", "ftafqmc_records",
-               "ftafqmc_backward", "ftafqmc_profile", "ftafqmc_last_error", "ftafqmc_destroy"]
+ABI_SYMBOLS = ["ftafqmc_workspace_bytes", "ftafqmc_init_ueg", "ftafqmc_query", "ftafqmc_reset", "ftafqmc_propagate", "ftafqmc_greens", "ftafqmc_energy", "ftafqmc_records",
+               "ftafqmc_backward", "ftafqmc_population_control", "ftafqmc_record_stats", "ftafqmc_profile",
+               "ftafqmc_last_error", "ftafqmc_destroy"]
 PROF_CLASSES = ["gemm", "elim", "greens_transpose", "weight_forcebias", "coef_gather", "stabilise", "energy",
                 "backward"]
 
@@ -48,7 +50,8 @@ class Info(ctypes.Structure):
                 ("mu", ctypes.c_double), ("e_madelung", ctypes.c_double),
                 ("gemm_tile_chain", ctypes.c_int), ("gemm_tile_apply", ctypes.c_int),
                 ("gemm_tile_shapes", ctypes.c_int), ("walker_groups", ctypes.c_int),
-                ("gemm_tile_epilogue", ctypes.c_int), ("gemm_tile_horner", ctypes.c_int)]
+                ("gemm_tile_epilogue", ctypes.c_int), ("gemm_tile_horner", ctypes.c_int),
+                ("taylor_degree", ctypes.c_int), ("refactor_every", ctypes.c_int)]
 
 
 _lib_handle = None
@@ -72,6 +75,8 @@ def load_library():
     lib.ftafqmc_energy.argtypes = [vp, ip, vp, vp, vp, vp, vp]
     lib.ftafqmc_records.argtypes = [vp, ip, vp, vp, ctypes.POINTER(ctypes.c_int), vp]
     lib.ftafqmc_backward.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp]
+    lib.ftafqmc_population_control.argtypes = [vp, ip, ip, vp, vp, vp]
+    lib.ftafqmc_record_stats.argtypes = [vp, ip, vp, vp, vp]
     lib.ftafqmc_profile.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
     lib.ftafqmc_last_error.argtypes = [vp]
     lib.ftafqmc_last_error.restype = ctypes.c_char_p
@@ -99,12 +104,18 @@ def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+class FtafqmcError(RuntimeError):
+    """A C ABI call returned a non-zero ftafqmc_status (in .code)."""
+
+    def __init__(self, code, msg):
+        super().__init__("ftafqmc call failed: %s %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
 def _check(rc, handle=None):
     if rc != 0:
-        msg = ""
-        if handle:
-            msg = load_library().ftafqmc_last_error(handle).decode()
-        raise RuntimeError("ftafqmc call failed: %s %s" % (STATUS.get(rc, rc), msg))
+        # handle None: the message of the last failed initialisation on this thread
+        raise FtafqmcError(rc, load_library().ftafqmc_last_error(handle).decode())
 
 
 # ------------------------------------------------------------ C ABI names ---
@@ -142,8 +153,16 @@ def ftafqmc_propagate(handle, fields, n_slices, device):
 
 
 def ftafqmc_greens(handle, sys, out, device):
-    code = FTAFQMC_C128 if out.dtype == torch.complex128 else FTAFQMC_C64
-    _check(load_library().ftafqmc_greens(handle, sys, _ptr(out), code, _stream(device)), handle)
+    """out: contiguous complex128 or complex64 CUDA tensor of shape [W][M][M] of system `sys`."""
+    codes = {torch.complex128: FTAFQMC_C128, torch.complex64: FTAFQMC_C64}
+    if out.dtype not in codes:
+        raise ValueError("ftafqmc_greens: out must be complex128 or complex64, not %s" % out.dtype)
+    if out.device.type != "cuda" or not out.is_contiguous():
+        raise ValueError("ftafqmc_greens: out must be a contiguous CUDA tensor")
+    inf = ftafqmc_query(handle, sys)
+    if tuple(out.shape) != (inf["n_walkers"], inf["M"], inf["M"]):
+        raise ValueError("ftafqmc_greens: out must have shape %s" % ((inf["n_walkers"], inf["M"], inf["M"]),))
+    _check(load_library().ftafqmc_greens(handle, sys, _ptr(out), codes[out.dtype], _stream(device)), handle)
     return out
 
 
@@ -161,6 +180,15 @@ def ftafqmc_records(handle, sys, trace, logw, n_rec, device):
 def ftafqmc_backward(handle, sys, mode, cot, jac, grad, walker, device):
     _check(load_library().ftafqmc_backward(handle, sys, mode, _ptr(cot), _ptr(jac), _ptr(grad), _ptr(walker),
                                            _stream(device)), handle)
+
+
+def ftafqmc_population_control(handle, sys, method, uniforms, parent, device):
+    _check(load_library().ftafqmc_population_control(handle, sys, method, _ptr(uniforms), _ptr(parent),
+                                                     _stream(device)), handle)
+
+
+def ftafqmc_record_stats(handle, sys, stats, average, device):
+    _check(load_library().ftafqmc_record_stats(handle, sys, _ptr(stats), _ptr(average), _stream(device)), handle)
 
 
 def ftafqmc_profile(handle, enable, classes=None):
@@ -195,6 +223,7 @@ class Context:
             systems = [systems]
         self.systems = [dict(s) for s in systems]
         self.device = torch.device(device)
+        self.handle = None
         load_library()
         nbytes = ftafqmc_workspace_bytes(self.systems)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -259,6 +288,25 @@ class Context:
             grad = torch.empty(2, dtype=torch.float64, device=self.device)
         ftafqmc_backward(self.handle, sys, FROZEN_PATH, cot, jac, grad, walker, self.device)
         return dict(jac=jac, walker=walker, grad=grad)
+
+    def population_control(self, method, uniforms, sys=0):
+        """Comb (POP_COMB) or pair branching (POP_PAIR_BRANCH) with the given uniforms (a float64
+        CUDA tensor of at least n_walkers values in [0, 1)); returns the parent of every slot."""
+        W = self.infos[sys]["n_walkers"]
+        u = torch.as_tensor(uniforms, dtype=torch.float64, device=self.device).contiguous()
+        if u.numel() < W:
+            raise ValueError("population control needs %d uniforms" % W)
+        parent = torch.empty(W, dtype=torch.int32, device=self.device)
+        ftafqmc_population_control(self.handle, sys, method, u, parent, self.device)
+        return parent
+
+    def record_stats(self, sys=0):
+        """Per-record weighted statistics [n_rec][8] and their time-slice averages [3]."""
+        n = self.info(sys)["n_measure"]
+        stats = torch.empty((max(n, 1), 8), dtype=torch.float64, device=self.device)
+        avg = torch.empty(3, dtype=torch.float64, device=self.device)
+        ftafqmc_record_stats(self.handle, sys, stats, avg, self.device)
+        return stats[:n], avg
 
     def profile(self, enable, classes=None):
         return ftafqmc_profile(self.handle, enable, classes)

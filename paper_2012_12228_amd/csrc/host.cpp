@@ -13,14 +13,32 @@
 #include <vector>
 
 #include "../../include/ftafqmc.h"
+#include "internal.h"
 #include "kernels.h"
 
 namespace {
+
+thread_local std::string init_err;       // message of the last failed initialisation on this thread
 
 constexpr double PI = 3.14159265358979323846;
 constexpr double MADELUNG = 2.837297;  // Sec. "Uniform Electron Gas"
 constexpr int MAX_M = 512;             // the elimination keeps a panel row per thread, two per thread at most
 constexpr int MAX_NQ = 8192;           // the shifted coefficients of one walker are staged in LDS
+// Taylor polynomial of e^V: the smallest degree (a multiple of 4, at least 16 in FP64 and 12 in
+// mixed precision, at most 24) whose leading remainder term nu^{p+1}/(p+1)! at the a-priori norm
+// estimate nu is below TAYLOR_APRIORI_TOL; every slice then checks the rigorous 1-norm bound
+// of the remainder on the device against TAYLOR_CHECK_TOL and flags the walker otherwise.
+constexpr int TAYLOR_MAX_NB = 6;
+constexpr double TAYLOR_APRIORI_TOL[2] = {1e-14, 1e-8};   // FP64, mixed
+// The check tolerance sits at the level of each precision's own product rounding: the 1-norm
+// bound is measured 50-400x above the true truncation error on the workloads (M=485: bound
+// 2e-9 at degree 12, 3e-14 at degree 16), and the FP32 products of the mixed chain round at
+// about 1e-7 relative.
+constexpr double TAYLOR_CHECK_TOL[2] = {1e-11, 1e-6};
+constexpr double TAYLOR_NU_MARGIN = 1.7;                  // measured: ||V^4||_1^{1/4} <= 1.7 x estimate
+// Re-factorisation interval: the kinetic part of the product between two Cholesky-QR passes has
+// condition number at most e^{STAB_KIN_RANGE} (dtau (max - min of lambda eps + h) per slice).
+constexpr double STAB_KIN_RANGE = 6.0;
 
 typedef std::array<int, 3> iv3;
 
@@ -40,6 +58,7 @@ struct HostSys {
   std::vector<int> idx, neg, qptr, qpair, flat, rbptr, rbidx;
   int rq_rows = 0, rq_nblk = 0;
   std::vector<double> vq, sq, eps, hK, kh, lnbt;
+  std::vector<double> tlev;             // trial levels: eps (free electron) or thermal Hartree-Fock
   std::vector<short> grid;
   size_t off_begin = 0, bytes = 0;
   SysDev dev;
@@ -53,6 +72,8 @@ struct HostSys {
   double2* Ynew0 = nullptr;
   int M2 = 0, ld2 = 0;                  // doubled system of the derivative
   TanDev tan;
+  int taylor_nb = 4;                    // Paterson-Stockmeyer blocks of 4: degree 4 taylor_nb
+  int stab_cap = 1;                     // re-factorise at least every stab_cap slices
 };
 
 // Logistic 1/(1+e^x) without overflow.
@@ -67,7 +88,7 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
   if (p.n_walkers < 1) return "n_walkers must be >= 1";
   if (p.precision != FTAFQMC_FP64 && p.precision != FTAFQMC_MIXED) return "unknown precision";
   if (!std::isfinite(p.kscale)) return "kscale must be finite";
-  if (p.flags & ~(FTAFQMC_CHECKPOINT | FTAFQMC_OVERLAP | FTAFQMC_GRAPH)) return "unknown flags";
+  if (p.flags & ~(FTAFQMC_CHECKPOINT | FTAFQMC_OVERLAP | FTAFQMC_GRAPH | FTAFQMC_TRIAL_THF)) return "unknown flags";
   s.groups = (p.flags & FTAFQMC_OVERLAP) ? 2 : 1;
   s.ckpt = (p.flags & FTAFQMC_CHECKPOINT) != 0;
   if (s.ckpt && p.precision != FTAFQMC_FP64) return "the path record for derivatives needs FP64 propagation";
@@ -129,17 +150,47 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
       if (j != i) a += s.vq[s.idx[(size_t)i * s.M + j]];
     s.hK[i] = -0.5 * a;
   }
-  // trial chemical potential: 2 sum_K f(eps_K - mu_T) = N by bisection
-  {
-    auto count = [&](double mu) { double c = 0; for (int i = 0; i < s.M; ++i) c += 2.0 * fermi(s.beta * (s.eps[i] - mu)); return c; };
-    double lo = s.eps[0] - 60.0 / s.beta, hi = s.eps[s.M - 1] + 60.0 / s.beta;
-    if (!(count(lo) < p.n_elec && p.n_elec < count(hi))) return "electron number not reachable in this basis";
+  // trial levels e_K and chemical potential: 2 sum_K f(e_K - mu_T) = N by bisection, with
+  // e_K = eps_K (free-electron trial) or the self-consistent thermal Hartree-Fock levels
+  // e_K = eps_K - sum_{K' != K} v(K - K') f_K' (Sec. "Results", fig. thf; the uniform gas keeps
+  // plane waves as Hartree-Fock orbitals, and the Q = 0 Hartree term goes with the background),
+  // iterated to a fixed point with mixing 1/2
+  s.tlev.assign(s.eps.begin(), s.eps.begin() + s.M);
+  auto chem_pot = [&](const std::vector<double>& e, double* mu_out) -> bool {
+    auto count = [&](double mu) { double c = 0; for (int i = 0; i < s.M; ++i) c += 2.0 * fermi(s.beta * (e[i] - mu)); return c; };
+    const double emin = *std::min_element(e.begin(), e.end()), emax = *std::max_element(e.begin(), e.end());
+    double lo = emin - 60.0 / s.beta, hi = emax + 60.0 / s.beta;
+    if (!(count(lo) < p.n_elec && p.n_elec < count(hi))) return false;
     for (int it = 0; it < 400; ++it) {
       const double mid = 0.5 * (lo + hi);
       if (count(mid) < p.n_elec) lo = mid; else hi = mid;
       if (hi - lo <= 4e-16 * std::max(1.0, std::fabs(mid))) break;
     }
-    s.muT = 0.5 * (lo + hi);
+    *mu_out = 0.5 * (lo + hi);
+    return true;
+  };
+  if (!chem_pot(s.tlev, &s.muT)) return "electron number not reachable in this basis";
+  if (p.flags & FTAFQMC_TRIAL_THF) {
+    std::vector<double> enew(s.M), f(s.M);
+    bool conv = false;
+    for (int it = 0; it < 10000 && !conv; ++it) {
+      double mu = 0.0;
+      if (!chem_pot(s.tlev, &mu)) return "electron number not reachable in this basis";
+      for (int i = 0; i < s.M; ++i) f[i] = fermi(s.beta * (s.tlev[i] - mu));
+      double diff = 0.0, emax = 1.0;
+      for (int i = 0; i < s.M; ++i) {
+        double x = 0.0;
+        for (int j = 0; j < s.M; ++j)
+          if (j != i) x += s.vq[s.idx[(size_t)i * s.M + j]] * f[j];
+        enew[i] = s.eps[i] - x;
+        diff = std::max(diff, std::fabs(enew[i] - s.tlev[i]));
+        emax = std::max(emax, std::fabs(s.tlev[i]));
+      }
+      if (diff <= 1e-14 * emax) { s.tlev = enew; conv = true; }
+      else for (int i = 0; i < s.M; ++i) s.tlev[i] = 0.5 * (s.tlev[i] + enew[i]);
+    }
+    if (!conv) return "thermal Hartree-Fock trial did not converge";
+    if (!chem_pot(s.tlev, &s.muT)) return "electron number not reachable in this basis";
   }
   s.mu = std::isnan(p.mu) ? s.muT : p.mu;
   s.EM = -MADELUNG * p.n_elec / (2.0 * s.L);
@@ -147,7 +198,7 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
   s.lnbt.assign(s.ld, 0.0);
   for (int i = 0; i < s.M; ++i) {
     s.kh[i] = std::exp(-0.5 * s.dtau * (p.kscale * s.eps[i] + s.hK[i] - s.mu));
-    s.lnbt[i] = -s.dtau * (s.eps[i] - s.muT);
+    s.lnbt[i] = -s.dtau * (s.tlev[i] - s.muT);
   }
   // pairs of each Q as flat indices of G_{r p} (K_p - K_r = Q)
   s.qptr.assign(s.NQ + 1, 0);
@@ -197,6 +248,38 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
     s.grid[(size_t)(s.flat[i] + s.gc0)] = (short)i;
   }
   s.nrec_max = s.n / p.stab_every + 2;
+  // A-priori size of V = sqrt(dtau) (x - xbar).v: an entry V_ij = i s_Q (z_Q + conj z_-Q) has
+  // E|V_ij|^2 = 4 s_Q^2 for unit Gaussian fields, and the norm of such a random matrix is about
+  // twice the root of its largest column variance.
+  {
+    double colmax = 0.0;
+    for (int j = 0; j < s.M; ++j) {
+      double a = 0.0;
+      for (int i = 0; i < s.M; ++i)
+        if (i != j) { const double sv = s.sq[s.idx[(size_t)i * s.M + j]]; a += sv * sv; }
+      colmax = std::max(colmax, a);
+    }
+    const double nu = TAYLOR_NU_MARGIN * 4.0 * std::sqrt(colmax);
+    const int mixed = p.precision == FTAFQMC_MIXED;
+    int nb = mixed ? 3 : 4;
+    for (; nb < TAYLOR_MAX_NB; ++nb) {
+      const int q = 4 * nb + 1;
+      double lt = q * std::log(nu);
+      for (int j = 2; j <= q; ++j) lt -= std::log((double)j);
+      if (std::exp(lt) <= TAYLOR_APRIORI_TOL[mixed]) break;
+    }
+    s.taylor_nb = nb;
+  }
+  {
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < s.M; ++i) {
+      const double e = p.kscale * s.eps[i] + s.hK[i];
+      lo = std::min(lo, e);
+      hi = std::max(hi, e);
+    }
+    const double per_slice = s.dtau * (hi - lo);
+    s.stab_cap = per_slice > 0.0 ? std::max(1, (int)std::floor(STAB_KIN_RANGE / per_slice)) : s.n;
+  }
   return "";
 }
 
@@ -230,7 +313,7 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.V2 = take(velem * mat * W);
   d.V3 = take(velem * mat * W);
   d.V4 = take(velem * mat * W);
-  for (int k = 0; k < 3; ++k) d.Bk[k] = take(velem * mat * W);
+  for (int k = 0; k < 5; ++k) d.Bk[k] = k < std::max(3, s.taylor_nb - 1) ? take(velem * mat * W) : nullptr;
   d.E0 = take(sizeof(double2) * mat * W);
   d.E1 = take(sizeof(double2) * mat * W);
   d.D = (double*)take(sizeof(double) * ld * W);
@@ -254,6 +337,9 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.rec_logw = (double*)take(sizeof(double) * (size_t)W * s.nrec_max);
   d.rec_status = (int*)take(sizeof(int) * (size_t)W * s.nrec_max);
   d.scratch = (double*)take(sizeof(double) * (size_t)ld * W);
+  d.tnorm = (double*)take(sizeof(double) * 16 * (size_t)W);
+  d.pop_parent = (int*)take(sizeof(int) * (size_t)W);
+  d.pop_logw = (double*)take(sizeof(double) * (size_t)W);
   s.mean = (double2*)take(sizeof(double2) * 4);
   d.rec_c = nullptr;
   d.rec_trG = nullptr;
@@ -280,6 +366,8 @@ size_t layout(HostSys& s, char* base, size_t off) {
     t.lndet_dummy = (double2*)take(sizeof(double2) * W);
     t.dd.status = t.tstat;
     t.dd.lndetT = t.lndet_dummy;
+    t.dd.logw = nullptr;                          // the doubled factorisation flags tstat only
+    t.dd.tnorm = nullptr;
     t.dd.mat_stride = (long long)mat2;
     t.dd.aug_stride = (long long)2 * mat2;
     t.Ydn = (double2*)take(sizeof(double2) * mat2 * W);
@@ -299,6 +387,8 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.M = M; d.ld = ld; d.NQ = NQ; d.W = W; d.n = s.n; d.grid_dim = s.gdim; d.grid_c0 = s.gc0;
   d.rq_rows = s.rq_rows; d.rq_nblk = s.rq_nblk;
   d.dtau = s.dtau; d.kscale = s.p.kscale; d.e_madelung = s.EM;
+  d.taylor_deg = 4 * s.taylor_nb;
+  d.taylor_tol = TAYLOR_CHECK_TOL[s.p.precision == FTAFQMC_MIXED ? 1 : 0];
   d.mat_stride = (long long)mat;
   d.aug_stride = (long long)2 * mat;
   d.w_off = 0; d.rec_W = W;
@@ -328,7 +418,7 @@ SysDev walker_view(const HostSys& s, int w0, int nw) {
   auto offv = [&](void* q, size_t bytes) { return q ? (void*)((char*)q + (size_t)w * bytes) : nullptr; };
   v.V = offv(v.V, velem * mat); v.V2 = offv(v.V2, velem * mat);
   v.V3 = offv(v.V3, velem * mat); v.V4 = offv(v.V4, velem * mat);
-  for (int k = 0; k < 3; ++k) v.Bk[k] = offv(v.Bk[k], velem * mat);
+  for (int k = 0; k < 5; ++k) v.Bk[k] = offv(v.Bk[k], velem * mat);
   v.E0 = offv(v.E0, sizeof(double2) * mat); v.E1 = offv(v.E1, sizeof(double2) * mat);
   v.D += w * ld; v.Dpi += w * ld; v.perm += w * ld; v.piv += w * ld;
   v.tri += w * (long long)elim_tri_elems(s.M);
@@ -337,6 +427,7 @@ SysDev walker_view(const HostSys& s, int w0, int nw) {
   v.expo += w; v.ell += w; v.lndetT += w; v.lndetX += w; v.logw += w; v.status += w;
   v.slice_lnS += w * s.n; v.slice_theta += w * s.n;
   v.exch += w * ld; v.local += w * 4; v.scratch += w * ld;
+  if (v.tnorm) v.tnorm += w * 16;
   if (v.rec_c) v.rec_c += w * s.n * (long long)s.NQ;
   if (v.rec_trG) v.rec_trG += w * (s.n + 1);
   v.W = nw; v.w_off = w0; v.rec_W = s.p.n_walkers;
@@ -411,14 +502,16 @@ GemmParams gp_base(const HostSys& s, const SysDev& d) {
 double inv_fact(int j) { double f = 1.0; for (int i = 2; i <= j; ++i) f *= i; return 1.0 / f; }
 
 // Y <- K e^V K Y with e^V = sum_{j<=deg} V^j / j! by Paterson-Stockmeyer with blocks of 4:
-// B_k = sum_{r<4} a_{4k+r} V^r and e^V = (((a_deg V^4 + B_top) V^4 + ...) V^4 + B_0).
-// FP64: degree 16 (nb = 4 blocks); mixed: degree 12 (nb = 3).  The V^4 product also writes
-// the top Horner term and the lower blocks, so every Horner step reads one matrix.
+// B_k = sum_{r<4} a_{4k+r} V^r and e^V = (((a_deg V^4 + B_top) V^4 + ...) V^4 + B_0), with
+// deg = 4 nb chosen per system (16 in FP64 and 12 in mixed precision on the workloads).  The
+// V^4 product also writes the top Horner term and up to three lower blocks, so every Horner
+// step reads one matrix; blocks below those (nb > 4) come from an elementwise pass.  With
+// `check`, the column norms of V and V^4 are taken for the device-side truncation bound.
 // Forms B = K e^V K from d.V; *B_out points at the buffer that holds it (E0 or E1).
-int form_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st, void** B_out) {
+int form_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st, void** B_out, bool check) {
   const bool mixed = s.p.precision == FTAFQMC_MIXED;
   const int prec = mixed ? GEMM_C32 : GEMM_Z64;
-  const int nb = mixed ? 3 : 4;
+  const int nb = s.taylor_nb;
   const int deg = 4 * nb;
   GemmParams g = gp_base(s, d);
   g.tile = s.tile_chain;
@@ -429,14 +522,22 @@ int form_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st, void*
   g.A = d.V2; g.B = d.V2; g.C = d.V4;                                                  // V^4 and the blocks
   g.tile = s.tile_epi;
   g.P1 = d.V; g.P2 = d.V2; g.P3 = d.V3;
-  g.nextra = nb;
-  {
-    const int top = 4 * (nb - 1);
-    g.extra[0] = GemmOut{d.E0, inv_fact(deg), inv_fact(top), inv_fact(top + 1), inv_fact(top + 2), inv_fact(top + 3)};
-    for (int k = nb - 2, e = 1; k >= 0; --k, ++e)
-      g.extra[e] = GemmOut{d.Bk[k], 0.0, inv_fact(4 * k), inv_fact(4 * k + 1), inv_fact(4 * k + 2), inv_fact(4 * k + 3)};
-  }
+  const int top = 4 * (nb - 1);
+  g.extra[0] = GemmOut{d.E0, inv_fact(deg), inv_fact(top), inv_fact(top + 1), inv_fact(top + 2), inv_fact(top + 3)};
+  int ne = 1;
+  for (int k = nb - 2; k >= 0 && ne < 4; --k, ++ne)
+    g.extra[ne] = GemmOut{d.Bk[k], 0.0, inv_fact(4 * k), inv_fact(4 * k + 1), inv_fact(4 * k + 2), inv_fact(4 * k + 3)};
+  g.nextra = ne;
   HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));
+  const int nlo = nb - ne;                      // blocks B_0 .. B_{nlo-1} not written by the epilogue
+  if (nlo > 0) {
+    TaylorLow t;
+    t.nlo = nlo;
+    for (int k = 0; k < nlo; ++k)
+      for (int r = 0; r < 4; ++r) t.c[k][r] = inv_fact(4 * k + r);
+    HIPCHK(timed(h, FTAFQMC_PROF_COEF, st, [&] { return launch_taylor_blocks(d, mixed, t, st); }));
+  }
+  if (check) HIPCHK(timed(h, FTAFQMC_PROF_COEF, st, [&] { return launch_taylor_norms(d, mixed, st); }));
   void* cur = d.E0;
   void* nxt = d.E1;
   for (int k = nb - 2; k >= 0; --k) {
@@ -455,7 +556,7 @@ int form_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st, void*
 int apply_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st) {
   const bool mixed = s.p.precision == FTAFQMC_MIXED;
   void* cur = nullptr;
-  int rc = form_propagator(h, s, d, st, &cur);
+  int rc = form_propagator(h, s, d, st, &cur, true);
   if (rc) return rc;
   GemmParams a = gp_base(s, d);
   a.tile = s.tile_apply;
@@ -543,10 +644,11 @@ int autotune_gemm(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
       else if (kind == 3) { g.A = d.V2; g.B = d.V4; g.C = d.V3; g.P1 = d.V; g.c1 = 1.0; }
       else {
         g.A = d.V2; g.B = d.V2; g.C = d.V4; g.P1 = d.V; g.P2 = d.V2; g.P3 = d.V3; g.c1 = 1.0;
-        const int nb = mixed ? 3 : 4;
-        g.nextra = nb;
+        const int nb = s.taylor_nb;
         g.extra[0] = GemmOut{d.E0, 1.0, 1.0, 1.0, 1.0, 1.0};
-        for (int k = nb - 2, e = 1; k >= 0; --k, ++e) g.extra[e] = GemmOut{d.Bk[k], 0.0, 1.0, 1.0, 1.0, 1.0};
+        int e = 1;
+        for (int k = nb - 2; k >= 0 && e < 4; --k, ++e) g.extra[e] = GemmOut{d.Bk[k], 0.0, 1.0, 1.0, 1.0, 1.0};
+        g.nextra = e;
       }
       if (!gemm_tile_supported(t, prec) || (grouped && gemm_tile_walker_sized(t))) continue;
       hipError_t e = launch_zgemm(g, prec, st);                 // warm-up
@@ -587,12 +689,14 @@ int reset_sys(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
 }
 
 // One slice k -> k+1 for the walkers of view d (fields of those walkers), on stream st.
-int slice_step(ftafqmc_ctx* h, HostSys& s, SysDev& d, const double2* fields, int k, int rec, hipStream_t st) {
+// rec >= 0: energy record number rec after the slice; refac: re-factorise the product.
+int slice_step(ftafqmc_ctx* h, HostSys& s, SysDev& d, const double2* fields, int k, int rec, bool refac,
+               hipStream_t st) {
   const int mixed = s.p.precision == FTAFQMC_MIXED;
   HIPCHK(timed(h, FTAFQMC_PROF_COEF, st, [&] { return launch_coef_v(d, fields, k, mixed, st); }));
   int rc = apply_propagator(h, s, d, st);
   if (rc) return rc;
-  if (rec >= 0) { rc = stabilise(h, s, d, st); if (rc) return rc; }
+  if (refac) { rc = stabilise(h, s, d, st); if (rc) return rc; }
   rc = greens(h, s, d, k + 1, 0, st);
   if (rc) return rc;
   if (rec >= 0) HIPCHK(timed(h, FTAFQMC_PROF_ENERGY, st, [&] { return launch_energy(d, rec, st); }));
@@ -607,10 +711,13 @@ int step(ftafqmc_ctx* h, HostSys& s, std::vector<SysDev>& views, const double2* 
   const int k = s.k;
   const bool boundary = ((k + 1) % s.p.stab_every == 0) || (k + 1 == s.n);
   const int rec = boundary ? s.nrec : -1;
+  // records at the caller's stabilisation interval; extra re-factorisations where the kinetic
+  // range of the product would make one Cholesky-QR pass lose orthogonality
+  const bool refac = boundary || ((k + 1) % s.stab_cap == 0);
   for (size_t g = 0; g < views.size(); ++g) {
     SysDev& d = views[g];
     const double2* f = fields + (long long)d.w_off * s.n * s.NQ;
-    int rc = slice_step(h, s, d, f, k, rec, g == 0 ? st : h->side[g - 1]);
+    int rc = slice_step(h, s, d, f, k, rec, refac, g == 0 ? st : h->side[g - 1]);
     if (rc) return rc;
   }
   std::swap(s.dev.Y, s.dev.Ynew);           // every view swapped its own pointers once
@@ -711,7 +818,7 @@ int backward(ftafqmc_ctx* h, HostSys& s, const double* cot, double2* jac, double
   for (int k = 0; k < s.n; ++k) {
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_coef_replay(d, k, st); }));
     void* B = nullptr;
-    int rc = form_propagator(h, s, d, st, &B);
+    int rc = form_propagator(h, s, d, st, &B, false);
     if (rc) return rc;
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_tan_prep(d, t, (const double2*)B, st); }));
     rc = doubled_greens(h, s, k, 0, st);
@@ -797,18 +904,18 @@ int ftafqmc_workspace_bytes(const ftafqmc_params* p, int n_sys, size_t* bytes) {
 
 int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size_t ws_bytes, void* stream,
                      ftafqmc_t* out) {
-  if (!p || n_sys < 1 || !out || !d_workspace) return FTAFQMC_E_ARG;
-  if (((uintptr_t)d_workspace) & 255) return FTAFQMC_E_ARG;
+  if (!p || n_sys < 1 || !out || !d_workspace) return lib_init_error(FTAFQMC_E_ARG, "null parameters, output or workspace");
+  if (((uintptr_t)d_workspace) & 255) return lib_init_error(FTAFQMC_E_ARG, "workspace not 256-byte aligned");
   ftafqmc_ctx* h = new (std::nothrow) ftafqmc_ctx();
-  if (!h) return FTAFQMC_E_ARG;
+  if (!h) return lib_init_error(FTAFQMC_E_ARG, "out of host memory");
   h->sys.resize(n_sys);
   size_t off = 0;
   for (int i = 0; i < n_sys; ++i) {
     std::string m = build_tables(h->sys[i], p[i]);
-    if (!m.empty()) { delete h; return FTAFQMC_E_ARG; }
+    if (!m.empty()) { delete h; return lib_init_error(FTAFQMC_E_ARG, m.c_str()); }
     off = layout(h->sys[i], nullptr, off);
   }
-  if (off > ws_bytes) { delete h; return FTAFQMC_E_ARG; }
+  if (off > ws_bytes) { delete h; return lib_init_error(FTAFQMC_E_ARG, "workspace smaller than ftafqmc_workspace_bytes"); }
   h->groups = 1;
   for (auto& s : h->sys) {
     if (s.p.flags & FTAFQMC_GRAPH) h->graph = true;
@@ -820,7 +927,7 @@ int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size
   for (int g = 0; ok && g + 1 < h->groups; ++g)
     ok = hipStreamCreateWithFlags(&h->side[g], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&h->join[g], hipEventDisableTiming) == hipSuccess;
-  if (!ok) { ftafqmc_destroy(h); return FTAFQMC_E_HIP; }
+  if (!ok) { ftafqmc_destroy(h); return lib_init_error(FTAFQMC_E_HIP, "event or stream creation failed"); }
   h->ws = (char*)d_workspace;
   h->ws_bytes = ws_bytes;
   hipStream_t st = (hipStream_t)stream;
@@ -848,10 +955,11 @@ int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size
     if (e == hipSuccess) e = up(d.flat, s.flat.data(), sizeof(int) * s.M);
     // the host tables are no longer needed once the copies have completed
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) { ftafqmc_destroy(h); return FTAFQMC_E_HIP; }
-    if (autotune_gemm(h, s, st) != FTAFQMC_OK) { ftafqmc_destroy(h); return FTAFQMC_E_HIP; }
-    if (reset_sys(h, s, st) != FTAFQMC_OK) { ftafqmc_destroy(h); return FTAFQMC_E_HIP; }
+    if (e != hipSuccess) { ftafqmc_destroy(h); return lib_init_error(FTAFQMC_E_HIP, "table upload failed"); }
+    if (autotune_gemm(h, s, st) != FTAFQMC_OK) { ftafqmc_destroy(h); return lib_init_error(FTAFQMC_E_HIP, "GEMM autotuning failed"); }
+    if (reset_sys(h, s, st) != FTAFQMC_OK) { ftafqmc_destroy(h); return lib_init_error(FTAFQMC_E_HIP, "walker initialisation failed"); }
   }
+  init_err.clear();
   *out = h;
   return FTAFQMC_OK;
 }
@@ -867,6 +975,8 @@ int ftafqmc_query(ftafqmc_t h, int sys, ftafqmc_info* out) {
   out->mu_T = s.muT; out->mu = s.mu; out->e_madelung = s.EM;
   out->gemm_tile_chain = s.tile_chain; out->gemm_tile_apply = s.tile_apply; out->gemm_tile_epilogue = s.tile_epi;
   out->gemm_tile_horner = s.tile_horner;
+  out->taylor_degree = 4 * s.taylor_nb;
+  out->refactor_every = s.stab_cap;
   out->gemm_tile_shapes = gemm_tile_count();
   out->walker_groups = (int)make_views(s, s.groups).size();
   return FTAFQMC_OK;
@@ -968,6 +1078,29 @@ int ftafqmc_backward(ftafqmc_t h, int sys, int mode, const double* d_cot, void* 
   return backward(h, s, d_cot, (double2*)d_jac, d_grad, (double2*)d_walker, (hipStream_t)stream);
 }
 
+int ftafqmc_population_control(ftafqmc_t h, int sys, int method, const double* d_u, int* d_parent, void* stream) {
+  int rc = check_handle(h, sys);
+  if (rc) return rc;
+  if (method != FTAFQMC_POP_COMB && method != FTAFQMC_POP_PAIR_BRANCH) return h->set(FTAFQMC_E_ARG, "unknown population control method");
+  if (!d_u) return h->set(FTAFQMC_E_ARG, "null uniforms");
+  HostSys& s = h->sys[sys];
+  if (s.ckpt) return h->set(FTAFQMC_E_STATE, "population control would break the recorded path of FTAFQMC_CHECKPOINT");
+  if (pop_select_lds(s.p.n_walkers) > 64 * 1024) return h->set(FTAFQMC_E_ARG, "too many walkers for population control");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_population_control(s.dev, method, d_u, s.dev.pop_parent, s.dev.pop_logw, st));
+  if (d_parent) HIPCHK(hipMemcpyAsync(d_parent, s.dev.pop_parent, sizeof(int) * s.p.n_walkers, hipMemcpyDeviceToDevice, st));
+  return FTAFQMC_OK;
+}
+
+int ftafqmc_record_stats(ftafqmc_t h, int sys, double* d_stats, double* d_average, void* stream) {
+  int rc = check_handle(h, sys);
+  if (rc) return rc;
+  if (!d_stats) return h->set(FTAFQMC_E_ARG, "null stats");
+  HostSys& s = h->sys[sys];
+  HIPCHK(launch_record_stats(s.dev, s.nrec, d_stats, d_average, (hipStream_t)stream));
+  return FTAFQMC_OK;
+}
+
 int ftafqmc_profile(ftafqmc_t h, int enable, double* h_ms, long long* h_count) {
   if (!h) return FTAFQMC_E_ARG;
   if (enable) {
@@ -1000,7 +1133,7 @@ int ftafqmc_profile(ftafqmc_t h, int enable, double* h_ms, long long* h_count) {
   return rc;
 }
 
-const char* ftafqmc_last_error(ftafqmc_t h) { return h ? h->err.c_str() : "null handle"; }
+const char* ftafqmc_last_error(ftafqmc_t h) { return h ? h->err.c_str() : init_err.c_str(); }
 
 void ftafqmc_destroy(ftafqmc_t h) {
   if (!h) return;
@@ -1016,3 +1149,8 @@ void ftafqmc_destroy(ftafqmc_t h) {
 }
 
 }  // extern "C"
+
+int lib_init_error(int code, const char* msg) {
+  init_err = msg ? msg : "";
+  return code;
+}

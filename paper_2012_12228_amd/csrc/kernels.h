@@ -70,7 +70,7 @@ struct SysDev {
   // state
   double2* Y; double2* Ti; double2* G; double2* aug;
   void* V; void* V2; void* V3; void* V4; void* E0; void* E1;  // complex128 or complex64
-  void* Bk[3];            // Paterson-Stockmeyer blocks B_0..B_2 (complex128 or complex64)
+  void* Bk[5];            // Paterson-Stockmeyer blocks B_0..B_{nb-2} (complex128 or complex64)
   double2* Ynew;
   double* D; double* Dpi; int* perm; int* piv;
   double2* tri;           // [W][elim_tri_elems(M)]
@@ -88,6 +88,11 @@ struct SysDev {
   double* rec_logw;       // [nrec_max][W]
   int* rec_status;        // [nrec_max][W]
   double* scratch;        // [W][ld] reals
+  double* tnorm;          // [W][16] per 64-column chunk: max column 1-norm of V (0..7) and of V^4 (8..15)
+  int* pop_parent;        // [W] population control: walker copied into each slot
+  double* pop_logw;       // [W] population control: new ln w of each slot
+  int taylor_deg;         // degree of the Taylor polynomial of e^V (a multiple of 4)
+  double taylor_tol;      // a walker whose truncation bound exceeds this is flagged numeric
   double2* rec_c;         // [W][n][NQ] shifted coefficients c_Q of every slice (path record), or null
   double2* rec_trG;       // [W][n+1] tr G_k of every slice, or null
   int w_off, rec_W;       // walker offset of this view and walker count of the record arrays
@@ -129,6 +134,19 @@ hipError_t launch_energy_tangent(const SysDev& s, const TanDev& t, int dir, hipS
 hipError_t launch_tan_mean(const SysDev& s, const TanDev& t, const double* cot, double2* jac,
                            double* grad, double2* walker, hipStream_t st);
 
+// Truncation check of the Taylor polynomial of e^V: per-chunk column 1-norms of V and V^4 into
+// tnorm (the weight kernel turns them into a bound on the remainder and flags the walker).
+hipError_t launch_taylor_norms(const SysDev& s, int mixed, hipStream_t st);
+// Lower Paterson-Stockmeyer blocks B_k = sum_{r<4} c[k][r] V^r (identity for r = 0) for k < nlo,
+// written to s.Bk[k] (used when the V^4 product's epilogue cannot write them all).
+struct TaylorLow { int nlo; double c[2][4]; };
+hipError_t launch_taylor_blocks(const SysDev& s, int mixed, const TaylorLow& t, hipStream_t st);
+// Population control (method 0 comb, 1 pair branch) with uniforms u; parent / newlogw [W].
+hipError_t launch_population_control(const SysDev& s, int method, const double* u, int* parent, double* newlogw,
+                                     hipStream_t st);
+size_t pop_select_lds(int W);
+// Weighted statistics of the nrec energy records into stats [nrec][8] (and their averages into avg [3]).
+hipError_t launch_record_stats(const SysDev& s, int nrec, double* stats, double* avg, hipStream_t st);
 hipError_t launch_init_state(const SysDev& s, hipStream_t st);
 hipError_t launch_coef_v(const SysDev& s, const double2* fields, int k, int mixed, hipStream_t st);
 hipError_t launch_greens_form(const SysDev& s, int k, hipStream_t st);
@@ -141,6 +159,8 @@ hipError_t launch_stab_finish_a(const SysDev& s, hipStream_t st);     // Y, D, R
 hipError_t launch_stab_build_ti(const SysDev& s, hipStream_t st);     // aug = [Ru^T | Ti_pi^T]
 hipError_t launch_stab_finish_b(const SysDev& s, hipStream_t st);     // Ti = (aug right)^T
 hipError_t launch_energy(const SysDev& s, int rec, hipStream_t st);   // local energies (+ record)
+// <rho(Q) rho(-Q)> per walker into out [W][NQ] (X: [W][ld][ld] scratch), weighted mean into mean [NQ]
+hipError_t launch_density_correlation(const SysDev& s, double2* X, double2* out, double2* mean, hipStream_t st);
 hipError_t launch_energy_mean(const SysDev& s, const double2* local, const double* logw,
                               const int* status, double2* mean, hipStream_t st);
 hipError_t launch_copy_greens(const SysDev& s, void* out, int dtype, hipStream_t st);

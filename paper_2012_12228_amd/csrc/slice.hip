@@ -93,6 +93,92 @@ __global__ __launch_bounds__(NT) void fill_v_kernel(SysDev s, TV* V, int chunks)
   }
 }
 
+// -------------------------------------------- Taylor truncation check ---
+// Column 1-norms of V and of V^4 (the Paterson-Stockmeyer chain's own V^4): 64 columns per
+// workgroup, the rows shared by the 4 waves; the maximum over the chunk's columns goes to
+// tnorm[w][c] (V) and tnorm[w][8 + c] (V^4).  A NaN entry makes the norm NaN.
+template <typename TV>
+__global__ __launch_bounds__(NT) void taylor_norms_kernel(SysDev s, const TV* V, const TV* V4, int chunks) {
+  __shared__ double part[2][NT / 64][64];
+  int w, c;
+  if (!xcd_walker_tile(blockIdx.x, s.W, chunks, &w, &c)) return;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int M = s.M, ld = s.ld, j = c * 64 + lane;
+  const TV* Vw = V + (long long)w * s.mat_stride;
+  const TV* V4w = V4 + (long long)w * s.mat_stride;
+  double a = 0.0, b = 0.0;
+  if (j < M) {
+#pragma unroll 4
+    for (int i = wid; i < M; i += NT / 64) {
+      const double2 x = to_d2(Vw[(long long)i * ld + j]), y = to_d2(V4w[(long long)i * ld + j]);
+      a += sqrt(cabs2(x));
+      b += sqrt(cabs2(y));
+    }
+  }
+  part[0][wid][lane] = a;
+  part[1][wid][lane] = b;
+  __syncthreads();
+  if (wid == 0) {
+    a = (part[0][0][lane] + part[0][1][lane]) + (part[0][2][lane] + part[0][3][lane]);
+    b = (part[1][0][lane] + part[1][1][lane]) + (part[1][2][lane] + part[1][3][lane]);
+    for (int o = 32; o > 0; o >>= 1) {
+      const double a2 = __shfl_xor(a, o, 64), b2 = __shfl_xor(b, o, 64);
+      a = (a2 > a || a2 != a2) ? a2 : a;       // a NaN wins
+      b = (b2 > b || b2 != b2) ? b2 : b;
+    }
+    if (lane == 0) {
+      s.tnorm[(long long)w * 16 + c] = a;
+      s.tnorm[(long long)w * 16 + 8 + c] = b;
+    }
+  }
+}
+
+// Bound on the Taylor remainder sum_{j > p} ||V^j|| / j! with ||V^{4q+b}|| <= ||V^4||^q ||V||^b
+// (1-norms, submultiplicative), from the chunk maxima in tnorm.  NaN if a norm is NaN.
+FT_DEV double taylor_tail(const SysDev& s, int w) {
+  double n1 = 0.0, n4 = 0.0;
+  const int chunks = (s.M + 63) / 64;
+  for (int c = 0; c < chunks; ++c) {
+    const double a = s.tnorm[(long long)w * 16 + c], b = s.tnorm[(long long)w * 16 + 8 + c];
+    n1 = (a > n1 || a != a) ? a : n1;
+    n4 = (b > n4 || b != b) ? b : n4;
+  }
+  if (n1 != n1 || n4 != n4) return NAN;
+  if (n4 == 0.0) return 0.0;
+  const double l1 = n1 > 0.0 ? log(n1) : -INFINITY, l4 = log(n4);
+  double lf = 0.0;                                   // ln j!
+  for (int j = 2; j <= s.taylor_deg; ++j) lf += log((double)j);
+  double tail = 0.0;
+  for (int j = s.taylor_deg + 1; j <= s.taylor_deg + 80; ++j) {
+    lf += log((double)j);
+    const int q = j >> 2, b = j & 3;
+    const double t = exp((double)q * l4 + (b ? (double)b * l1 : 0.0) - lf);
+    tail += t;
+    if (t < 1e-30 * tail) break;
+  }
+  return tail;
+}
+
+// Lower Taylor blocks B_k = c[k][0] I + c[k][1] V + c[k][2] V^2 + c[k][3] V^3, k < t.nlo.
+template <typename TV>
+__global__ __launch_bounds__(NT) void taylor_blocks_kernel(SysDev s, TaylorLow t) {
+  const long long total = (long long)s.W * s.mat_stride;
+  const TV* V = (const TV*)s.V;
+  const TV* V2 = (const TV*)s.V2;
+  const TV* V3 = (const TV*)s.V3;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < total; e += (long long)gridDim.x * NT) {
+    const long long loc = e % s.mat_stride;
+    const int i = (int)(loc / s.ld), j = (int)(loc % s.ld);
+    const double di = (i == j && i < s.M) ? 1.0 : 0.0;
+    const double2 v1 = to_d2(V[e]), v2 = to_d2(V2[e]), v3 = to_d2(V3[e]);
+    for (int k = 0; k < t.nlo; ++k) {
+      double2 b = make_double2(t.c[k][0] * di, 0.0);
+      b = cadd(b, cadd(cscale(v1, t.c[k][1]), cadd(cscale(v2, t.c[k][2]), cscale(v3, t.c[k][3]))));
+      store_c((TV*)s.Bk[k] + e, b);
+    }
+  }
+}
+
 // ------------------------------------------------------ Green's function ---
 FT_DEV void split_L(const SysDev& s, int i, int k, double* lb, double* ls) {
   const double lnl = (double)(s.n - k) * s.lnbt[i];
@@ -313,7 +399,12 @@ __global__ __launch_bounds__(NT) void weight_kernel(SysDev s, int k, double sum_
   s.slice_theta[(long long)w * s.n + (k - 1)] = th;
   if (st == 0) {
     const double cth = cos(th);
-    if (!(isfinite(lnI) && isfinite(ell.x) && isfinite(ell.y)) || bad > 0.0) { s.status[w] = 2; s.logw[w] = -INFINITY; }
+    // the slice's e^V is trusted only while its Taylor remainder bound is below the tolerance
+    const double tail = s.tnorm ? taylor_tail(s, w) : 0.0;
+    if (!(isfinite(lnI) && isfinite(ell.x) && isfinite(ell.y)) || bad > 0.0 || !(tail <= s.taylor_tol)) {
+      s.status[w] = 2;
+      s.logw[w] = -INFINITY;
+    }
     else if (cth <= 0.0) { s.status[w] = 1; s.logw[w] = -INFINITY; }
     else s.logw[w] += lnI + log(cth);
   }
@@ -439,23 +530,38 @@ __global__ __launch_bounds__(NT) void stab_finish_a_kernel(SysDev s) {
   }
 }
 
+// New D from the pivots d_i of the Cholesky (LDL^H) step, and the conditioning test of the pass:
+// rho = min_i d_i / S_ii is the smallest squared sine between a pre-pivoted column of Y and the
+// span of the columns before it (S = E0^H E0, S_ii = |Y e_perm(i)|^2 from the pre-pivot norms).
+// Cholesky-QR loses orthogonality like eps / rho; below STAB_MIN_RHO (or at a non-positive or
+// non-finite pivot) the walker is flagged numeric instead of carrying a non-orthogonal Q.
+constexpr double STAB_MIN_RHO = 1e-5;
 __global__ __launch_bounds__(NT) void stab_newd_kernel(SysDev s) {
+  __shared__ double red[8];
   const int w = blockIdx.x;
   if (w >= s.W) return;
   const double2* aug = s.aug + (long long)w * s.aug_stride;
   const double* Dpi = s.Dpi + (long long)w * s.ld;
+  const int* perm = s.perm + (long long)w * s.ld;
+  const double* nrm = s.scratch + (long long)w * s.ld;      // |Y e_j| |D_j| from the pre-pivot
   double* D = s.D + (long long)w * s.ld;
-  int bad = 0;
+  double bad = 0.0;
   for (int i = threadIdx.x; i < s.ld; i += NT) {
     double v = 0.0;
     if (i < s.M) {
       const double d = aug[(long long)i * 2 * s.ld + i].x;
-      if (!(d > 0.0) || !isfinite(d)) bad = 1;
+      const double cn = nrm[perm[i]] / fabs(Dpi[i]);
+      const double rho = d / (cn * cn);
+      if (!(d > 0.0) || !isfinite(d) || !(rho >= STAB_MIN_RHO)) bad = 1.0;
       v = sqrt(d) * Dpi[i];
     }
     D[i] = v;
   }
-  if (bad) s.status[w] = 2;   // Cholesky breakdown: the partial product was too ill-conditioned
+  bad = block_sum_256(bad, red);
+  if (threadIdx.x == 0 && bad > 0.0 && s.status[w] == 0) {
+    s.status[w] = 2;   // the partial product was too ill-conditioned for one Cholesky-QR pass
+    if (s.logw) s.logw[w] = -INFINITY;
+  }
 }
 
 // aug = [Ru^T | (Ti[:, perm])^T]
@@ -519,8 +625,9 @@ __global__ __launch_bounds__(NT) void stab_finish_b_kernel(SysDev s) {
 // K_c = K_b - (K_a - K_d), P = I - G^T.  One workgroup per (walker, a), the d shared over the
 // waves, b over the lanes; the lookup tables sit in LDS and each lane's (at most 8) gathers
 // of row d are issued together.
-template <int EX_B>                                 // b per lane: M <= 64 EX_B
-__global__ __launch_bounds__(NT) void exchange_kernel(SysDev s) {
+// With X: the sum over b for every pair (a, d) also goes to X[w][a][d] (for <rho(Q) rho(-Q)>).
+template <int EX_B, bool WITHX>                     // b per lane: M <= 64 EX_B
+__global__ __launch_bounds__(NT) void exchange_kernel(SysDev s, double2* X) {
   extern __shared__ char dyn[];
   const int M = s.M, ld = s.ld;
   double2* pcol = (double2*)dyn;                    // [M]: P_ab = delta_ab - G_ba
@@ -574,9 +681,55 @@ __global__ __launch_bounds__(NT) void exchange_kernel(SysDev s) {
     }
     acc.x += v * part.x;
     acc.y += v * part.y;
+    if constexpr (WITHX) {
+      const double px = wave_sum(part.x), py = wave_sum(part.y);
+      if (lane == 0) X[(long long)w * s.mat_stride + (long long)a * ld + d] = make_double2(px, py);
+    }
   }
   acc = block_csum_256(acc, red);
   if (threadIdx.x == 0) s.exch[(long long)w * ld + a] = acc;
+}
+
+// <rho(Q) rho(-Q)> = 4 r_Q r_-Q + 2 (n_Q - Lambda_Q) per walker and Q (Wick's theorem with both
+// spins), with Lambda_Q = sum over the pairs (p, r) of Q (K_p - K_r = Q) of X[p][r] and
+// n_Q = sum over the same pairs of P_pp = 1 - G_pp.  One thread per (walker, Q).
+__global__ __launch_bounds__(NT) void density_corr_kernel(SysDev s, const double2* X, double2* out, int chunks) {
+  int w, c;
+  if (!xcd_walker_tile(blockIdx.x, s.W, chunks, &w, &c)) return;
+  const int q = c * NT + threadIdx.x;
+  if (q >= s.NQ) return;
+  const double2* G = s.G + (long long)w * s.mat_stride;
+  const double2* Xw = X + (long long)w * s.mat_stride;
+  double2 lam = zero2(), nq = zero2();
+  for (int e = s.qptr[q]; e < s.qptr[q + 1]; ++e) {
+    const int f = s.qpair[e];                     // r ld + p
+    const int r = f / s.ld, p = f - r * s.ld;
+    lam = cadd(lam, Xw[(long long)p * s.ld + r]);
+    const double2 g = G[(long long)p * s.ld + p];
+    nq = cadd(nq, make_double2(1.0 - g.x, -g.y));
+  }
+  const double2* rr = s.r + (long long)w * s.NQ;
+  const double2 h = cmul(rr[q], rr[s.neg[q]]);
+  out[(long long)w * s.NQ + q] = make_double2(4.0 * h.x + 2.0 * (nq.x - lam.x), 4.0 * h.y + 2.0 * (nq.y - lam.y));
+}
+
+// Weighted mean over live walkers of per-walker values v [W][n] into mean [n].
+__global__ __launch_bounds__(NT) void weighted_mean_kernel(const double2* v, int n, const double* logw,
+                                                           const int* status, int W, double2* mean) {
+  const int q = blockIdx.x * NT + threadIdx.x;
+  if (q >= n) return;
+  double mx = -INFINITY;
+  for (int w = 0; w < W; ++w)
+    if (status[w] == 0 && isfinite(logw[w])) mx = fmax(mx, logw[w]);
+  double ws = 0.0;
+  double2 acc = zero2();
+  for (int w = 0; w < W; ++w)
+    if (status[w] == 0 && isfinite(logw[w])) {
+      const double f = exp(logw[w] - mx);
+      ws += f;
+      acc = cadd(acc, cscale(v[(long long)w * n + q], f));
+    }
+  mean[q] = ws > 0.0 ? cscale(acc, 1.0 / ws) : make_double2(NAN, NAN);
 }
 
 // E1 = 2 lambda sum eps P_KK, N = 2 sum P_KK, Hartree = (1/2) sum v_Q 4 r_Q r_-Q,
@@ -683,6 +836,20 @@ hipError_t launch_coef_v(const SysDev& s, const double2* fields, int k, int mixe
   else fill_v_kernel<double2><<<tiles_blocks(s, chunks), NT, 0, st>>>(s, (double2*)s.V, chunks);
   return hipGetLastError();
 }
+hipError_t launch_taylor_norms(const SysDev& s, int mixed, hipStream_t st) {
+  const int chunks = (s.M + 63) / 64;
+  if (chunks > 8) return hipErrorInvalidValue;
+  if (mixed) taylor_norms_kernel<float2><<<tiles_blocks(s, chunks), NT, 0, st>>>(s, (const float2*)s.V, (const float2*)s.V4, chunks);
+  else taylor_norms_kernel<double2><<<tiles_blocks(s, chunks), NT, 0, st>>>(s, (const double2*)s.V, (const double2*)s.V4, chunks);
+  return hipGetLastError();
+}
+hipError_t launch_taylor_blocks(const SysDev& s, int mixed, const TaylorLow& t, hipStream_t st) {
+  if (t.nlo < 0 || t.nlo > 2) return hipErrorInvalidValue;
+  if (t.nlo == 0) return hipSuccess;
+  if (mixed) taylor_blocks_kernel<float2><<<2048, NT, 0, st>>>(s, t);
+  else taylor_blocks_kernel<double2><<<2048, NT, 0, st>>>(s, t);
+  return hipGetLastError();
+}
 hipError_t launch_greens_form(const SysDev& s, int k, hipStream_t st) {
   greens_form_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s, k);
   return hipGetLastError();
@@ -731,13 +898,28 @@ hipError_t launch_stab_finish_b(const SysDev& s, hipStream_t st) {
   stab_finish_b_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s);
   return hipGetLastError();
 }
-hipError_t launch_energy(const SysDev& s, int rec, hipStream_t st) {
+template <bool WITHX> hipError_t launch_exchange(const SysDev& s, double2* X, hipStream_t st) {
   const size_t shm = (size_t)s.M * (sizeof(double2) + sizeof(int)) +
                      (size_t)s.grid_dim * s.grid_dim * s.grid_dim * sizeof(short) + 16;
-  if (s.M <= 64 * 2) exchange_kernel<2><<<tiles_blocks(s, s.M), NT, shm, st>>>(s);
-  else if (s.M <= 64 * 4) exchange_kernel<4><<<tiles_blocks(s, s.M), NT, shm, st>>>(s);
-  else if (s.M <= 64 * 8) exchange_kernel<8><<<tiles_blocks(s, s.M), NT, shm, st>>>(s);
+  if (s.M <= 64 * 2) exchange_kernel<2, WITHX><<<tiles_blocks(s, s.M), NT, shm, st>>>(s, X);
+  else if (s.M <= 64 * 4) exchange_kernel<4, WITHX><<<tiles_blocks(s, s.M), NT, shm, st>>>(s, X);
+  else if (s.M <= 64 * 8) exchange_kernel<8, WITHX><<<tiles_blocks(s, s.M), NT, shm, st>>>(s, X);
   else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+hipError_t launch_density_correlation(const SysDev& s, double2* X, double2* out, double2* mean, hipStream_t st) {
+  hipError_t e = launch_exchange<true>(s, X, st);
+  if (e != hipSuccess) return e;
+  const int chunks = (s.NQ + NT - 1) / NT;
+  density_corr_kernel<<<tiles_blocks(s, chunks), NT, 0, st>>>(s, X, out, chunks);
+  e = hipGetLastError();
+  if (e != hipSuccess || !mean) return e;
+  weighted_mean_kernel<<<(s.NQ + NT - 1) / NT, NT, 0, st>>>(out, s.NQ, s.logw, s.status, s.W, mean);
+  return hipGetLastError();
+}
+hipError_t launch_energy(const SysDev& s, int rec, hipStream_t st) {
+  hipError_t e0 = launch_exchange<false>(s, nullptr, st);
+  if (e0 != hipSuccess) return e0;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   energy_finish_kernel<<<s.W, NT, 0, st>>>(s, rec);

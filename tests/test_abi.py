@@ -48,7 +48,7 @@ def test_invalid_parameters_are_rejected(bad):
         F.ftafqmc_workspace_bytes([sysdef])
 
 
-@pytest.mark.parametrize("bad", [dict(flags=8), dict(flags=1, precision=1), dict(flags=1, nmax2=11, n_elec=66, theta=0.125)])
+@pytest.mark.parametrize("bad", [dict(flags=1024), dict(flags=1, precision=1), dict(flags=1, nmax2=11, n_elec=66, theta=0.125)])
 def test_invalid_flags_are_rejected(bad):
     """Unknown flag bits, a path record with mixed precision, and a path record whose doubled
     system would exceed the elimination's 512 rows (M = 171 is fine; M > 256 is not)."""
@@ -65,7 +65,8 @@ def test_flag_values_match_the_header():
     text = open(HEADER).read()
     for name, val in (("FTAFQMC_CHECKPOINT", F.FTAFQMC_CHECKPOINT), ("FTAFQMC_OVERLAP", F.FTAFQMC_OVERLAP),
                       ("FTAFQMC_GRAPH", F.FTAFQMC_GRAPH), ("FTAFQMC_FROZEN_PATH", F.FROZEN_PATH),
-                      ("FTAFQMC_PROFILE_ONLY", F.FTAFQMC_PROFILE_ONLY)):
+                      ("FTAFQMC_PROFILE_ONLY", F.FTAFQMC_PROFILE_ONLY), ("FTAFQMC_TRIAL_THF", F.FTAFQMC_TRIAL_THF),
+                      ("FTAFQMC_POP_COMB", F.POP_COMB), ("FTAFQMC_POP_PAIR_BRANCH", F.POP_PAIR_BRANCH)):
         m = re.search(r"#define\s+%s\s+(\d+)" % name, text)
         assert m and int(m.group(1)) == val, name
 

@@ -234,19 +234,140 @@ def test_bitwise_reproducible():
 
 
 def test_phaseless_kills_match_oracle():
+    """Fields of twice the unit variance at r_s = 2 kill half the walkers (cos theta <= 0) while
+    every slice's Taylor remainder bound stays below 1e-14: kills, survivors' weights and the
+    final G match the oracle."""
     F = _F()
-    sd = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5, walkers=24)
+    sd = dict(n_elec=14, rs=2.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5, walkers=24)
     s = oracle_system(sd)
-    flds = 6.0 * si.fields(4242, 24, s.n_slices, s.NQ)
+    flds = 2.0 * si.fields(4242, 24, s.n_slices, s.NQ)
     ctx, _ = gpu_run(F, [sd], [flds])
-    st = ctx.energy()["status"].cpu().numpy()
+    e = ctx.energy()
+    st = e["status"].cpu().numpy()
     refs = [path.run_walker(s, flds[w]) for w in range(24)]
     want = np.array([r["status"] for r in refs])
-    assert (want == path.KILLED).any()
+    assert (want == path.KILLED).sum() >= 6 and (want == path.ALIVE).sum() >= 6
     assert np.array_equal(st, want)
-    lw = ctx.energy()["logw"].cpu().numpy()
+    lw = e["logw"].cpu().numpy()
     assert np.all(np.isinf(lw[want == path.KILLED]))
-    assert np.all(np.isfinite(ctx.greens().cpu().numpy()))
+    G = ctx.greens().cpu().numpy()
+    for w in range(24):
+        if want[w] == path.ALIVE:
+            assert abs(lw[w] - refs[w]["logw"]) < FP64_REL * max(1.0, abs(refs[w]["logw"])), w
+        assert rel_mat(G[w], refs[w]["G"]) < FP64_REL, w
+
+
+def test_taylor_bound_flags_oversized_fields():
+    """Fields of six times the unit variance make the degree-16 Taylor polynomial of e^V
+    inaccurate (remainder bound ~1e-7).  The device check must flag such walkers numeric: no
+    walker may stay alive with a truncated exponential."""
+    F = _F()
+    sd = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5, walkers=8)
+    s = oracle_system(sd)
+    flds = 6.0 * si.fields(4242, 8, s.n_slices, s.NQ)
+    ctx, _ = gpu_run(F, [sd], [flds])
+    assert ctx.info()["taylor_degree"] == 16
+    e = ctx.energy()
+    st = e["status"].cpu().numpy()
+    assert np.all(st == path.NUMERIC), st
+    assert np.all(np.isinf(e["logw"].cpu().numpy()))
+    assert torch.isnan(e["mean"]).all()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_large_dtau_raises_taylor_degree(precision):
+    """dtau = 0.2 (four times the workload's step): the a-priori norm estimate of V raises the
+    Taylor degree to 20 (FP64; the V^4 product's epilogue writes three of the four lower blocks
+    and an elementwise pass the last) or 16 (mixed), and the path matches the oracle (expm)."""
+    F = _F()
+    sd = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.2, stab_every=2, walkers=16, precision=precision)
+    s = oracle_system(sd)
+    flds = si.fields(2002, sd["walkers"], s.n_slices, s.NQ)
+    ctx, _ = gpu_run(F, [sd], [flds])
+    assert ctx.info()["taylor_degree"] == (20 if precision == 0 else 16)
+    rec = ctx.records()
+    G = ctx.greens().cpu().numpy()
+    st = ctx.energy()["status"].cpu().numpy()
+    for w in range(sd["walkers"]):
+        ref = path.run_walker(s, flds[w], energy_fn=energy.local_energy)
+        assert st[w] == ref["status"] == path.ALIVE, w
+        check_walker(rec["trace"].cpu().numpy()[:, w], rec["logw"].cpu().numpy()[:, w], G[w], ref,
+                     mixed=precision == 1, label=w)
+
+
+@pytest.mark.parametrize("case", ["m19_theta0.0625_stab_n", "m19_theta0.5_stab_n"])
+def test_stab_every_n_is_refactorised_or_flagged(case):
+    """stab_every = n (one stabilisation, at the end): at Theta = 0.0625 (r_s = 0.5) the product's
+    kinetic range over 43 slices is e^23, beyond one Cholesky-QR pass, so the library re-factorises
+    every 10 slices on its own (records stay at slice n); at Theta = 0.5 one pass at slice 22
+    suffices.  Every walker matches the oracle to 1e-10 or is flagged numeric; none is alive and
+    wrong."""
+    F = _F()
+    if case.startswith("m19_theta0.0625"):
+        sd = dict(n_elec=14, rs=0.5, theta=0.0625, nmax2=2, dtau=0.05, walkers=32)
+    else:
+        sd = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, walkers=32)
+    s = oracle_system(dict(sd, stab_every=1))
+    sd["stab_every"] = s.n_slices
+    flds = si.fields(4343, sd["walkers"], s.n_slices, s.NQ)
+    ctx, _ = gpu_run(F, [sd], [flds])
+    inf = ctx.info()
+    assert inf["refactor_every"] == (10 if case.startswith("m19_theta0.0625") else 43)
+    rec = ctx.records()
+    assert rec["slices"] == [s.n_slices]
+    st = ctx.energy()["status"].cpu().numpy()
+    G = ctx.greens().cpu().numpy()
+    s.stab_every = s.n_slices
+    alive = 0
+    for w in range(sd["walkers"]):
+        ref = path.run_walker(s, flds[w], energy_fn=energy.local_energy)
+        if st[w] == path.NUMERIC:
+            continue
+        assert st[w] == ref["status"], w
+        check_walker(rec["trace"].cpu().numpy()[:, w], rec["logw"].cpu().numpy()[:, w], G[w], ref, label=w)
+        alive += 1
+    assert alive == sd["walkers"]            # the re-factorisation cap keeps every pass conditioned
+
+
+def test_weighted_means_under_unequal_weights():
+    """ftafqmc_energy's d_mean is sum_w w O_w / sum_w w over live walkers: checked against the
+    oracle's per-walker values and weights (ln w spread over several units) at 1e-10."""
+    F = _F()
+    wl = si.WORKLOADS["ueg_n14_m19"]
+    sd = dict(wl["systems"][0])
+    s = oracle_system(sd)
+    W = sd["walkers"]
+    flds = si.fields(si.system_seed("ueg_n14_m19", 0), W, s.n_slices, s.NQ)
+    ctx, _ = gpu_run(F, [sd], [flds])
+    mean = ctx.energy()["mean"].cpu().numpy()
+    refs = [path.run_walker(s, flds[w], energy_fn=energy.local_energy) for w in range(W)]
+    lw = np.array([r["logw"] for r in refs])
+    live = np.array([r["status"] == path.ALIVE for r in refs])
+    assert live.sum() == W and lw.max() - lw.min() > 1.0       # genuinely unequal weights
+    wts = np.exp(lw - lw.max())
+    for c, key in enumerate(("E1", "E2", "E", "N")):
+        vals = np.array([r["records"][-1][key] for r in refs])
+        want = np.sum(wts * vals) / np.sum(wts)
+        assert relc(mean[c], want) < FP64_REL, (key, mean[c], want)
+        unweighted = vals.mean()
+        assert relc(unweighted, want) > 1e3 * FP64_REL          # the weights matter at this tolerance
+
+
+def test_greens_complex64_copy_and_dtype_checks():
+    F = _F()
+    sd = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5, walkers=4)
+    s = oracle_system(sd)
+    flds = si.fields(31, 4, s.n_slices, s.NQ)
+    ctx, _ = gpu_run(F, [sd], [flds])
+    g128 = ctx.greens(dtype=torch.complex128)
+    g64 = ctx.greens(dtype=torch.complex64)
+    torch.cuda.synchronize()
+    assert torch.equal(g64, g128.to(torch.complex64))
+    for bad in (torch.empty((4, s.M, s.M), dtype=torch.float32, device="cuda"),
+                torch.empty((4, s.M, s.M + 1), dtype=torch.complex128, device="cuda"),
+                torch.empty((4, s.M, 2 * s.M), dtype=torch.complex128, device="cuda")[:, :, ::2]):
+        with pytest.raises(ValueError):
+            F.ftafqmc_greens(ctx.handle, 0, bad, ctx.device)
 
 
 def test_nan_fields_flag_only_that_walker():
