@@ -159,13 +159,13 @@ class RightBlock:
         return (self.Q * self.D[None, :]) @ self.T
 
 
-def greens_at(sys, right, k):
+def greens_at(sys, right, k, lexp=None):
     """G_k = (I + B_T^{n-k} R_k)^{-1} and ln det(I + B_T^{n-k} R_k).
 
-    The left block is the diagonal B_T^{n-k}; C = B_T^{n-k} Q_R D_R is factorised
-    by row-sorted QRCP and combined with T_R.
+    The left block is the diagonal B_T^{n-k} (B_T^lexp when lexp is given); C = B_T^{n-k} Q_R D_R
+    is factorised by row-sorted QRCP and combined with T_R.
     """
-    left = np.exp((sys.n_slices - k) * sys.log_trial_diag())
+    left = np.exp((sys.n_slices - k if lexp is None else lexp) * sys.log_trial_diag())
     C = left[:, None] * right.Q * right.D[None, :]
     Q, D, T = qdt_update(C, right.T, row_grading=left)
     return greens_from_qdt(Q, D, T)
@@ -193,12 +193,13 @@ def shifted_one_body(sys, G, z_k):
 
 
 def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, stop_after=None,
-               record_path=False):
+               record_path=False, modified=False):
     """Propagate one walker from tau = 0 to tau = beta with fields z[k, q].
 
     stop_after: end the path after that many slices (a bounded sample for timing).
     record_path: also return the sampled path, i.e. the shifted one-body matrix V_k and the
     weight exponent of every slice (out["path"]), so that replay_walker can re-run it.
+    modified: the constraint of the modified overlap ratio, eq. ztfix (see Walker).
 
     z: complex [n_slices, NQ]; Re z = field of A(Q), Im z = field of B(Q).
     Measures the local energy (energy_fn(sys, G)) after slice k+1 when
@@ -215,7 +216,7 @@ def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, st
             expos.append(expo)
         return V, expo
 
-    out = _walk(sys, shifted, measure_every, energy_fn, keep_greens, stop_after)
+    out = _walk(sys, shifted, measure_every, energy_fn, keep_greens, stop_after, modified)
     if record_path:
         out["path"] = dict(V=Vs, expo=expos)
     return out
@@ -236,18 +237,34 @@ class Walker:
     """One walker at slice k: the QDT factors of its sampled product R_k, G_k and
     ln det(I + A_k) (A_k = B_T^{n-k} R_k), ln w and its status.  step() inserts the next slice
     propagator and applies the phaseless weight update; copy() clones the walker (population
-    control copies whole walkers)."""
+    control copies whole walkers).
 
-    def __init__(self, sys):
+    modified=True takes the constraint from the modified overlap ratio of eq. ztfix,
+    S~_k = tr(B_T^n B_k ... B_1) / tr(B_T^n B_{k-1} ... B_1), i.e. A_k = B_T^n R_k at every slice:
+    G, ln det, the force bias, S and theta all use it (the trial raised to the n-th power
+    throughout, Sec. "The T -> 0 limit").  Estimators still use G_k = (I + B_T^{n-k} R_k)^{-1}
+    (measure_greens)."""
+
+    def __init__(self, sys, modified=False):
         self.sys = sys
         self.k = 0
+        self.modified = modified
         self.right = RightBlock(sys.M)
-        self.G, self.ell = greens_at(sys, self.right, 0)
+        self.G, self.ell = greens_at(sys, self.right, 0, self._lexp(0))
         self.logw, self.status = 0.0, ALIVE
+
+    def _lexp(self, k):
+        return self.sys.n_slices if self.modified else self.sys.n_slices - k
+
+    def measure_greens(self):
+        """G_k = (I + B_T^{n-k} R_k)^{-1}, the Green's function of the estimators."""
+        if not self.modified:
+            return self.G
+        return greens_at(self.sys, self.right, self.k)[0]
 
     def copy(self):
         w = Walker.__new__(Walker)
-        w.sys, w.k = self.sys, self.k
+        w.sys, w.k, w.modified = self.sys, self.k, self.modified
         w.right = RightBlock(self.sys.M)
         w.right.Q, w.right.D, w.right.T = self.right.Q.copy(), self.right.D.copy(), self.right.T.copy()
         w.G, w.ell, w.logw, w.status = self.G.copy(), self.ell, self.logw, self.status
@@ -263,7 +280,7 @@ class Walker:
         kh = np.exp(-0.5 * sys.dtau * sys.h1_diag())
         B = kh[:, None] * sla.expm(V) * kh[None, :]          # eq. B
         self.right.push(B)
-        self.G, ell_new = greens_at(sys, self.right, k + 1)
+        self.G, ell_new = greens_at(sys, self.right, k + 1, self._lexp(k + 1))
         lnS = 2.0 * (ell_new - self.ell)
         self.ell = ell_new
         theta = float(wrap_angle(lnS.imag))
@@ -279,10 +296,10 @@ class Walker:
         return lnS, theta, lnI
 
 
-def _walk(sys, shifted, measure_every, energy_fn, keep_greens, stop_after):
+def _walk(sys, shifted, measure_every, energy_fn, keep_greens, stop_after, modified=False):
     n = sys.n_slices
     s = sys.stab_every if measure_every is None else measure_every
-    wk = Walker(sys)
+    wk = Walker(sys, modified)
     ell0 = wk.ell
     lnS_all = np.zeros(n, dtype=np.complex128)
     theta_all = np.zeros(n)
@@ -299,10 +316,10 @@ def _walk(sys, shifted, measure_every, energy_fn, keep_greens, stop_after):
         if (k + 1) % s == 0 or k + 1 == n:
             rec = dict(slice=k + 1, logw=wk.logw, status=wk.status, lndet=wk.ell)
             if energy_fn is not None:
-                rec.update(energy_fn(sys, wk.G))
+                rec.update(energy_fn(sys, wk.measure_greens()))
             records.append(rec)
             if keep_greens:
-                greens.append(wk.G.copy())
-    return dict(G=wk.G, lndet=wk.ell, lndet0=ell0, logw=wk.logw, status=wk.status, lnS=lnS_all,
+                greens.append(wk.measure_greens().copy())
+    return dict(G=wk.measure_greens(), G_constraint=wk.G, lndet=wk.ell, lndet0=ell0, logw=wk.logw, status=wk.status, lnS=lnS_all,
                 theta=theta_all, lnI=lnI_all, alive=alive_after, records=records, greens=greens,
                 greens_all=greens_all, right=wk.right)

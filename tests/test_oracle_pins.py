@@ -504,3 +504,39 @@ def test_thermal_hartree_fock_trial_is_stationary_point_of_mermin_functional(arg
     f0 = 1.0 / (1.0 + np.exp(s.beta * (s.eps - ueg.trial_chemical_potential(s.eps, s.beta, n))))
     K = int(np.argmin(np.abs(f0 - 0.5)))
     assert abs(dOmega_dx(f0, K)) > 1e-2 * f0[K] * (1.0 - f0[K])
+
+
+# ---------------------------------------------- modified overlap ratio ---
+def test_modified_overlap_zero_field_closed_form():
+    """Eq. ztfix with zero fields: every B is the diagonal exp(-dtau (lambda eps + h - mu)), so
+    ln S~_k = 2 sum_K [ln(1 + t_K^n b_K^k) - ln(1 + t_K^n b_K^(k-1))] with t = diag B_T; the
+    standard ratio has t^(n-k) and t^(n-k+1) instead.  Estimators keep G_k = (I + B_T^{n-k} R_k)^-1."""
+    s = ueg.UEGSystem(14, 1.0, 0.5, 2, 0.05, stab_every=5, kscale=0.9, mu=1.1)
+    z = np.zeros((s.n_slices, s.NQ), dtype=np.complex128)
+    out = path.run_walker(s, z, modified=True, energy_fn=energy.local_energy)
+    std = path.run_walker(s, z)
+    n = s.n_slices
+    lt = s.log_trial_diag()
+    lb = -s.dtau * s.h1_diag()
+    for k in range(1, n + 1):
+        want = 2.0 * np.sum(np.log1p(np.exp(n * lt + k * lb)) - np.log1p(np.exp(n * lt + (k - 1) * lb)))
+        assert out["lnS"][k - 1].real == pytest.approx(want, rel=1e-12, abs=1e-13), k
+        assert abs(std["lnS"][k - 1].real - want) > 1e-6          # the two constraints differ
+    g = 1.0 / (1.0 + np.exp(n * lb))                            # G at tau = beta: (I + B^n)^-1
+    assert np.allclose(np.diagonal(out["G"]), g, rtol=1e-12)
+    assert np.allclose(out["G"], std["G"], rtol=1e-12, atol=1e-14)
+
+
+def test_modified_overlap_ratios_telescope():
+    """On an interacting path the per-slice ratios of eq. ztfix multiply to
+    tr(B_T^n R_n) / tr(B_T^n) = det(I + B_T^n R_n)^2 / det(I + B_T^n)^2."""
+    s = ueg.UEGSystem(14, 1.0, 0.5, 2, 0.05, stab_every=5)
+    z = si.walker_fields(31, 0, s.n_slices, s.NQ)
+    out = path.run_walker(s, z, modified=True)
+    total = np.sum(out["lnS"])
+    _, l_end = path.greens_at(s, out["right"], s.n_slices, s.n_slices)
+    _, l_0 = path.greens_at(s, path.RightBlock(s.M), 0, s.n_slices)
+    want = 2.0 * (l_end - l_0)
+    assert abs(total.real - want.real) < 1e-10 * max(1.0, abs(want.real))
+    d = np.mod(total.imag - want.imag + np.pi, 2 * np.pi) - np.pi
+    assert abs(d) < 1e-10
