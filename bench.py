@@ -111,6 +111,11 @@ def run_precision(F, torch, systems, fields, steps, warmup):
     ws = sum(inf["n_walkers"] * inf["n_slices"] for inf in infos)
     out = {"seconds": t1 - t0, "walker_slices_per_s": ws * steps / (t1 - t0),
            "ms_per_step": 1e3 * (t1 - t0) / steps}
+    if n_sys > 1:
+        # each system's share of the last timed path (events on its own streams)
+        sys_ms = ctx.system_times()
+        out["system_ms"] = sys_ms
+        out["system_ms_sum_over_wall"] = sum(sys_ms) / out["ms_per_step"]
     # the roofline's kernel: events on the library's stream around every propagator GEMM launch
     ctx.profile(True, classes=["gemm"])
     t2 = time.perf_counter()
@@ -216,6 +221,15 @@ def bench_workload(F, torch, workload, precs, steps, warmup, overlap=False):
         torch.cuda.empty_cache()
     if "fp64" in energies and "mixed" in energies:
         results["mixed_vs_fp64"] = mixed_vs_fp64(energies["fp64"], energies["mixed"])
+    if len(wl["systems"]) > 1 and "mixed" in results:
+        # the same batch with the systems one after another on the caller's stream
+        os.environ["FTAFQMC_SERIAL_SYSTEMS"] = "1"
+        systems = [dict(sd, precision=1) for sd in wl["systems"]]
+        ctx, ser, _ = run_precision(F, torch, systems, fields, steps, warmup)
+        ctx.close()
+        del os.environ["FTAFQMC_SERIAL_SYSTEMS"]
+        results["mixed"]["serial_systems_walker_slices_per_s"] = ser["walker_slices_per_s"]
+        results["mixed"]["serial_systems_ms"] = ser["system_ms"]
     return results, fields
 
 
@@ -381,6 +395,9 @@ def main():
                 "ms_per_step": {p: res[p]["ms_per_step"] for p in ("fp64", "mixed")},
                 "gemm_roofline_frac": {p: res[p]["gemm_roofline_frac"] for p in ("fp64", "mixed")},
                 "gemm_avg_ms": {p: res[p]["gemm_avg_ms"] for p in ("fp64", "mixed")},
+                "system_ms": {p: res[p].get("system_ms") for p in ("fp64", "mixed")},
+                "system_ms_sum_over_wall": {p: res[p].get("system_ms_sum_over_wall") for p in ("fp64", "mixed")},
+                "serial_systems_walker_slices_per_s": res["mixed"].get("serial_systems_walker_slices_per_s"),
                 "profile_ms_per_step": {p: res[p]["profile_ms_per_step"] for p in ("fp64", "mixed")},
                 "mixed_vs_fp64": res["mixed_vs_fp64"]}
             print("workload %s done" % name, file=sys.stderr, flush=True)

@@ -81,7 +81,7 @@ typedef struct {
   double kscale;   /* lambda in H_1 = lambda T + h (1 = the physical Hamiltonian) */
   int precision;   /* FTAFQMC_FP64 or FTAFQMC_MIXED */
   int flags;       /* 0, or any of FTAFQMC_CHECKPOINT, FTAFQMC_OVERLAP, FTAFQMC_GRAPH,
-                      FTAFQMC_TRIAL_THF */
+                      FTAFQMC_TRIAL_THF, FTAFQMC_MODIFIED_OVERLAP, FTAFQMC_MEASURE_EVERY_SLICE */
 } ftafqmc_params;
 
 /* flags: record the sampled path (the shifted coefficients c_Q and tr G of every slice) so
@@ -104,6 +104,16 @@ typedef struct {
  * 2 sum f = N (plane waves stay Hartree-Fock orbitals of the uniform gas; the Q = 0 Hartree term
  * cancels against the background).  mu_T (and the default mu) become this trial's. */
 #define FTAFQMC_TRIAL_THF 8
+/* flags: the phaseless constraint from the modified overlap ratio of eq. ztfix,
+ * S~_k = tr(B_T^n B_k ... B_1) / tr(B_T^n B_{k-1} ... B_1): the trial always enters to the n-th
+ * power, so the force bias, ln det, S and theta of every slice use (I + B_T^n R_k)^{-1}; the
+ * estimators (ftafqmc_energy, ftafqmc_greens, the records) keep G_k = (I + B_T^{n-k} R_k)^{-1},
+ * formed at records and after the last slice of each ftafqmc_propagate call (one more
+ * elimination there).  Not with FTAFQMC_CHECKPOINT. */
+#define FTAFQMC_MODIFIED_OVERLAP 16
+/* flags: an energy record after every slice (for time-slice averages, ftafqmc_record_stats)
+ * instead of every stab_every slices; stabilisation keeps its own interval. */
+#define FTAFQMC_MEASURE_EVERY_SLICE 32
 /* ftafqmc_backward modes */
 #define FTAFQMC_FROZEN_PATH 0
 
@@ -240,6 +250,62 @@ int ftafqmc_population_control(ftafqmc_t h, int sys, int method, const double* d
  * d_average: device double [3] or NULL: the average over the records with live walkers of
  *   Re<E> and of Re<N>, and the number of such records. */
 int ftafqmc_record_stats(ftafqmc_t h, int sys, double* d_stats, double* d_average, void* stream);
+
+/* Density correlation <rho(Q) rho(-Q)> of system `sys` from every walker's current G, for every
+ * momentum transfer Q (both spins); divided by N it is the static structure factor
+ * S(Q) = <rho(Q) rho(-Q)> / N of Sec. "Results".  Per walker, by Wick's theorem with
+ * P = I - G^T: 4 r_Q r_-Q + 2 (n_Q - Lambda_Q), with r_Q = sum_K P_{K+Q,K},
+ * n_Q = sum_{K, K+Q in basis} P_{K+Q,K+Q} and the exchange sum Lambda_Q of the local energy.
+ * d_walker: device complex128 [W][N_Q] or NULL; d_mean: device complex128 [N_Q] or NULL, the
+ * weighted mean over live walkers (NaN if none).  Q order as ftafqmc_qvectors.  Uses internal
+ * scratch that ftafqmc_propagate also uses: call it between propagations. */
+int ftafqmc_density_correlation(ftafqmc_t h, int sys, void* d_walker, void* d_mean, void* stream);
+
+/* The momentum transfers of system `sys` as integer vectors n (Q = 2 pi n / L), host int
+ * [N_Q][3], in the library's Q order (sorted by |n|^2, then n_x, n_y, n_z). */
+int ftafqmc_qvectors(ftafqmc_t h, int sys, int* h_qvec);
+
+/* Set the interacting chemical potential of system `sys` (it enters only the half-step factors
+ * exp(-dtau/2 (lambda eps + h - mu)) of eq. B) and put the system back at tau = 0. */
+int ftafqmc_set_mu(ftafqmc_t h, int sys, double mu, void* stream);
+
+/* Tune mu of system `sys` so that the ensemble's <N> at tau = beta matches n_target (Sec.
+ * "Computational Details").  Every run is the whole path of every walker on the same fields
+ * d_fields (device complex128 [W][n][N_Q], common random numbers); <N> is the weighted mean of
+ * Re N over live walkers and its standard error is that of ftafqmc_record_stats.  Starting from
+ * the system's current mu:
+ *   FTAFQMC_MU_BRACKET_FIT: the paper's procedure.  Steps of 0.05 scale (doubled) until <N> - n
+ *     changes sign, bisection until the bracket is below 1% of scale = max(|mu|, 1/beta), mu~
+ *     its midpoint; five runs at mu~ + scale {-0.025, -0.0125, 0, 0.0125, 0.025}; a straight line
+ *     N = a + b mu by least squares with weights 1/sigma^2 (equal weights if a sigma is 0);
+ *     mu* = (n_target - a) / b.
+ *   FTAFQMC_MU_NEWTON: mu <- mu - (<N> - n_target) / (d<N>/dmu) with the frozen-path derivative
+ *     of ftafqmc_backward (the system needs FTAFQMC_CHECKPOINT) until |<N> - n_target| <=
+ *     tol n_target.
+ * h_trace: host double [max_runs][4] or NULL: mu, <N>, its standard error, d<N>/dmu (0 when not
+ * taken) of every run.  The system is left at the tuned mu and reset to tau = 0.  Synchronises
+ * the stream after every run.  Errors: E_NUMERIC when max_runs runs do not suffice or no walker
+ * survives a run; E_STATE for Newton without FTAFQMC_CHECKPOINT or on a handle with a captured
+ * graph or profiling on. */
+#define FTAFQMC_MU_BRACKET_FIT 0
+#define FTAFQMC_MU_NEWTON 1
+typedef struct {
+  double mu;        /* the tuned chemical potential */
+  double mu_tilde;  /* bracketing: midpoint of the 1% bracket; Newton: the tuned mu */
+  double n_mean;    /* <N> of the last run and its standard error */
+  double n_stderr;
+  int runs;         /* whole-path runs made */
+} ftafqmc_mu_result;
+int ftafqmc_tune_mu(ftafqmc_t h, int sys, const void* d_fields, int method, double n_target, double tol,
+                    int max_runs, double* h_trace, ftafqmc_mu_result* out, void* stream);
+
+/* Wall time in milliseconds of each system's share of the last eager ftafqmc_propagate call
+ * (h_ms: host double [n_sys]), from events on the system's first stream before its first slice
+ * and after its last.  The systems of a handle run concurrently, each on streams of its own (the
+ * caller's stream and side streams the handle owns, default priority), enqueued slice by slice
+ * in order of decreasing per-slice work M^3 W; their sum over the call's wall time says how
+ * much they overlapped.  E_STATE before any eager call (graph replays record no times). */
+int ftafqmc_system_times(ftafqmc_t h, double* h_ms);
 
 /* Kernel-class timing with HIP events recorded on the caller's stream around every
  * launch (instrumentation).  enable = 1 starts recording every class;

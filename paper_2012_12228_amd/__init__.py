@@ -23,13 +23,18 @@ FTAFQMC_CHECKPOINT = 1     # params flag: record the path for ftafqmc_backward
 FTAFQMC_OVERLAP = 2        # params flag: two walker groups on two streams
 FTAFQMC_GRAPH = 4          # params flag: replay whole-path propagation from a captured HIP graph
 FTAFQMC_TRIAL_THF = 8      # params flag: thermal Hartree-Fock trial instead of the free-electron one
+FTAFQMC_MODIFIED_OVERLAP = 16     # params flag: constraint from the modified overlap ratio (eq. ztfix)
+FTAFQMC_MEASURE_EVERY_SLICE = 32  # params flag: an energy record after every slice
 FTAFQMC_PROFILE_ONLY = 256  # ftafqmc_profile: record only the classes in the low bits
 FROZEN_PATH = 0            # ftafqmc_backward mode
 POP_COMB, POP_PAIR_BRANCH = 0, 1   # ftafqmc_population_control methods
+MU_BRACKET_FIT, MU_NEWTON = 0, 1   # ftafqmc_tune_mu methods
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NUMERIC", -4: "E_STATE", -5: "E_UNSUPPORTED"}
 
 ABI_SYMBOLS = ["ftafqmc_workspace_bytes", "ftafqmc_init_ueg", "ftafqmc_query", "ftafqmc_reset", "ftafqmc_propagate", "ftafqmc_greens", "ftafqmc_energy", "ftafqmc_records",
-               "ftafqmc_backward", "ftafqmc_population_control", "ftafqmc_record_stats", "ftafqmc_profile",
+               "ftafqmc_backward", "ftafqmc_population_control", "ftafqmc_record_stats",
+               "ftafqmc_density_correlation", "ftafqmc_qvectors", "ftafqmc_set_mu", "ftafqmc_tune_mu",
+               "ftafqmc_system_times", "ftafqmc_profile",
                "ftafqmc_last_error", "ftafqmc_destroy"]
 PROF_CLASSES = ["gemm", "elim", "greens_transpose", "weight_forcebias", "coef_gather", "stabilise", "energy",
                 "backward"]
@@ -52,6 +57,11 @@ class Info(ctypes.Structure):
                 ("gemm_tile_shapes", ctypes.c_int), ("walker_groups", ctypes.c_int),
                 ("gemm_tile_epilogue", ctypes.c_int), ("gemm_tile_horner", ctypes.c_int),
                 ("taylor_degree", ctypes.c_int), ("refactor_every", ctypes.c_int)]
+
+
+class MuResult(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("mu_tilde", ctypes.c_double), ("n_mean", ctypes.c_double),
+                ("n_stderr", ctypes.c_double), ("runs", ctypes.c_int)]
 
 
 _lib_handle = None
@@ -77,6 +87,12 @@ def load_library():
     lib.ftafqmc_backward.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp]
     lib.ftafqmc_population_control.argtypes = [vp, ip, ip, vp, vp, vp]
     lib.ftafqmc_record_stats.argtypes = [vp, ip, vp, vp, vp]
+    lib.ftafqmc_density_correlation.argtypes = [vp, ip, vp, vp, vp]
+    lib.ftafqmc_qvectors.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
+    lib.ftafqmc_set_mu.argtypes = [vp, ip, ctypes.c_double, vp]
+    lib.ftafqmc_system_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.ftafqmc_tune_mu.argtypes = [vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(MuResult), vp]
     lib.ftafqmc_profile.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
     lib.ftafqmc_last_error.argtypes = [vp]
     lib.ftafqmc_last_error.restype = ctypes.c_char_p
@@ -189,6 +205,36 @@ def ftafqmc_population_control(handle, sys, method, uniforms, parent, device):
 
 def ftafqmc_record_stats(handle, sys, stats, average, device):
     _check(load_library().ftafqmc_record_stats(handle, sys, _ptr(stats), _ptr(average), _stream(device)), handle)
+
+
+def ftafqmc_density_correlation(handle, sys, walker, mean, device):
+    _check(load_library().ftafqmc_density_correlation(handle, sys, _ptr(walker), _ptr(mean), _stream(device)), handle)
+
+
+def ftafqmc_qvectors(handle, sys, n_q):
+    buf = (ctypes.c_int * (3 * n_q))()
+    _check(load_library().ftafqmc_qvectors(handle, sys, buf), handle)
+    return [tuple(buf[3 * q:3 * q + 3]) for q in range(n_q)]
+
+
+def ftafqmc_system_times(handle, n_sys):
+    ms = (ctypes.c_double * n_sys)()
+    _check(load_library().ftafqmc_system_times(handle, ms), handle)
+    return list(ms)
+
+
+def ftafqmc_set_mu(handle, sys, mu, device):
+    _check(load_library().ftafqmc_set_mu(handle, sys, float(mu), _stream(device)), handle)
+
+
+def ftafqmc_tune_mu(handle, sys, fields, method, n_target, tol, max_runs, device):
+    trace = (ctypes.c_double * (4 * max_runs))()
+    res = MuResult()
+    _check(load_library().ftafqmc_tune_mu(handle, sys, _ptr(fields), method, float(n_target), float(tol), int(max_runs),
+                                          trace, ctypes.byref(res), _stream(device)), handle)
+    out = {f: getattr(res, f) for f, _ in MuResult._fields_}
+    out["trace"] = [tuple(trace[4 * i:4 * i + 4]) for i in range(res.runs)]
+    return out
 
 
 def ftafqmc_profile(handle, enable, classes=None):
@@ -307,6 +353,34 @@ class Context:
         avg = torch.empty(3, dtype=torch.float64, device=self.device)
         ftafqmc_record_stats(self.handle, sys, stats, avg, self.device)
         return stats[:n], avg
+
+    def density_correlation(self, sys=0):
+        """<rho(Q) rho(-Q)> per walker [W][N_Q] and its weighted mean [N_Q] (complex128); the
+        static structure factor is this over N."""
+        inf = self.infos[sys]
+        walker = torch.empty((inf["n_walkers"], inf["n_q"]), dtype=torch.complex128, device=self.device)
+        mean = torch.empty(inf["n_q"], dtype=torch.complex128, device=self.device)
+        ftafqmc_density_correlation(self.handle, sys, walker, mean, self.device)
+        return walker, mean
+
+    def system_times(self):
+        """Milliseconds of each system's share of the last eager propagate call."""
+        return ftafqmc_system_times(self.handle, len(self.systems))
+
+    def set_mu(self, mu, sys=0):
+        ftafqmc_set_mu(self.handle, sys, mu, self.device)
+        self.infos[sys] = self.info(sys)
+
+    def tune_mu(self, fields, method=MU_BRACKET_FIT, n_target=None, tol=1e-8, max_runs=60, sys=0):
+        """Tune mu so that <N> at tau = beta matches n_target (default: the system's N)."""
+        if n_target is None:
+            n_target = self.systems[sys]["n_elec"]
+        out = ftafqmc_tune_mu(self.handle, sys, fields, method, n_target, tol, max_runs, self.device)
+        self.infos[sys] = self.info(sys)
+        return out
+
+    def qvectors(self, sys=0):
+        return ftafqmc_qvectors(self.handle, sys, self.infos[sys]["n_q"])
 
     def profile(self, enable, classes=None):
         return ftafqmc_profile(self.handle, enable, classes)

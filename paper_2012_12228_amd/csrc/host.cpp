@@ -73,6 +73,11 @@ struct HostSys {
   int M2 = 0, ld2 = 0;                  // doubled system of the derivative
   TanDev tan;
   int taylor_nb = 4;                    // Paterson-Stockmeyer blocks of 4: degree 4 taylor_nb
+  bool modified = false;                // constraint from the modified overlap ratio (eq. ztfix)
+  bool every = false;                   // energy record after every slice
+  double* small = nullptr;              // [32] device doubles for host-driven loops (mu tuning)
+  int lane0 = 0;                        // first stream lane of this system (its groups follow)
+  hipEvent_t t0 = nullptr, t1 = nullptr;  // start and end of its share of the last eager propagate call
   int stab_cap = 1;                     // re-factorise at least every stab_cap slices
 };
 
@@ -88,7 +93,13 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
   if (p.n_walkers < 1) return "n_walkers must be >= 1";
   if (p.precision != FTAFQMC_FP64 && p.precision != FTAFQMC_MIXED) return "unknown precision";
   if (!std::isfinite(p.kscale)) return "kscale must be finite";
-  if (p.flags & ~(FTAFQMC_CHECKPOINT | FTAFQMC_OVERLAP | FTAFQMC_GRAPH | FTAFQMC_TRIAL_THF)) return "unknown flags";
+  if (p.flags & ~(FTAFQMC_CHECKPOINT | FTAFQMC_OVERLAP | FTAFQMC_GRAPH | FTAFQMC_TRIAL_THF | FTAFQMC_MODIFIED_OVERLAP |
+                  FTAFQMC_MEASURE_EVERY_SLICE))
+    return "unknown flags";
+  s.modified = (p.flags & FTAFQMC_MODIFIED_OVERLAP) != 0;
+  s.every = (p.flags & FTAFQMC_MEASURE_EVERY_SLICE) != 0;
+  if (s.modified && (p.flags & FTAFQMC_CHECKPOINT))
+    return "the frozen-path derivative is built for the standard overlap ratio only";
   s.groups = (p.flags & FTAFQMC_OVERLAP) ? 2 : 1;
   s.ckpt = (p.flags & FTAFQMC_CHECKPOINT) != 0;
   if (s.ckpt && p.precision != FTAFQMC_FP64) return "the path record for derivatives needs FP64 propagation";
@@ -247,7 +258,7 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
     s.flat[i] = v[0] * s.gdim * s.gdim + v[1] * s.gdim + v[2];
     s.grid[(size_t)(s.flat[i] + s.gc0)] = (short)i;
   }
-  s.nrec_max = s.n / p.stab_every + 2;
+  s.nrec_max = (p.flags & FTAFQMC_MEASURE_EVERY_SLICE) ? s.n + 1 : s.n / p.stab_every + 2;
   // A-priori size of V = sqrt(dtau) (x - xbar).v: an entry V_ij = i s_Q (z_Q + conj z_-Q) has
   // E|V_ij|^2 = 4 s_Q^2 for unit Gaussian fields, and the norm of such a random matrix is about
   // twice the root of its largest column variance.
@@ -322,6 +333,8 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.piv = (int*)take(sizeof(int) * ld * W);
   d.tri = (double2*)take(sizeof(double2) * elim_tri_elems(M) * W);
   d.r = (double2*)take(sizeof(double2) * (size_t)NQ * W);
+  d.rb = s.modified ? (double2*)take(sizeof(double2) * (size_t)NQ * W) : d.r;
+  d.Gt = s.modified ? (double2*)take(sizeof(double2) * mat * W) : d.G;
   d.cq = (double2*)take(sizeof(double2) * (size_t)NQ * W);
   d.expo = (double2*)take(sizeof(double2) * W);
   d.ell = (double2*)take(sizeof(double2) * W);
@@ -340,6 +353,7 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.tnorm = (double*)take(sizeof(double) * 16 * (size_t)W);
   d.pop_parent = (int*)take(sizeof(int) * (size_t)W);
   d.pop_logw = (double*)take(sizeof(double) * (size_t)W);
+  s.small = (double*)take(sizeof(double) * 32);   // statistics of one record, a Jacobian
   s.mean = (double2*)take(sizeof(double2) * 4);
   d.rec_c = nullptr;
   d.rec_trG = nullptr;
@@ -423,6 +437,8 @@ SysDev walker_view(const HostSys& s, int w0, int nw) {
   v.D += w * ld; v.Dpi += w * ld; v.perm += w * ld; v.piv += w * ld;
   v.tri += w * (long long)elim_tri_elems(s.M);
   v.r += w * s.NQ;
+  v.rb += w * s.NQ;
+  v.Gt += w * mat;
   v.cq += w * s.NQ;
   v.expo += w; v.ell += w; v.lndetT += w; v.lndetX += w; v.logw += w; v.status += w;
   v.slice_lnS += w * s.n; v.slice_theta += w * s.n;
@@ -446,10 +462,15 @@ struct ftafqmc_ctx {
   bool prof = false;
   unsigned prof_mask = 0;                 // classes recorded while prof is set
   std::vector<ProfEvent> events;
-  int groups = 1;                       // streams in use: the caller's and groups - 1 side streams
+  // Stream lanes: lane 0 is the caller's stream, lane L > 0 the handle's side stream side[L-1]
+  // (default priority).  System i uses lanes lane0_i .. lane0_i + groups_i - 1: its own lanes when
+  // the systems run concurrently, lane 0 and up for all of them when they run one after another.
+  int lanes = 1;
   static constexpr int MAX_GROUPS = 4;
-  hipStream_t side[MAX_GROUPS - 1] = {}; // streams of groups 1.. (default priority)
-  hipEvent_t fork = nullptr, join[MAX_GROUPS - 1] = {};
+  static constexpr int MAX_LANES = 16;
+  hipStream_t side[MAX_LANES - 1] = {};
+  hipEvent_t fork = nullptr, join[MAX_LANES - 1] = {};
+  bool times_valid = false;             // per-system events of the last propagate call were recorded
   // FTAFQMC_GRAPH: the launch sequence of a whole path, captured once and replayed
   bool graph = false;
   hipStream_t cap = nullptr;            // capture stream (the caller's may be the legacy default stream)
@@ -483,9 +504,9 @@ template <typename F> hipError_t timed(ftafqmc_ctx* h, int cls, hipStream_t st, 
   return e;
 }
 
-double sum_ln_lb(const HostSys& s, int k) {
+double sum_ln_lb(const HostSys& s, int lexp) {
   double a = 0.0;
-  for (int i = 0; i < s.M; ++i) a += -std::max(0.0, (double)(s.n - k) * s.lnbt[i]);
+  for (int i = 0; i < s.M; ++i) a += -std::max(0.0, (double)lexp * s.lnbt[i]);
   return a;
 }
 
@@ -586,17 +607,41 @@ int stabilise(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st) {
   return FTAFQMC_OK;
 }
 
-// G_k, ln det(I + A_k), the weight update of the slice that ended at k, r_Q of G_k.
-int greens(ftafqmc_ctx* h, HostSys& s, SysDev& d, int k, int init, hipStream_t st) {
-  HIPCHK(timed(h, FTAFQMC_PROF_GREENS, st, [&] { return launch_greens_form(d, k, st); }));
+// (I + B_T^lexp R)^{-1} into d.G with ln det X of the eliminated block (Sec. "Numerical Stabilization").
+int greens_solve(ftafqmc_ctx* h, HostSys& s, SysDev& d, int lexp, hipStream_t st) {
+  HIPCHK(timed(h, FTAFQMC_PROF_GREENS, st, [&] { return launch_greens_form(d, lexp, st); }));
   ElimParams e;
   e.aug = d.aug; e.stride = d.aug_stride; e.lda = 2 * s.ld; e.M = s.M; e.rhs_off = s.ld; e.nrhs = s.M;
   e.W = d.W; e.pivot = 1; e.backsub = 1; e.lndet = d.lndetX; e.status = d.status;
   e.piv = d.piv; e.ld = s.ld; e.tri = d.tri;
   HIPCHK(timed(h, FTAFQMC_PROF_ELIM, st, [&] { return launch_elim(e, st); }));
-  HIPCHK(timed(h, FTAFQMC_PROF_GREENS, st, [&] { return launch_greens_post(d, k, st); }));
-  const double slb = sum_ln_lb(s, k);
-  HIPCHK(timed(h, FTAFQMC_PROF_WEIGHT, st, [&] { return launch_weight(d, k, slb, init, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_GREENS, st, [&] { return launch_greens_post(d, lexp, st); }));
+  return FTAFQMC_OK;
+}
+
+// The constraint's G, ln det(I + A_k) and the weight update of the slice that ended at k, with
+// r_Q for the next force bias; A_k = B_T^{n-k} R_k (eq. Abrenda), or B_T^n R_k for the modified
+// overlap ratio (eq. ztfix), whose constraint G lives in Gt.  With `measure` (or the standard
+// ratio, where the two coincide) also G_k = (I + B_T^{n-k} R_k)^{-1} and its r_Q for the estimators.
+int greens(ftafqmc_ctx* h, HostSys& s, SysDev& d, int k, int init, bool measure, hipStream_t st) {
+  if (!s.modified) {
+    int rc = greens_solve(h, s, d, s.n - k, st);
+    if (rc) return rc;
+    const double slb = sum_ln_lb(s, s.n - k);
+    HIPCHK(timed(h, FTAFQMC_PROF_WEIGHT, st, [&] { return launch_weight(d, k, slb, init, st); }));
+    return FTAFQMC_OK;
+  }
+  SysDev cv = d;
+  cv.G = d.Gt;
+  cv.r = d.rb;
+  int rc = greens_solve(h, s, cv, s.n, st);
+  if (rc) return rc;
+  const double slb = sum_ln_lb(s, s.n);
+  HIPCHK(timed(h, FTAFQMC_PROF_WEIGHT, st, [&] { return launch_weight(cv, k, slb, init, st); }));
+  if (!measure) return FTAFQMC_OK;
+  rc = greens_solve(h, s, d, s.n - k, st);
+  if (rc) return rc;
+  HIPCHK(timed(h, FTAFQMC_PROF_WEIGHT, st, [&] { return launch_rq(d, st); }));
   return FTAFQMC_OK;
 }
 
@@ -680,7 +725,7 @@ int reset_sys(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   s.dev.Y = s.Y0;                       // every path starts from the same buffers (graph replay)
   s.dev.Ynew = s.Ynew0;
   HIPCHK(launch_init_state(s.dev, st));
-  int rc = greens(h, s, s.dev, 0, 1, st);
+  int rc = greens(h, s, s.dev, 0, 1, true, st);
   if (rc) return rc;
   s.k = 0;
   s.nrec = 0;
@@ -689,15 +734,16 @@ int reset_sys(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
 }
 
 // One slice k -> k+1 for the walkers of view d (fields of those walkers), on stream st.
-// rec >= 0: energy record number rec after the slice; refac: re-factorise the product.
+// rec >= 0: energy record number rec after the slice; refac: re-factorise the product;
+// last: the last slice of this propagate call (the estimators' G must be current after it).
 int slice_step(ftafqmc_ctx* h, HostSys& s, SysDev& d, const double2* fields, int k, int rec, bool refac,
-               hipStream_t st) {
+               bool last, hipStream_t st) {
   const int mixed = s.p.precision == FTAFQMC_MIXED;
   HIPCHK(timed(h, FTAFQMC_PROF_COEF, st, [&] { return launch_coef_v(d, fields, k, mixed, st); }));
   int rc = apply_propagator(h, s, d, st);
   if (rc) return rc;
   if (refac) { rc = stabilise(h, s, d, st); if (rc) return rc; }
-  rc = greens(h, s, d, k + 1, 0, st);
+  rc = greens(h, s, d, k + 1, 0, rec >= 0 || last, st);
   if (rc) return rc;
   if (rec >= 0) HIPCHK(timed(h, FTAFQMC_PROF_ENERGY, st, [&] { return launch_energy(d, rec, st); }));
   return FTAFQMC_OK;
@@ -707,21 +753,23 @@ int slice_step(ftafqmc_ctx* h, HostSys& s, SysDev& d, const double2* fields, int
 // caller's stream and the handle's side stream: the elimination of one group is latency bound
 // (a workgroup per walker walks its pivot columns one by one) and overlaps with the GEMMs of the
 // other.  Walkers are independent, so the results do not depend on the split.
-int step(ftafqmc_ctx* h, HostSys& s, std::vector<SysDev>& views, const double2* fields, hipStream_t st) {
+int step(ftafqmc_ctx* h, HostSys& s, std::vector<SysDev>& views, const double2* fields, bool last, hipStream_t st) {
   const int k = s.k;
   const bool boundary = ((k + 1) % s.p.stab_every == 0) || (k + 1 == s.n);
-  const int rec = boundary ? s.nrec : -1;
+  const bool record = boundary || s.every;
+  const int rec = record ? s.nrec : -1;
   // records at the caller's stabilisation interval; extra re-factorisations where the kinetic
   // range of the product would make one Cholesky-QR pass lose orthogonality
   const bool refac = boundary || ((k + 1) % s.stab_cap == 0);
   for (size_t g = 0; g < views.size(); ++g) {
     SysDev& d = views[g];
     const double2* f = fields + (long long)d.w_off * s.n * s.NQ;
-    int rc = slice_step(h, s, d, f, k, rec, refac, g == 0 ? st : h->side[g - 1]);
+    const int lane = s.lane0 + (int)g;
+    int rc = slice_step(h, s, d, f, k, rec, refac, last || k + 1 == s.n, lane == 0 ? st : h->side[lane - 1]);
     if (rc) return rc;
   }
   std::swap(s.dev.Y, s.dev.Ynew);           // every view swapped its own pointers once
-  if (boundary) {
+  if (record) {
     s.rec_slice.push_back(k + 1);
     ++s.nrec;
   }
@@ -854,30 +902,105 @@ int backward(ftafqmc_ctx* h, HostSys& s, const double* cot, double2* jac, double
   return FTAFQMC_OK;
 }
 
+hipStream_t lane_stream(ftafqmc_ctx* h, hipStream_t st, int lane) { return lane == 0 ? st : h->side[lane - 1]; }
+
 // The launch sequence of ftafqmc_propagate for n_slices slices (eager, or under graph capture).
-int run_slices(ftafqmc_ctx* h, const void* const* d_fields, int n_slices, hipStream_t st) {
+// Each system runs on its own lanes: the side lanes start after the work already queued on the
+// caller's stream and the caller's stream continues after all of them (fork / join).  Within a
+// slice round the systems are enqueued in order of decreasing per-slice work (M^3 W), so that
+// the longest paths start first; a system that has reached its n slices drops out.
+int run_slices(ftafqmc_ctx* h, const void* const* d_fields, int n_slices, hipStream_t st, bool capture) {
   std::vector<std::vector<SysDev>> views;
   for (auto& s : h->sys) views.push_back(make_views(s, s.groups));
-  // the side stream starts after the work already queued on the caller's stream, and the
-  // caller's stream continues only after the side stream's work (fork / join)
+  std::vector<int> order(h->sys.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  auto work = [&](int i) { const HostSys& s = h->sys[i]; return (double)s.M * s.M * s.M * s.p.n_walkers; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
   HIPCHK(hipEventRecord(h->fork, st));
-  for (int g = 0; g + 1 < h->groups; ++g) HIPCHK(hipStreamWaitEvent(h->side[g], h->fork, 0));
+  for (int l = 1; l < h->lanes; ++l) HIPCHK(hipStreamWaitEvent(h->side[l - 1], h->fork, 0));
+  const bool timing = !capture;
+  std::vector<char> started(h->sys.size(), 0);
   int rc = FTAFQMC_OK;
   for (int j = 0; j < n_slices && rc == FTAFQMC_OK; ++j) {
     bool any = false;
-    for (size_t i = 0; i < h->sys.size() && rc == FTAFQMC_OK; ++i) {
+    for (int i : order) {
       HostSys& s = h->sys[i];
       if (s.k >= s.n) continue;
       any = true;
-      rc = step(h, s, views[i], (const double2*)d_fields[i], st);
+      const hipStream_t s0 = lane_stream(h, st, s.lane0);
+      if (timing && !started[i]) { HIPCHK(hipEventRecord(s.t0, s0)); started[i] = 1; }
+      const bool last = j + 1 == n_slices || s.k + 1 == s.n;
+      rc = step(h, s, views[i], (const double2*)d_fields[i], last, st);
+      if (rc) break;
+      if (last) {                        // the system's share of this call ends: join its groups
+        for (size_t g = 1; g < views[i].size(); ++g) {
+          const int l = s.lane0 + (int)g;
+          HIPCHK(hipEventRecord(h->join[l - 1], h->side[l - 1]));
+          HIPCHK(hipStreamWaitEvent(s0, h->join[l - 1], 0));
+        }
+        if (timing) HIPCHK(hipEventRecord(s.t1, s0));
+      }
     }
     if (!any) break;
   }
-  for (int g = 0; g + 1 < h->groups; ++g) {
-    HIPCHK(hipEventRecord(h->join[g], h->side[g]));
-    HIPCHK(hipStreamWaitEvent(st, h->join[g], 0));
+  for (int l = 1; l < h->lanes; ++l) {
+    HIPCHK(hipEventRecord(h->join[l - 1], h->side[l - 1]));
+    HIPCHK(hipStreamWaitEvent(st, h->join[l - 1], 0));
   }
+  bool all = true;
+  for (size_t i = 0; i < h->sys.size(); ++i) all = all && started[i];
+  h->times_valid = timing && all && rc == FTAFQMC_OK;
   return rc;
+}
+
+// mu enters only the half-step factors K = exp(-dtau/2 (lambda eps + h - mu)) (eq. B).
+int set_mu(ftafqmc_ctx* h, HostSys& s, double mu, hipStream_t st) {
+  s.mu = mu;
+  for (int i = 0; i < s.M; ++i) s.kh[i] = std::exp(-0.5 * s.dtau * (s.p.kscale * s.eps[i] + s.hK[i] - s.mu));
+  HIPCHK(hipMemcpyAsync((void*)s.dev.kh, s.kh.data(), sizeof(double) * s.ld, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));          // the host vector may change again before a later copy
+  return FTAFQMC_OK;
+}
+
+// One whole path of system s at chemical potential mu on its fields: Re<N> at tau = beta, its
+// standard error over the walkers, and with `deriv` the frozen-path d Re<N> / dmu.
+int mu_run(ftafqmc_ctx* h, HostSys& s, const double2* fields, double mu, bool deriv, double* n, double* err,
+           double* dn, hipStream_t st) {
+  int rc = set_mu(h, s, mu, st);
+  if (rc) return rc;
+  rc = reset_sys(h, s, st);
+  if (rc) return rc;
+  std::vector<SysDev> views = make_views(s, s.groups);
+  const hipStream_t s0 = lane_stream(h, st, s.lane0);
+  HIPCHK(hipEventRecord(h->fork, st));
+  for (int l = 1; l < h->lanes; ++l) HIPCHK(hipStreamWaitEvent(h->side[l - 1], h->fork, 0));
+  for (int k = 0; k < s.n && rc == FTAFQMC_OK; ++k) rc = step(h, s, views, fields, k + 1 == s.n, st);
+  for (int l = 1; l < h->lanes; ++l) {
+    HIPCHK(hipEventRecord(h->join[l - 1], h->side[l - 1]));
+    HIPCHK(hipStreamWaitEvent(st, h->join[l - 1], 0));
+  }
+  (void)s0;
+  if (rc) return rc;
+  // statistics of the last record (tau = beta): a view of that record alone
+  SysDev last = s.dev;
+  last.rec_E += (long long)(s.nrec - 1) * s.p.n_walkers * 4;
+  last.rec_logw += (long long)(s.nrec - 1) * s.p.n_walkers;
+  last.rec_status += (long long)(s.nrec - 1) * s.p.n_walkers;
+  HIPCHK(launch_record_stats(last, 1, s.small, nullptr, st));
+  double stats[8];
+  HIPCHK(hipMemcpyAsync(stats, s.small, sizeof(stats), hipMemcpyDeviceToHost, st));
+  if (deriv) {
+    rc = backward(h, s, nullptr, (double2*)(s.small + 8), nullptr, nullptr, st);
+    if (rc) return rc;
+  }
+  double jac[8] = {0};
+  if (deriv) HIPCHK(hipMemcpyAsync(jac, s.small + 8, sizeof(jac), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *n = stats[2];
+  *err = stats[3];
+  if (dn) *dn = deriv ? jac[2] : 0.0;          // Re d<N>/dmu (second complex entry)
+  if (!(stats[7] > 0.0)) return h->set(FTAFQMC_E_NUMERIC, "mu tuning: no live walker");
+  return FTAFQMC_OK;
 }
 
 int check_handle(ftafqmc_ctx* h, int sys) {
@@ -904,6 +1027,13 @@ int ftafqmc_workspace_bytes(const ftafqmc_params* p, int n_sys, size_t* bytes) {
 
 int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size_t ws_bytes, void* stream,
                      ftafqmc_t* out) {
+  return init_ueg_impl(p, n_sys, d_workspace, ws_bytes, stream, out, false);
+}
+
+}  // extern "C"
+
+int init_ueg_impl(const ftafqmc_params* p, int n_sys, void* d_workspace, size_t ws_bytes, void* stream,
+                  ftafqmc_t* out, bool no_side_streams) {
   if (!p || n_sys < 1 || !out || !d_workspace) return lib_init_error(FTAFQMC_E_ARG, "null parameters, output or workspace");
   if (((uintptr_t)d_workspace) & 255) return lib_init_error(FTAFQMC_E_ARG, "workspace not 256-byte aligned");
   ftafqmc_ctx* h = new (std::nothrow) ftafqmc_ctx();
@@ -916,17 +1046,29 @@ int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size
     off = layout(h->sys[i], nullptr, off);
   }
   if (off > ws_bytes) { delete h; return lib_init_error(FTAFQMC_E_ARG, "workspace smaller than ftafqmc_workspace_bytes"); }
-  h->groups = 1;
+  // Systems run concurrently on lanes of their own (the small systems' latency-bound kernels
+  // then overlap with the large ones'); FTAFQMC_SERIAL_SYSTEMS=1 in the environment, or the
+  // static workspace (which creates no streams), runs them one after another on lane 0 and up.
+  const char* serial_env = std::getenv("FTAFQMC_SERIAL_SYSTEMS");
+  const bool concurrent = n_sys > 1 && !no_side_streams && !(serial_env && std::atoi(serial_env) == 1);
+  h->lanes = 1;
+  int next = 0;
   for (auto& s : h->sys) {
     if (s.p.flags & FTAFQMC_GRAPH) h->graph = true;
     if (const char* env = std::getenv("FTAFQMC_WALKER_GROUPS"))   // experiments: force a group count
       s.groups = std::max(1, std::min(ftafqmc_ctx::MAX_GROUPS, std::atoi(env)));
-    h->groups = std::max(h->groups, s.groups);
+    if (no_side_streams) s.groups = 1;
+    s.lane0 = concurrent ? next : 0;
+    if (s.lane0 + s.groups > ftafqmc_ctx::MAX_LANES) s.lane0 = 0;   // more lanes than streams: share
+    next = s.lane0 + s.groups;
+    h->lanes = std::max(h->lanes, s.lane0 + s.groups);
   }
   bool ok = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) == hipSuccess;
-  for (int g = 0; ok && g + 1 < h->groups; ++g)
-    ok = hipStreamCreateWithFlags(&h->side[g], hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&h->join[g], hipEventDisableTiming) == hipSuccess;
+  for (int l = 1; ok && l < h->lanes; ++l)
+    ok = hipStreamCreateWithFlags(&h->side[l - 1], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&h->join[l - 1], hipEventDisableTiming) == hipSuccess;
+  for (auto& s : h->sys)
+    ok = ok && hipEventCreate(&s.t0) == hipSuccess && hipEventCreate(&s.t1) == hipSuccess;
   if (!ok) { ftafqmc_destroy(h); return lib_init_error(FTAFQMC_E_HIP, "event or stream creation failed"); }
   h->ws = (char*)d_workspace;
   h->ws_bytes = ws_bytes;
@@ -964,6 +1106,8 @@ int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size
   return FTAFQMC_OK;
 }
 
+extern "C" {
+
 int ftafqmc_query(ftafqmc_t h, int sys, ftafqmc_info* out) {
   int rc = check_handle(h, sys);
   if (rc) return rc;
@@ -999,14 +1143,14 @@ int ftafqmc_propagate(ftafqmc_t h, const void* const* d_fields, int n_slices, vo
   hipStream_t st = (hipStream_t)stream;
   bool whole = h->graph && !h->prof;
   for (auto& s : h->sys) whole = whole && s.k == 0 && n_slices >= s.n;
-  if (!whole) return run_slices(h, d_fields, n_slices, st);
+  if (!whole) return run_slices(h, d_fields, n_slices, st, false);
   std::vector<const void*> key(d_fields, d_fields + h->sys.size());
   if (!h->gexec || key != h->gfields) {
     if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
     if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     // record on the capture stream (nothing runs); the instantiated graph is launched on st
     HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    const int rc = run_slices(h, d_fields, n_slices, h->cap);
+    const int rc = run_slices(h, d_fields, n_slices, h->cap, true);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(h->cap, &g);
     if (rc != FTAFQMC_OK || e != hipSuccess) {
@@ -1101,6 +1245,143 @@ int ftafqmc_record_stats(ftafqmc_t h, int sys, double* d_stats, double* d_averag
   return FTAFQMC_OK;
 }
 
+int ftafqmc_density_correlation(ftafqmc_t h, int sys, void* d_walker, void* d_mean, void* stream) {
+  int rc = check_handle(h, sys);
+  if (rc) return rc;
+  HostSys& s = h->sys[sys];
+  hipStream_t st = (hipStream_t)stream;
+  // the exchange partial sums per (a, d) use E0 and the per-walker values cq (both free between
+  // propagate calls)
+  HIPCHK(launch_density_correlation(s.dev, (double2*)s.dev.E0, s.dev.cq, (double2*)d_mean, st));
+  if (d_walker)
+    HIPCHK(hipMemcpyAsync(d_walker, s.dev.cq, sizeof(double2) * (size_t)s.NQ * s.p.n_walkers, hipMemcpyDeviceToDevice, st));
+  return FTAFQMC_OK;
+}
+
+int ftafqmc_qvectors(ftafqmc_t h, int sys, int* h_qvec) {
+  int rc = check_handle(h, sys);
+  if (rc) return rc;
+  if (!h_qvec) return h->set(FTAFQMC_E_ARG, "null output");
+  const HostSys& s = h->sys[sys];
+  for (int q = 0; q < s.NQ; ++q)
+    for (int c = 0; c < 3; ++c) h_qvec[3 * q + c] = s.qvec[q][c];
+  return FTAFQMC_OK;
+}
+
+int ftafqmc_set_mu(ftafqmc_t h, int sys, double mu, void* stream) {
+  int rc = check_handle(h, sys);
+  if (rc) return rc;
+  if (!std::isfinite(mu)) return h->set(FTAFQMC_E_ARG, "mu must be finite");
+  HostSys& s = h->sys[sys];
+  rc = set_mu(h, s, mu, (hipStream_t)stream);
+  if (rc) return rc;
+  return reset_sys(h, s, (hipStream_t)stream);
+}
+
+int ftafqmc_tune_mu(ftafqmc_t h, int sys, const void* d_fields, int method, double n_target, double tol,
+                    int max_runs, double* h_trace, ftafqmc_mu_result* out, void* stream) {
+  int rc = check_handle(h, sys);
+  if (rc) return rc;
+  HostSys& s = h->sys[sys];
+  if (!d_fields || !out || max_runs < 1 || !(n_target > 0.0)) return h->set(FTAFQMC_E_ARG, "bad tuning arguments");
+  if (method != FTAFQMC_MU_BRACKET_FIT && method != FTAFQMC_MU_NEWTON) return h->set(FTAFQMC_E_ARG, "unknown method");
+  if (method == FTAFQMC_MU_NEWTON && !s.ckpt)
+    return h->set(FTAFQMC_E_STATE, "Newton steps need the derivative: initialise with FTAFQMC_CHECKPOINT");
+  if (h->gexec || h->prof) return h->set(FTAFQMC_E_STATE, "tuning runs eagerly: no graph or profiling");
+  hipStream_t st = (hipStream_t)stream;
+  const double2* f = (const double2*)d_fields;
+  int runs = 0;
+  double n = 0.0, err = 0.0, dn = 0.0;
+  auto run = [&](double mu, bool deriv) -> int {
+    if (runs >= max_runs) return h->set(FTAFQMC_E_NUMERIC, "mu tuning exceeded its run budget");
+    const int r = mu_run(h, s, f, mu, deriv, &n, &err, &dn, st);
+    if (r) return r;
+    if (h_trace) { h_trace[4 * runs] = mu; h_trace[4 * runs + 1] = n; h_trace[4 * runs + 2] = err; h_trace[4 * runs + 3] = dn; }
+    ++runs;
+    return FTAFQMC_OK;
+  };
+  const double mu0 = s.mu;
+  if (method == FTAFQMC_MU_NEWTON) {
+    double mu = mu0;
+    for (;;) {
+      rc = run(mu, true);
+      if (rc) return rc;
+      if (std::fabs(n - n_target) <= tol * n_target) break;
+      if (!(dn != 0.0) || !std::isfinite(dn)) return h->set(FTAFQMC_E_NUMERIC, "mu tuning: zero or non-finite d<N>/dmu");
+      mu = mu - (n - n_target) / dn;
+    }
+    out->mu = mu; out->mu_tilde = mu;
+  } else {
+    // bracket the root with single runs (error bars ignored) to 1% of max(|mu|, 1/beta), then a
+    // weighted least-squares line through five runs on mu~ +- 2.5% (Sec. "Computational Details")
+    const double scale0 = std::max(std::fabs(mu0), 1.0 / s.beta);
+    double step = 0.05 * scale0, a, b;
+    if ((rc = run(mu0, false))) return rc;
+    if (n < n_target) {
+      a = mu0;
+      b = a + step;
+      for (;;) {
+        if ((rc = run(b, false))) return rc;
+        if (!(n < n_target)) break;
+        a = b; step = 2.0 * step; b = a + step;
+      }
+    } else {
+      b = mu0;
+      a = b - step;
+      for (;;) {
+        if ((rc = run(a, false))) return rc;
+        if (n < n_target) break;
+        b = a; step = 2.0 * step; a = b - step;
+      }
+    }
+    while (b - a > 0.01 * std::max(std::fabs(0.5 * (a + b)), 1.0 / s.beta)) {
+      const double m = 0.5 * (a + b);
+      if ((rc = run(m, false))) return rc;
+      if (n < n_target) a = m; else b = m;
+    }
+    const double mt = 0.5 * (a + b), scale = std::max(std::fabs(mt), 1.0 / s.beta);
+    const double offs[5] = {-0.025, -0.0125, 0.0, 0.0125, 0.025};
+    double mus[5], ns[5], es[5];
+    bool pos = true;
+    for (int i = 0; i < 5; ++i) {
+      mus[i] = mt + offs[i] * scale;
+      if ((rc = run(mus[i], false))) return rc;
+      ns[i] = n; es[i] = err;
+      pos = pos && err > 0.0;
+    }
+    double S0 = 0, S1 = 0, S2 = 0, T0 = 0, T1 = 0;
+    for (int i = 0; i < 5; ++i) {
+      const double w = pos ? 1.0 / (es[i] * es[i]) : 1.0;
+      S0 += w; S1 += w * mus[i]; S2 += w * mus[i] * mus[i]; T0 += w * ns[i]; T1 += w * mus[i] * ns[i];
+    }
+    const double det = S0 * S2 - S1 * S1;
+    const double af = (S2 * T0 - S1 * T1) / det, bf = (S0 * T1 - S1 * T0) / det;
+    out->mu = (n_target - af) / bf;
+    out->mu_tilde = mt;
+  }
+  out->n_mean = n;
+  out->n_stderr = err;
+  out->runs = runs;
+  // the system is left at the tuned mu, back at tau = 0
+  rc = set_mu(h, s, out->mu, st);
+  if (rc) return rc;
+  return reset_sys(h, s, st);
+}
+
+int ftafqmc_system_times(ftafqmc_t h, double* h_ms) {
+  if (!h) return FTAFQMC_E_ARG;
+  if (!h_ms) return h->set(FTAFQMC_E_ARG, "null output");
+  if (!h->times_valid) return h->set(FTAFQMC_E_STATE, "no eager ftafqmc_propagate call has been timed");
+  for (size_t i = 0; i < h->sys.size(); ++i) {
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(h->sys[i].t1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->sys[i].t0, h->sys[i].t1);
+    if (e != hipSuccess) return h->set(FTAFQMC_E_HIP, std::string("system times: ") + hipGetErrorString(e));
+    h_ms[i] = ms;
+  }
+  return FTAFQMC_OK;
+}
+
 int ftafqmc_profile(ftafqmc_t h, int enable, double* h_ms, long long* h_count) {
   if (!h) return FTAFQMC_E_ARG;
   if (enable) {
@@ -1138,7 +1419,11 @@ const char* ftafqmc_last_error(ftafqmc_t h) { return h ? h->err.c_str() : init_e
 void ftafqmc_destroy(ftafqmc_t h) {
   if (!h) return;
   for (auto& ev : h->events) { (void)hipEventDestroy(ev.a); (void)hipEventDestroy(ev.b); }
-  for (int g = 0; g + 1 < ftafqmc_ctx::MAX_GROUPS; ++g) {
+  for (auto& s : h->sys) {
+    if (s.t0) (void)hipEventDestroy(s.t0);
+    if (s.t1) (void)hipEventDestroy(s.t1);
+  }
+  for (int g = 0; g + 1 < ftafqmc_ctx::MAX_LANES; ++g) {
     if (h->side[g]) { (void)hipStreamSynchronize(h->side[g]); (void)hipStreamDestroy(h->side[g]); }
     if (h->join[g]) (void)hipEventDestroy(h->join[g]);
   }

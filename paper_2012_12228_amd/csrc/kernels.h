@@ -75,6 +75,8 @@ struct SysDev {
   double* D; double* Dpi; int* perm; int* piv;
   double2* tri;           // [W][elim_tri_elems(M)]
   double2* r;             // [W][NQ] <rho_Q> per spin of the current G
+  double2* rb;            // [W][NQ] <rho_Q> that the force bias uses (= r, or of Gt)
+  double2* Gt;            // [W][ld][ld] G of the constraint product (= G, or the eq. ztfix one)
   double2* cq;            // [W][NQ] shifted coefficients c_Q of the current slice
   double2* expo;          // [W] weight exponent of the current slice
   double2* ell;           // [W] ln det(I + A_k)
@@ -149,8 +151,10 @@ size_t pop_select_lds(int W);
 hipError_t launch_record_stats(const SysDev& s, int nrec, double* stats, double* avg, hipStream_t st);
 hipError_t launch_init_state(const SysDev& s, hipStream_t st);
 hipError_t launch_coef_v(const SysDev& s, const double2* fields, int k, int mixed, hipStream_t st);
-hipError_t launch_greens_form(const SysDev& s, int k, hipStream_t st);
-hipError_t launch_greens_post(const SysDev& s, int k, hipStream_t st);
+// G of (I + B_T^lexp R)^{-1}: the transposed augmented system, and G from its solution
+hipError_t launch_greens_form(const SysDev& s, int lexp, hipStream_t st);
+hipError_t launch_greens_post(const SysDev& s, int lexp, hipStream_t st);
+hipError_t launch_rq(const SysDev& s, hipStream_t st);                // r_Q of s.G into s.r
 hipError_t launch_weight(const SysDev& s, int k, double sum_lnLb, int init, hipStream_t st);
 int rq_block_elems();     // complex entries of G per row block of the r_Q kernel (rows * ld at most)
 hipError_t launch_stab_perm(const SysDev& s, hipStream_t st);

@@ -117,25 +117,29 @@ __global__ __launch_bounds__(NT) void pop_select_kernel(const double* logw, cons
 }
 
 // Copy the walker state of parent[j] into slot j (j != parent[j]) and set every ln w:
-// Y, T^{-1}, G ([ld][ld] each), D [ld], r [NQ]; ln det(I + A), ln det T, status.
+// Y, T^{-1}, G ([ld][ld] each; and the constraint's G when it is a separate buffer), D [ld],
+// r [NQ] (and the force bias's r when separate); ln det(I + A), ln det T, status.
 constexpr int POP_CHUNK = 8192;
-__global__ __launch_bounds__(NT) void pop_copy_kernel(SysDev s, const int* parent, const double* newlogw, int chunks) {
+__global__ __launch_bounds__(NT) void pop_copy_kernel(SysDev s, const int* parent, const double* newlogw, int chunks,
+                                                      int nmat) {
   const int j = blockIdx.x / chunks, ch = blockIdx.x - j * chunks;
   if (j >= s.W) return;
   const int src = parent[j];
   if (ch == 0 && threadIdx.x == 0) s.logw[j] = newlogw[j];
   if (src == j) return;
   const long long mat = s.mat_stride;
-  const long long e0 = (long long)ch * POP_CHUNK, e1 = min(e0 + POP_CHUNK, 3 * mat);
+  const long long e0 = (long long)ch * POP_CHUNK, e1 = min(e0 + POP_CHUNK, nmat * mat);
   for (long long e = e0 + threadIdx.x; e < e1; e += NT) {
     const int m = (int)(e / mat);
     const long long o = e - m * mat;
-    double2* base = m == 0 ? s.Y : (m == 1 ? s.Ti : s.G);
+    double2* base = m == 0 ? s.Y : (m == 1 ? s.Ti : (m == 2 ? s.G : s.Gt));
     base[(long long)j * mat + o] = base[(long long)src * mat + o];
   }
   if (ch == chunks - 1) {
     for (int i = threadIdx.x; i < s.ld; i += NT) s.D[(long long)j * s.ld + i] = s.D[(long long)src * s.ld + i];
     for (int q = threadIdx.x; q < s.NQ; q += NT) s.r[(long long)j * s.NQ + q] = s.r[(long long)src * s.NQ + q];
+    if (s.rb != s.r)
+      for (int q = threadIdx.x; q < s.NQ; q += NT) s.rb[(long long)j * s.NQ + q] = s.rb[(long long)src * s.NQ + q];
     if (threadIdx.x == 0) {
       s.ell[j] = s.ell[src];
       s.lndetT[j] = s.lndetT[src];
@@ -208,8 +212,9 @@ hipError_t launch_population_control(const SysDev& s, int method, const double* 
   pop_select_kernel<<<1, NT, lds, st>>>(s.logw, s.status, s.W, method, u, parent, newlogw);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int chunks = (int)((3 * s.mat_stride + POP_CHUNK - 1) / POP_CHUNK);
-  pop_copy_kernel<<<s.W * chunks, NT, 0, st>>>(s, parent, newlogw, chunks);
+  const int nmat = s.Gt != s.G ? 4 : 3;
+  const int chunks = (int)((nmat * s.mat_stride + POP_CHUNK - 1) / POP_CHUNK);
+  pop_copy_kernel<<<s.W * chunks, NT, 0, st>>>(s, parent, newlogw, chunks, nmat);
   return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(NT) void coef_kernel(SysDev s, const double2* field
   const int w = blockIdx.x;
   if (w >= s.W) return;
   const double2* z = fields + ((long long)w * s.n + k) * s.NQ;
-  const double2* r = s.r + (long long)w * s.NQ;
+  const double2* r = s.rb + (long long)w * s.NQ;     // the force bias's <rho_Q>
   double2* cq = s.cq + (long long)w * s.NQ;
   double2 ex = zero2();
   for (int q = threadIdx.x; q < s.NQ; q += NT) {
@@ -180,8 +180,8 @@ __global__ __launch_bounds__(NT) void taylor_blocks_kernel(SysDev s, TaylorLow t
 }
 
 // ------------------------------------------------------ Green's function ---
-FT_DEV void split_L(const SysDev& s, int i, int k, double* lb, double* ls) {
-  const double lnl = (double)(s.n - k) * s.lnbt[i];
+FT_DEV void split_L(const SysDev& s, int i, int lexp, double* lb, double* ls) {
+  const double lnl = (double)lexp * s.lnbt[i];
   *lb = exp(-fmax(lnl, 0.0));
   *ls = exp(fmin(lnl, 0.0));
 }
@@ -192,7 +192,7 @@ FT_DEV void split_D(double d, double* db, double* ds) {
 }
 
 // aug[i][j] = X[j][i], aug[i][ld + j] = (Ti D_b)[j][i]  (transposed through LDS)
-__global__ __launch_bounds__(NT) void greens_form_kernel(SysDev s, int k) {
+__global__ __launch_bounds__(NT) void greens_form_kernel(SysDev s, int lexp) {
   __shared__ double2 tX[TT][TT + 1];
   __shared__ double2 tU[TT][TT + 1];
   const int nt = (s.ld + TT - 1) / TT;
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(NT) void greens_form_kernel(SysDev s, int k) {
     double2 x = zero2(), u = zero2();
     if (row < s.M && col < s.M) {
       double lb, ls, db, ds;
-      split_L(s, row, k, &lb, &ls);
+      split_L(s, row, lexp, &lb, &ls);
       split_D(D[col], &db, &ds);
       const double2 tv = Ti[(long long)row * s.ld + col], yv = Y[(long long)row * s.ld + col];
       u = cscale(tv, db);
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(NT) void greens_form_kernel(SysDev s, int k) {
 }
 
 // G[i][j] = H[j][i] L_b[j] with H = aug right block (= X^{-T} (Ti D_b)^T)
-__global__ __launch_bounds__(NT) void greens_post_kernel(SysDev s, int k) {
+__global__ __launch_bounds__(NT) void greens_post_kernel(SysDev s, int lexp) {
   __shared__ double2 tH[TT][TT + 1];
   const int nt = (s.ld + TT - 1) / TT;
   int w, tile;
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(NT) void greens_post_kernel(SysDev s, int k) {
     double2 h = zero2();
     if (row < s.M && col < s.M) {
       double lb, ls;
-      split_L(s, row, k, &lb, &ls);
+      split_L(s, row, lexp, &lb, &ls);
       h = cscale(aug[(long long)row * 2 * s.ld + s.ld + col], lb);
     }
     tH[yy][tx] = h;
@@ -850,23 +850,26 @@ hipError_t launch_taylor_blocks(const SysDev& s, int mixed, const TaylorLow& t, 
   else taylor_blocks_kernel<double2><<<2048, NT, 0, st>>>(s, t);
   return hipGetLastError();
 }
-hipError_t launch_greens_form(const SysDev& s, int k, hipStream_t st) {
-  greens_form_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s, k);
+hipError_t launch_greens_form(const SysDev& s, int lexp, hipStream_t st) {
+  greens_form_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s, lexp);
   return hipGetLastError();
 }
-hipError_t launch_greens_post(const SysDev& s, int k, hipStream_t st) {
-  greens_post_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s, k);
+hipError_t launch_greens_post(const SysDev& s, int lexp, hipStream_t st) {
+  greens_post_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s, lexp);
   return hipGetLastError();
 }
 int rq_block_elems() { return RQ_ELEMS; }
-hipError_t launch_weight(const SysDev& s, int k, double sum_lnLb, int init, hipStream_t st) {
+hipError_t launch_rq(const SysDev& s, hipStream_t st) {
   if (s.NQ > 0 && s.NQ <= RQ_QPT * RQ_NT && s.rq_rows * s.ld <= RQ_ELEMS) {
     rq_stream_kernel<<<s.W, RQ_NT, 0, st>>>(s);
   } else {
     const int chunks = (s.NQ + NT - 1) / NT;
     rq_kernel<<<tiles_blocks(s, chunks), NT, 0, st>>>(s, chunks);
   }
-  hipError_t e = hipGetLastError();
+  return hipGetLastError();
+}
+hipError_t launch_weight(const SysDev& s, int k, double sum_lnLb, int init, hipStream_t st) {
+  hipError_t e = launch_rq(s, st);
   if (e != hipSuccess) return e;
   weight_kernel<<<s.W, NT, 0, st>>>(s, k, sum_lnLb, init);
   return hipGetLastError();

@@ -556,3 +556,25 @@ def test_graph_replays_match_eager_paths(overlap):
         for a, b in zip(snapshot(ctx), refs[which]):
             assert np.array_equal(a, b), (rep, which)
     ctx.close()
+
+
+def test_concurrent_systems_match_serial_schedule(monkeypatch):
+    """The four systems of the uneven batch run on streams of their own, enqueued longest-first;
+    the same batch with FTAFQMC_SERIAL_SYSTEMS=1 (one after another) must give bit-identical
+    results, and every system reports its share of the call's wall time."""
+    F = _F()
+    wl = si.WORKLOADS["ueg_uneven4"]
+    systems = [dict(sd, walkers=8, precision=1) for sd in wl["systems"]]
+    flds = []
+    for i, sd in enumerate(systems):
+        s = oracle_system(sd)
+        flds.append(si.fields(si.system_seed("ueg_uneven4", i), sd["walkers"], s.n_slices, s.NQ))
+    conc, _ = gpu_run(F, systems, flds)
+    times = conc.system_times()
+    assert len(times) == 4 and all(t > 0 for t in times)
+    monkeypatch.setenv("FTAFQMC_SERIAL_SYSTEMS", "1")
+    ser, _ = gpu_run(F, systems, flds)
+    for i in range(4):
+        a, b = conc.energy(i), ser.energy(i)
+        assert torch.equal(a["local"], b["local"]) and torch.equal(a["logw"], b["logw"]), i
+        assert torch.equal(conc.greens(i), ser.greens(i)), i
