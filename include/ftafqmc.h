@@ -164,6 +164,20 @@ int ftafqmc_workspace_bytes(const ftafqmc_params* p, int n_sys, size_t* bytes);
 int ftafqmc_init_ueg(const ftafqmc_params* p, int n_sys, void* d_workspace, size_t ws_bytes,
                      void* stream, ftafqmc_t* out);
 
+/* Allocation-free variant of ftafqmc_init_ueg, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid allocation).  The
+ * workspace is a file-scope device array of FTAFQMC_STATIC_WORKSPACE_BYTES that the library
+ * holds on every device it runs on until the process ends (the M = 19, 64-walker system needs
+ * 21 MiB); the call itself allocates no device memory.  Everything else is as ftafqmc_init_ueg,
+ * and the handle is used and destroyed like any other.  One live handle per device may hold the
+ * array: a second call on the same device returns FTAFQMC_E_STATE until that handle is
+ * destroyed, and work of such handles from several threads or processes that overlaps on one
+ * device would race on the array.  Errors: FTAFQMC_E_ARG when the systems need more than the
+ * maximum or ask for FTAFQMC_OVERLAP or FTAFQMC_GRAPH (which create streams and graphs), with
+ * the message in ftafqmc_last_error(NULL). */
+#define FTAFQMC_STATIC_WORKSPACE_BYTES (64u << 20)
+int ftafqmc_init_ueg_static(const ftafqmc_params* p, int n_sys, void* stream, ftafqmc_t* out);
+
 /* Sizes and constants of system `sys` (host-side; does not synchronise). */
 int ftafqmc_query(ftafqmc_t h, int sys, ftafqmc_info* out);
 
@@ -323,7 +337,8 @@ enum { FTAFQMC_PROF_GEMM = 0, FTAFQMC_PROF_ELIM = 1, FTAFQMC_PROF_GREENS = 2, FT
 int ftafqmc_profile(ftafqmc_t h, int enable, double* h_ms, long long* h_count);
 
 /* Message of the last error on this handle ("" if none); valid until the next call.  With
- * h = NULL: the message of the last failed ftafqmc_init_ueg call on this thread. */
+ * h = NULL: the message of the last failed ftafqmc_init_ueg / ftafqmc_init_ueg_static call on
+ * this thread. */
 const char* ftafqmc_last_error(ftafqmc_t h);
 
 /* Release the handle (host memory only; the caller frees the workspace). */

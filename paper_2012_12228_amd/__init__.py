@@ -31,11 +31,13 @@ POP_COMB, POP_PAIR_BRANCH = 0, 1   # ftafqmc_population_control methods
 MU_BRACKET_FIT, MU_NEWTON = 0, 1   # ftafqmc_tune_mu methods
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NUMERIC", -4: "E_STATE", -5: "E_UNSUPPORTED"}
 
-ABI_SYMBOLS = ["ftafqmc_workspace_bytes", "ftafqmc_init_ueg", "ftafqmc_query", "ftafqmc_reset", "ftafqmc_propagate", "ftafqmc_greens", "ftafqmc_energy", "ftafqmc_records",
+ABI_SYMBOLS = ["ftafqmc_workspace_bytes", "ftafqmc_init_ueg", "ftafqmc_init_ueg_static", "ftafqmc_query",
+               "ftafqmc_reset", "ftafqmc_propagate", "ftafqmc_greens", "ftafqmc_energy", "ftafqmc_records",
                "ftafqmc_backward", "ftafqmc_population_control", "ftafqmc_record_stats",
                "ftafqmc_density_correlation", "ftafqmc_qvectors", "ftafqmc_set_mu", "ftafqmc_tune_mu",
                "ftafqmc_system_times", "ftafqmc_profile",
                "ftafqmc_last_error", "ftafqmc_destroy"]
+STATIC_WORKSPACE_BYTES = 64 << 20   # FTAFQMC_STATIC_WORKSPACE_BYTES
 PROF_CLASSES = ["gemm", "elim", "greens_transpose", "weight_forcebias", "coef_gather", "stabilise", "energy",
                 "backward"]
 
@@ -78,6 +80,7 @@ def load_library():
     vp, ip, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
     lib.ftafqmc_workspace_bytes.argtypes = [ctypes.POINTER(Params), ip, ctypes.POINTER(sz)]
     lib.ftafqmc_init_ueg.argtypes = [ctypes.POINTER(Params), ip, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.ftafqmc_init_ueg_static.argtypes = [ctypes.POINTER(Params), ip, vp, ctypes.POINTER(vp)]
     lib.ftafqmc_query.argtypes = [vp, ip, ctypes.POINTER(Info)]
     lib.ftafqmc_reset.argtypes = [vp, vp]
     lib.ftafqmc_propagate.argtypes = [vp, ctypes.POINTER(vp), ip, vp]
@@ -147,6 +150,14 @@ def ftafqmc_init_ueg(systems, workspace, device):
     h = ctypes.c_void_p(0)
     _check(load_library().ftafqmc_init_ueg(arr, len(systems), _ptr(workspace), workspace.numel(),
                                            _stream(device), ctypes.byref(h)))
+    return h
+
+
+def ftafqmc_init_ueg_static(systems, device):
+    """Initialise with the library's static device workspace (no device allocation)."""
+    arr = (Params * len(systems))(*[_params(s) for s in systems])
+    h = ctypes.c_void_p(0)
+    _check(load_library().ftafqmc_init_ueg_static(arr, len(systems), _stream(device), ctypes.byref(h)))
     return h
 
 
@@ -264,18 +275,25 @@ def ftafqmc_destroy(handle):
 class Context:
     """One library handle over one or more UEG systems, with its torch workspace."""
 
-    def __init__(self, systems, device="cuda:0"):
+    def __init__(self, systems, device="cuda:0", static_workspace=False):
+        """static_workspace: use ftafqmc_init_ueg_static (the library's own device array, no
+        allocation) instead of a torch workspace."""
         if isinstance(systems, dict):
             systems = [systems]
         self.systems = [dict(s) for s in systems]
         self.device = torch.device(device)
         self.handle = None
         load_library()
-        nbytes = ftafqmc_workspace_bytes(self.systems)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        off = (-self.workspace.data_ptr()) % 256
-        self.workspace = self.workspace[off:off + nbytes]
-        self.handle = ftafqmc_init_ueg(self.systems, self.workspace, self.device)
+        if static_workspace:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                self.handle = ftafqmc_init_ueg_static(self.systems, self.device)
+        else:
+            nbytes = ftafqmc_workspace_bytes(self.systems)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.workspace.data_ptr()) % 256
+            self.workspace = self.workspace[off:off + nbytes]
+            self.handle = ftafqmc_init_ueg(self.systems, self.workspace, self.device)
         self.infos = [ftafqmc_query(self.handle, i) for i in range(len(self.systems))]
 
     def info(self, sys=0):

@@ -1418,6 +1418,7 @@ const char* ftafqmc_last_error(ftafqmc_t h) { return h ? h->err.c_str() : init_e
 
 void ftafqmc_destroy(ftafqmc_t h) {
   if (!h) return;
+  static_ws_release(h);
   for (auto& ev : h->events) { (void)hipEventDestroy(ev.a); (void)hipEventDestroy(ev.b); }
   for (auto& s : h->sys) {
     if (s.t0) (void)hipEventDestroy(s.t0);

@@ -9,3 +9,5 @@ int lib_init_error(int code, const char* msg);
 // another, each system's walkers in one group).
 int init_ueg_impl(const ftafqmc_params* p, int n_sys, void* d_workspace, size_t ws_bytes, void* stream,
                   ftafqmc_t* out, bool no_side_streams);
+// Called by ftafqmc_destroy: a handle that held a device's static workspace releases it.
+void static_ws_release(ftafqmc_t h);
