@@ -329,6 +329,9 @@ def main():
                     help="skip the extra timing of the mixed path with FTAFQMC_OVERLAP")
     ap.add_argument("--no-extra-workloads", action="store_true",
                     help="skip the one-path timings of the uneven four-system batch and the M=485 workload")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="one warm-up path and one path of --precision (mixed when 'both') with no HIP events and "
+                         "no other measurement: the program rocprofv3 kernel-trace and counter passes run")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -347,6 +350,20 @@ def main():
         torch.cuda.synchronize()
         del src_t, dst_t
     wl = si.WORKLOADS[args.workload]
+    if args.profile_run:
+        p = "mixed" if args.precision == "both" else args.precision
+        fields = load_fields(F, torch, args.workload)
+        ctx = F.Context([dict(sd, precision=0 if p == "fp64" else 1) for sd in wl["systems"]])
+        _path(ctx, fields, len(wl["systems"]))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _path(ctx, fields, len(wl["systems"]))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ws = sum(ctx.info(i)["n_walkers"] * ctx.info(i)["n_slices"] for i in range(len(wl["systems"])))
+        print(json.dumps({"profile_run": args.workload, "precision": p, "walker_slices_per_s": ws / dt}))
+        ctx.close()
+        return
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     results, fields = bench_workload(F, torch, args.workload, precs, args.steps, args.warmup, overlap=args.overlap)
     for p in precs:
