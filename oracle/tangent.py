@@ -193,3 +193,82 @@ def walker_tangents(sys, z, params=("mu", "kscale")):
     fwd["E"] = fwd["records"][-1]
     out = {p: path_tangent(sys, fwd, p) for p in params}
     return fwd, out
+
+
+# --------------------------------------------------------------------------
+# pathwise derivatives: the raw fields held fixed, the force bias recomputed
+# --------------------------------------------------------------------------
+def pathwise_tangent(sys, z, param):
+    """Derivatives of one walker's path with the raw fields z held fixed while mu or lambda
+    moves: besides the half-step factors K, the force bias of every slice follows G_k
+    (Sec. "Phaseless approximation"), so the shifted one-body matrix V_k, its exponential and
+    the exponent of eq. import all move.  This is what central differences of run_walker in
+    (mu, lambda) measure.
+
+    Per slice k, with the doubled product Rd = [[R, dR], [0, R]] (Leibniz) stratified as in the
+    forward path:
+      * G_k and dG_k are the blocks of the literal doubled inverse (I + diag(L, L) Rd)^{-1},
+        L = B_T^{n-k}; dP = -dG^T gives dr_Q (per spin) and the shift derivatives
+        dxbar_A = -sqrt(dtau) 2i a_Q (dr_Q + dr_-Q), dxbar_B = sqrt(dtau) 2 a_Q (dr_Q - dr_-Q);
+      * dV is the one-body matrix of the coefficients of (-dxbar_A, -dxbar_B);
+      * d e^V is the Frechet derivative, the off-diagonal block of expm([[V, dV], [0, V]]);
+      * dB = dK e^V K + K e^V dK + K (d e^V) K;
+      * d ln S_k from the cyclic Green's function as for the frozen path, and
+        d(exponent_k) = sum [(x_A - xbar_A) dxbar_A + (x_B - xbar_B) dxbar_B].
+    Returns (fwd, dict(dlnS, dexpo, dlogw, G, dG, dE1, dE2, dE, dN)).
+    """
+    fwd = _path.run_walker(sys, z, energy_fn=local_energy)
+    fwd["E"] = fwd["records"][-1]
+    M, n = sys.M, sys.n_slices
+    kh, dkh = one_body_factors(sys, param)
+    bt = np.exp(sys.log_trial_diag())
+    sdt = np.sqrt(sys.dtau)
+    Qd = np.eye(2 * M, dtype=np.complex128)
+    Dd = np.ones(2 * M, dtype=np.complex128)
+    Td = np.eye(2 * M, dtype=np.complex128)
+    I = np.eye(M)
+    dlnS = np.zeros(n, dtype=np.complex128)
+    dexpo = np.zeros(n, dtype=np.complex128)
+    Z = np.zeros((M, M), dtype=np.complex128)
+    for k in range(n):
+        Gd = literal_greens_doubled(sys, Qd, Dd, Td, k)
+        G, dG = Gd[:M, :M], Gd[:M, M:]
+        P, dP = np.eye(M) - G.T, -dG.T
+        r = np.array([P[sys.pairs[q]].sum() for q in range(sys.NQ)], dtype=np.complex128)
+        dr = np.array([dP[sys.pairs[q]].sum() for q in range(sys.NQ)], dtype=np.complex128)
+        xbA, xbB = _path.force_bias(sys, P)
+        dxbA = -sdt * 2.0 * 1j * sys.aq * (dr + dr[sys.neg])
+        dxbB = sdt * 2.0 * sys.aq * (dr - dr[sys.neg])
+        xA, xB = z[k].real, z[k].imag
+        V = _path.one_body_matrix(sys, _path.hs_rho_coefficients(sys, xA - xbA, xB - xbB))
+        dV = _path.one_body_matrix(sys, _path.hs_rho_coefficients(sys, -dxbA, -dxbB))
+        dexpo[k] = np.sum((xA - xbA) * dxbA + (xB - xbB) * dxbB)
+        big = sla.expm(np.block([[V, dV], [Z, V]]))
+        E, dE = big[:M, :M], big[:M, M:]
+        B = kh[:, None] * E * kh[None, :]
+        dB = dkh[:, None] * E * kh[None, :] + kh[:, None] * E * dkh[None, :] + kh[:, None] * dE * kh[None, :]
+        Gc = cyclic_greens_doubled(sys, Qd, Dd, Td, k)
+        G0, dG0 = Gc[:M, :M], Gc[:M, M:]
+        Wm = B / bt[None, :] - I
+        Phi = Wm @ (I - G0)
+        dPhi = (dB / bt[None, :]) @ (I - G0) - Wm @ dG0
+        dlnS[k] = 2.0 * np.trace(np.linalg.solve(I + Phi, dPhi))
+        Bd = np.block([[B, dB], [np.zeros_like(B), B]])
+        Qd, Dd, Td = _path.qdt_update((Bd @ Qd) * Dd[None, :], Td)
+    Gd = literal_greens_doubled(sys, Qd, Dd, Td, n)
+    G, dG = Gd[:M, :M], Gd[:M, M:]
+    d = 0.0
+    for k in range(n):
+        if not fwd["alive"][k]:
+            break
+        d += dlnS[k].real + dexpo[k].real - np.tan(fwd["theta"][k]) * dlnS[k].imag
+    dkscale = 1.0 if param == "kscale" else 0.0
+    e = energy_tangent(sys, G, dG, dkscale)
+    return fwd, dict(dlnS=dlnS, dexpo=dexpo, dlogw=d, G=G, dG=dG, **e)
+
+
+def kink_margin(fwd):
+    """Smallest cos(theta_k) over the slices the walker survived: the weight is not
+    differentiable where a slice's cos(theta) crosses 0 (the phaseless kill)."""
+    c = [np.cos(fwd["theta"][k]) for k in range(len(fwd["theta"])) if fwd["alive"][k]]
+    return min(c) if c else -1.0

@@ -178,3 +178,74 @@ def test_doubled_tangent_at_cond_1e30_against_high_precision():
     dGref = np.array([[complex((Gp[i, j] - Gm[i, j]) / (2 * h)) for j in range(M)] for i in range(M)])
     assert np.abs(t["dG"] - dGref).max() < 1e-13
     assert np.abs(dGref).max() > 1e-2      # the derivative is not trivially small here
+
+
+# ---------------------------------------------------------------- pathwise ---
+def _pathwise_fd(kw, z, param, h=1e-5):
+    base = dict(mu=ueg.UEGSystem(**kw).mu_T, kscale=1.0)
+    out = {}
+    for sg in (1, -1):
+        b = dict(base)
+        b[param] += sg * h
+        sp = ueg.UEGSystem(mu=b["mu"], kscale=b["kscale"], **kw)
+        o = path.run_walker(sp, z, energy_fn=energy.local_energy)
+        out[sg] = (o["logw"], o["records"][-1]["E"], o["records"][-1]["N"])
+    return [(out[1][i] - out[-1][i]) / (2 * h) for i in range(3)]
+
+
+@pytest.mark.parametrize("param", ["mu", "kscale"])
+@pytest.mark.parametrize("walker", [0, 3])
+def test_pathwise_tangent_matches_central_differences(param, walker):
+    """Raw fields held fixed, force bias recomputed: the tangent equals central differences
+    (h = 1e-5) of the whole path in ln w, E and N at tau = beta (1e-7 relative: the difference
+    quotient's own error is ~h^2)."""
+    kw = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5)
+    s = ueg.UEGSystem(**kw)
+    z = si.walker_fields(77, walker, s.n_slices, s.NQ)
+    fwd, t = tangent.pathwise_tangent(s, z, param)
+    assert tangent.kink_margin(fwd) > 1e-3
+    fd = _pathwise_fd(kw, z, param)
+    for got, want in ((t["dlogw"], fd[0]), (t["dE"], fd[1]), (t["dN"], fd[2])):
+        assert abs(got - want) < 1e-7 * max(1.0, abs(want)), (got, want)
+    # and it is not the frozen-path derivative (the force-bias feedback moves the path)
+    fz = tangent.path_tangent(s, path.run_walker(s, z, record_path=True, energy_fn=energy.local_energy), param)
+    assert abs(fz["dlogw"] - t["dlogw"]) > 1e-3
+
+
+def test_pathwise_equals_frozen_with_zero_fields():
+    """Zero fields keep G diagonal, so r_Q = 0 and dr_Q = 0 for every Q: the force bias does not
+    move and the pathwise derivative is the frozen one (the mu direction in closed form)."""
+    kw = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5)
+    s = ueg.UEGSystem(**kw)
+    z = np.zeros((s.n_slices, s.NQ), dtype=np.complex128)
+    fwd, t = tangent.pathwise_tangent(s, z, "mu")
+    ref = path.run_walker(s, z, energy_fn=energy.local_energy, keep_greens="all")
+    cf = tangent.mu_tangent_closed_form(s, ref)
+    assert np.allclose(t["dlnS"], cf["dlnS"], rtol=1e-10, atol=1e-12)
+    assert abs(t["dlogw"] - cf["dlogw"]) < 1e-10 * max(1.0, abs(cf["dlogw"]))
+    assert np.allclose(t["dG"], cf["dG"], atol=1e-12)
+    assert np.all(np.abs(t["dexpo"]) < 1e-14)
+
+
+def test_pathwise_ensemble_means_match_differences():
+    """d<E>/dmu and d<N>/dmu of the weighted means over 6 walkers, pathwise, against central
+    differences of the means."""
+    kw = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5)
+    s = ueg.UEGSystem(**kw)
+    zs = [si.walker_fields(78, w, s.n_slices, s.NQ) for w in range(6)]
+    vals, dvals, lw, dlw, st = [], [], [], [], []
+    for z in zs:
+        fwd, t = tangent.pathwise_tangent(s, z, "mu")
+        vals.append(fwd["E"]["N"]); dvals.append(t["dN"]); lw.append(fwd["logw"]); dlw.append(t["dlogw"])
+        st.append(fwd["status"])
+    _, dmean = tangent.ensemble_tangent(np.array(vals), np.array(dvals), np.array(lw), np.array(dlw), np.array(st))
+    h = 1e-5
+    means = []
+    for sg in (1, -1):
+        sp = ueg.UEGSystem(mu=s.mu_T + sg * h, **kw)
+        outs = [path.run_walker(sp, z, energy_fn=energy.local_energy) for z in zs]
+        l = np.array([o["logw"] for o in outs])
+        w = np.exp(l - l.max())
+        means.append(np.sum(w * np.array([o["records"][-1]["N"] for o in outs])) / w.sum())
+    fd = (means[0] - means[1]) / (2 * h)
+    assert abs(dmean - fd) < 1e-7 * abs(fd)
