@@ -280,8 +280,8 @@ def time_overlap(F, torch, systems, fields, steps):
 
 
 def time_backward(F, torch, workload="ueg_n38_m123"):
-    """Wall time of one frozen-path derivative pass (ftafqmc_backward) on the derivative
-    workload, beside the FP64 forward path it differentiates (both with inputs in HBM)."""
+    """Wall time of one frozen-path and one pathwise derivative pass (ftafqmc_backward) on the
+    derivative workload, beside the FP64 forward path they differentiate (inputs in HBM)."""
     wl = si.WORKLOADS[workload]
     sd = dict(wl["systems"][0], precision=0, flags=F.FTAFQMC_CHECKPOINT)
     ctx = F.Context(sd)
@@ -304,12 +304,22 @@ def time_backward(F, torch, workload="ueg_n38_m123"):
     ctx.backward()
     prof = ctx.profile(False)
     jac = b["jac"].cpu().numpy()
+    ctx.backward(mode=F.PATHWISE)                    # warm-up of the pathwise pass
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    bp = ctx.backward(mode=F.PATHWISE)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    jp = bp["jac"].cpu().numpy()
     ctx.close()
     ws = inf["n_walkers"] * inf["n_slices"]
     return {"workload": workload, "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
             "walker_slices_per_s_backward": ws / (t2 - t1),
             "profile_ms": {k: v[0] for k, v in prof.items() if v[1]},
-            "d<E>/dmu": jac[0].real, "d<N>/dmu": jac[1].real, "d<E>/dlambda": jac[2].real, "d<N>/dlambda": jac[3].real}
+            "d<E>/dmu": jac[0].real, "d<N>/dmu": jac[1].real, "d<E>/dlambda": jac[2].real, "d<N>/dlambda": jac[3].real,
+            "pathwise_s": t4 - t3, "pathwise_over_forward": (t4 - t3) / (t1 - t0),
+            "pathwise": {"d<E>/dmu": jp[0].real, "d<N>/dmu": jp[1].real, "d<E>/dlambda": jp[2].real,
+                         "d<N>/dlambda": jp[3].real}}
 
 
 def main():

@@ -116,6 +116,7 @@ typedef struct {
 #define FTAFQMC_MEASURE_EVERY_SLICE 32
 /* ftafqmc_backward modes */
 #define FTAFQMC_FROZEN_PATH 0
+#define FTAFQMC_PATHWISE 1
 
 /* Derived sizes and constants of one system (host-side values). */
 typedef struct {
@@ -227,10 +228,29 @@ int ftafqmc_records(ftafqmc_t h, int sys, void* d_trace, double* d_logw, int* h_
  *   d_grad   [2] double: dL/dmu, dL/dlambda = cot . Re(jac)
  *   d_walker [W][6] complex128: per walker (d ln w, dE, dN) along mu, then along lambda
  *            (NaN for a walker whose doubled factorisation broke down).
+ * Mode FTAFQMC_PATHWISE differentiates the same estimator with the raw fields x_k held fixed
+ * instead of the shifted ones: the force bias xbar_k = -sqrt(dtau) v_Q <rho_Q>_{G_k} (eq. fb)
+ * moves with G_k, hence the shifted fields x_k - xbar_k, the one-body operator V_k, e^{V_k}
+ * (its Frechet derivative carried through the same Taylor chain as the forward product) and the
+ * exponent of the importance function (eq. import), on top of everything the frozen mode
+ * moves.  Both directions carry the doubled product; each slice also forms the doubled
+ * G_k = (I + diag(B_T^{n-k}) R_k)^{-1} for dG_k, so the cost is about twice the frozen mode's
+ * lambda direction per direction.  The path must have been propagated with one field buffer
+ * for all of its slices (the layout [W][n][N_Q] of ftafqmc_propagate, from slice 0 in one call
+ * or in several calls on the same buffer), which must still hold the path's fields.
+ * The weight is differentiable away from the phaseless kill (cos theta_k = 0 on a slice the
+ * walker survived); ftafqmc_kink_flags marks walkers near it.
  * Walkers that are killed or numerically failed carry zero weight and do not enter the means.
- * Errors: E_STATE without the record or before slice n; E_UNSUPPORTED for other modes. */
+ * Errors: E_STATE without the record, before slice n, or (pathwise) when the slices came from
+ * different field buffers; E_ARG for an unknown mode. */
 int ftafqmc_backward(ftafqmc_t h, int sys, int mode, const double* d_cot, void* d_jac,
                      double* d_grad, void* d_walker, void* stream);
+
+/* Walkers whose recorded path came within `threshold` of the phaseless kill: d_flags [W] int
+ * (device), 1 where cos theta_k < threshold on some slice k the walker survived (eq. theta;
+ * the pathwise derivative of such a walker's weight is taken next to the kink of
+ * max(0, cos theta)), else 0.  Read from the phases every system records per slice. */
+int ftafqmc_kink_flags(ftafqmc_t h, int sys, double threshold, int* d_flags, void* stream);
 
 /* Population control of system `sys` (Sec. "Computational Details": the comb method, and pair
  * branching for Theta <= 0.25), between ftafqmc_propagate calls.  Weights are

@@ -26,14 +26,15 @@ FTAFQMC_TRIAL_THF = 8      # params flag: thermal Hartree-Fock trial instead of 
 FTAFQMC_MODIFIED_OVERLAP = 16     # params flag: constraint from the modified overlap ratio (eq. ztfix)
 FTAFQMC_MEASURE_EVERY_SLICE = 32  # params flag: an energy record after every slice
 FTAFQMC_PROFILE_ONLY = 256  # ftafqmc_profile: record only the classes in the low bits
-FROZEN_PATH = 0            # ftafqmc_backward mode
+FROZEN_PATH = 0            # ftafqmc_backward modes: shifted fields held fixed
+PATHWISE = 1               #   raw fields held fixed, the force bias follows G_k
 POP_COMB, POP_PAIR_BRANCH = 0, 1   # ftafqmc_population_control methods
 MU_BRACKET_FIT, MU_NEWTON = 0, 1   # ftafqmc_tune_mu methods
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NUMERIC", -4: "E_STATE", -5: "E_UNSUPPORTED"}
 
 ABI_SYMBOLS = ["ftafqmc_workspace_bytes", "ftafqmc_init_ueg", "ftafqmc_init_ueg_static", "ftafqmc_query",
                "ftafqmc_reset", "ftafqmc_propagate", "ftafqmc_greens", "ftafqmc_energy", "ftafqmc_records",
-               "ftafqmc_backward", "ftafqmc_population_control", "ftafqmc_record_stats",
+               "ftafqmc_backward", "ftafqmc_kink_flags", "ftafqmc_population_control", "ftafqmc_record_stats",
                "ftafqmc_density_correlation", "ftafqmc_qvectors", "ftafqmc_set_mu", "ftafqmc_tune_mu",
                "ftafqmc_system_times", "ftafqmc_profile",
                "ftafqmc_last_error", "ftafqmc_destroy"]
@@ -88,6 +89,7 @@ def load_library():
     lib.ftafqmc_energy.argtypes = [vp, ip, vp, vp, vp, vp, vp]
     lib.ftafqmc_records.argtypes = [vp, ip, vp, vp, ctypes.POINTER(ctypes.c_int), vp]
     lib.ftafqmc_backward.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp]
+    lib.ftafqmc_kink_flags.argtypes = [vp, ip, ctypes.c_double, vp, vp]
     lib.ftafqmc_population_control.argtypes = [vp, ip, ip, vp, vp, vp]
     lib.ftafqmc_record_stats.argtypes = [vp, ip, vp, vp, vp]
     lib.ftafqmc_density_correlation.argtypes = [vp, ip, vp, vp, vp]
@@ -209,6 +211,10 @@ def ftafqmc_backward(handle, sys, mode, cot, jac, grad, walker, device):
                                            _stream(device)), handle)
 
 
+def ftafqmc_kink_flags(handle, sys, threshold, flags, device):
+    _check(load_library().ftafqmc_kink_flags(handle, sys, float(threshold), _ptr(flags), _stream(device)), handle)
+
+
 def ftafqmc_population_control(handle, sys, method, uniforms, parent, device):
     _check(load_library().ftafqmc_population_control(handle, sys, method, _ptr(uniforms), _ptr(parent),
                                                      _stream(device)), handle)
@@ -313,6 +319,7 @@ class Context:
         if n_slices is None:
             n_slices = max(inf["n_slices"] for inf in self.infos)
         ftafqmc_propagate(self.handle, fields, n_slices, self.device)
+        self._fields = fields        # held until the next call: the pathwise backward re-reads them
 
     def greens(self, sys=0, dtype=torch.complex128):
         inf = self.infos[sys]
@@ -336,8 +343,10 @@ class Context:
         slices = ftafqmc_records(self.handle, sys, trace, logw, n, self.device)
         return dict(slices=slices, trace=trace[:n], logw=logw[:n])
 
-    def backward(self, sys=0, cot=None):
-        """Frozen-path derivatives at tau = beta (the system needs flags=FTAFQMC_CHECKPOINT).
+    def backward(self, sys=0, cot=None, mode=FROZEN_PATH):
+        """Derivatives at tau = beta in (mu, lambda) (the system needs flags=FTAFQMC_CHECKPOINT):
+        FROZEN_PATH holds the shifted fields fixed, PATHWISE the raw fields (the force bias then
+        follows G_k; the path must have been propagated from one field buffer).
 
         Returns dict(jac [4] complex128 = d<E>/dmu, d<N>/dmu, d<E>/dlambda, d<N>/dlambda,
         walker [W][6] complex128 = (d ln w, dE, dN) along mu then lambda, and
@@ -350,8 +359,15 @@ class Context:
         if cot is not None:
             cot = torch.as_tensor(cot, dtype=torch.float64, device=self.device).contiguous()
             grad = torch.empty(2, dtype=torch.float64, device=self.device)
-        ftafqmc_backward(self.handle, sys, FROZEN_PATH, cot, jac, grad, walker, self.device)
+        ftafqmc_backward(self.handle, sys, mode, cot, jac, grad, walker, self.device)
         return dict(jac=jac, walker=walker, grad=grad)
+
+    def kink_flags(self, threshold, sys=0):
+        """int32 [W]: 1 where the walker's recorded path had cos(theta_k) < threshold on a slice
+        it survived (its weight is next to the kink of the phaseless kill)."""
+        flags = torch.empty(self.infos[sys]["n_walkers"], dtype=torch.int32, device=self.device)
+        ftafqmc_kink_flags(self.handle, sys, threshold, flags, self.device)
+        return flags
 
     def population_control(self, method, uniforms, sys=0):
         """Comb (POP_COMB) or pair branching (POP_PAIR_BRANCH) with the given uniforms (a float64
@@ -426,6 +442,12 @@ class FrozenPathMeans(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, mu, kscale, system, fields):
+        return FrozenPathMeans._run(ctx, mu, kscale, system, fields, FROZEN_PATH)
+
+    @staticmethod
+    def _run(ctx, mu, kscale, system, fields, mode):
+        ctx.mode = mode
+        ctx.fields = fields          # the pathwise backward re-reads the path's fields
         sysdef = dict(system)
         sysdef.update(mu=float(mu.detach()), kscale=float(kscale.detach()), precision=FTAFQMC_FP64,
                       flags=FTAFQMC_CHECKPOINT)
@@ -439,9 +461,18 @@ class FrozenPathMeans(torch.autograd.Function):
     def backward(ctx, gE, gN):
         c = ctx.context
         cot = torch.stack([gE.reshape(()), gN.reshape(())]).to(torch.float64)
-        g = c.backward(cot=cot)["grad"]
+        g = c.backward(cot=cot, mode=ctx.mode)["grad"]
         c.close()
         return g[0], g[1], None, None
+
+
+class PathwiseMeans(FrozenPathMeans):
+    """As FrozenPathMeans with the raw fields held fixed (the force bias of every slice follows
+    G_k): the derivative that central differences of the whole run in (mu, lambda) measure."""
+
+    @staticmethod
+    def forward(ctx, mu, kscale, system, fields):
+        return FrozenPathMeans._run(ctx, mu, kscale, system, fields, PATHWISE)
 
 
 def walker_slices_per_second(systems_info, seconds):

@@ -59,6 +59,7 @@ struct HostSys {
   int rq_rows = 0, rq_nblk = 0;
   std::vector<double> vq, sq, eps, hK, kh, lnbt;
   std::vector<double> tlev;             // trial levels: eps (free electron) or thermal Hartree-Fock
+  std::vector<double> lnbt2;            // ln diag B_T for both halves of the doubled system
   std::vector<short> grid;
   size_t off_begin = 0, bytes = 0;
   SysDev dev;
@@ -77,6 +78,8 @@ struct HostSys {
   bool every = false;                   // energy record after every slice
   double* small = nullptr;              // [32] device doubles for host-driven loops (mu tuning)
   int lane0 = 0;                        // first stream lane of this system (its groups follow)
+  const void* fields = nullptr;         // field buffer of the current path (pathwise derivative)
+  bool fields_ok = false;               // one buffer served every slice so far
   hipEvent_t t0 = nullptr, t1 = nullptr;  // start and end of its share of the last eager propagate call
   int stab_cap = 1;                     // re-factorise at least every stab_cap slices
 };
@@ -211,6 +214,8 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
     s.kh[i] = std::exp(-0.5 * s.dtau * (p.kscale * s.eps[i] + s.hK[i] - s.mu));
     s.lnbt[i] = -s.dtau * (s.tlev[i] - s.muT);
   }
+  s.lnbt2.assign(s.ld2, 0.0);
+  for (int i = 0; i < s.M2; ++i) s.lnbt2[i] = s.lnbt[i % s.M];
   // pairs of each Q as flat indices of G_{r p} (K_p - K_r = Q)
   s.qptr.assign(s.NQ + 1, 0);
   for (int i = 0; i < s.M; ++i)
@@ -396,6 +401,24 @@ size_t layout(HostSys& s, char* base, size_t off) {
     t.alive = (int*)take(sizeof(int) * W);
     t.bc_stride = (long long)ld * ld2;
     t.gs_stride = (long long)ld2 * ld;
+    // pathwise mode
+    t.Tid = (double2*)take(sizeof(double2) * mat2 * W);
+    t.Gd = (double2*)take(sizeof(double2) * mat2 * W);
+    t.lnbt2 = (double*)take(sizeof(double) * ld2);
+    t.lndetX2 = (double2*)take(sizeof(double2) * W);
+    t.Gk = (double2*)take(sizeof(double2) * mat * W);
+    t.dGk = (double2*)take(sizeof(double2) * mat * W);
+    t.rk = (double2*)take(sizeof(double2) * (size_t)NQ * W);
+    t.drk = (double2*)take(sizeof(double2) * (size_t)NQ * W);
+    t.dcq = (double2*)take(sizeof(double2) * (size_t)NQ * W);
+    t.dexpo = (double2*)take(sizeof(double2) * W);
+    t.dV = (double2*)take(sizeof(double2) * mat * W);
+    t.dV2 = (double2*)take(sizeof(double2) * mat * W);
+    t.dV3 = (double2*)take(sizeof(double2) * mat * W);
+    t.dV4 = (double2*)take(sizeof(double2) * mat * W);
+    t.dE0 = (double2*)take(sizeof(double2) * mat * W);
+    t.dE1 = (double2*)take(sizeof(double2) * mat * W);
+    for (int k = 0; k < 5; ++k) t.dBk[k] = k < std::max(3, s.taylor_nb - 1) ? (double2*)take(sizeof(double2) * mat * W) : nullptr;
   }
   s.bytes = off - s.off_begin;
   d.M = M; d.ld = ld; d.NQ = NQ; d.W = W; d.n = s.n; d.grid_dim = s.gdim; d.grid_c0 = s.gc0;
@@ -522,6 +545,8 @@ GemmParams gp_base(const HostSys& s, const SysDev& d) {
 
 double inv_fact(int j) { double f = 1.0; for (int i = 2; i <= j; ++i) f *= i; return 1.0 / f; }
 
+int horner_step(ftafqmc_ctx* h, HostSys& s, SysDev& d, void* cur, void* nxt, int k, hipStream_t st);
+
 // Y <- K e^V K Y with e^V = sum_{j<=deg} V^j / j! by Paterson-Stockmeyer with blocks of 4:
 // B_k = sum_{r<4} a_{4k+r} V^r and e^V = (((a_deg V^4 + B_top) V^4 + ...) V^4 + B_0), with
 // deg = 4 nb chosen per system (16 in FP64 and 12 in mixed precision on the workloads).  The
@@ -559,18 +584,27 @@ int form_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st, void*
     HIPCHK(timed(h, FTAFQMC_PROF_COEF, st, [&] { return launch_taylor_blocks(d, mixed, t, st); }));
   }
   if (check) HIPCHK(timed(h, FTAFQMC_PROF_COEF, st, [&] { return launch_taylor_norms(d, mixed, st); }));
+  if (!B_out) return FTAFQMC_OK;              // the powers and blocks only (the pathwise chain)
   void* cur = d.E0;
   void* nxt = d.E1;
   for (int k = nb - 2; k >= 0; --k) {
-    GemmParams e = gp_base(s, d);
-    e.tile = s.tile_horner;
-    e.A = cur; e.B = d.V4; e.C = nxt;
-    e.P1 = d.Bk[k]; e.c1 = 1.0;
-    if (k == 0) { e.rs = d.kh; e.cs = d.kh; }            // K e^V K
-    HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(e, prec, st); }));
+    const int rc = horner_step(h, s, d, cur, nxt, k, st);
+    if (rc) return rc;
     std::swap(cur, nxt);
   }
   *B_out = cur;
+  return FTAFQMC_OK;
+}
+
+// One Horner step of the Taylor polynomial: nxt = cur V^4 + B_k, with K on both sides at k = 0.
+int horner_step(ftafqmc_ctx* h, HostSys& s, SysDev& d, void* cur, void* nxt, int k, hipStream_t st) {
+  const bool mixed = s.p.precision == FTAFQMC_MIXED;
+  GemmParams e = gp_base(s, d);
+  e.tile = s.tile_horner;
+  e.A = cur; e.B = d.V4; e.C = nxt;
+  e.P1 = d.Bk[k]; e.c1 = 1.0;
+  if (k == 0) { e.rs = d.kh; e.cs = d.kh; }            // K e^V K
+  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(e, mixed ? GEMM_C32 : GEMM_Z64, st); }));
   return FTAFQMC_OK;
 }
 
@@ -823,8 +857,9 @@ int doubled_greens(ftafqmc_ctx* h, HostSys& s, int k, int literal, hipStream_t s
 }
 
 // One slice of the doubled product: Rd <- [[B, dB], [0, B]] Rd, then the pre-pivoted
-// Cholesky-QR re-factorisation Yd Dd Td with Td <- Ru Td[perm, :].
-int doubled_push(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
+// Cholesky-QR re-factorisation Yd Dd Td with Td <- Ru Td[perm, :]; with `with_inverse` also
+// Tid <- Tid[:, perm] Ru^{-1} (the inverse triangular factor, as the forward path carries it).
+int doubled_push(ftafqmc_ctx* h, HostSys& s, hipStream_t st, bool with_inverse) {
   TanDev& t = s.tan;
   SysDev& dd = t.dd;
   const int M = s.M;
@@ -849,10 +884,42 @@ int doubled_push(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
   const ElimParams e = ep_dd(s, 0, 0);
   HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_elim(e, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_stab_finish_a(dd, st); }));
+  if (with_inverse) {
+    SysDev pv = dd;
+    pv.Ti = t.Tid;
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_stab_build_ti(pv, st); }));
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_elim(e, st); }));
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_stab_finish_b(pv, st); }));
+  }
   HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_permute_rows(t, st); }));
   GemmParams gt = gp_dd(s);
   gt.A = dd.E1; gt.B = dd.E0; gt.C = t.Td;
   HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(gt, GEMM_Z64, st); }));
+  return FTAFQMC_OK;
+}
+
+// The ratio of the step that inserts B_{k+1}: [I + Phi | dPhi] = [I + W - W Gc11 | dW - (dW Gc11 +
+// W Gc12)] from Fcat = [dW | W] and the cyclic doubled Green's function, eliminated in d.aug (the
+// right block then holds (I + Phi)^{-1} dPhi).
+int ratio_solve(ftafqmc_ctx* h, HostSys& s, hipStream_t st) {
+  SysDev& d = s.dev;
+  TanDev& t = s.tan;
+  const int M = s.M, ld = s.ld, W = s.p.n_walkers;
+  GemmParams g;
+  std::memset(&g, 0, sizeof(g));
+  g.W = W; g.role = 1; g.alpha = -1.0; g.c1 = 1.0;
+  g.sA = g.sP = t.bc_stride; g.sB = t.gs_stride; g.sC = d.aug_stride;
+  g.lda = g.ldp = s.ld2; g.ldb = ld; g.ldc = 2 * ld;
+  g.A = t.Fcat + M; g.P1 = t.Fcat + M; g.B = t.Gst; g.C = d.aug; g.cI = 1.0;
+  g.m = M; g.n = M; g.k = M; g.mpad = M; g.npad = ld;
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));
+  g.A = t.Fcat; g.P1 = t.Fcat; g.C = d.aug + ld; g.cI = 0.0; g.k = s.M2;
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));
+  ElimParams e;
+  e.aug = d.aug; e.stride = d.aug_stride; e.lda = 2 * ld; e.M = M; e.rhs_off = ld; e.nrhs = M;
+  e.W = W; e.pivot = 1; e.backsub = 1; e.lndet = nullptr; e.status = t.tstat;
+  e.piv = d.piv; e.ld = ld; e.tri = d.tri;
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_elim(e, st); }));
   return FTAFQMC_OK;
 }
 
@@ -871,24 +938,10 @@ int backward(ftafqmc_ctx* h, HostSys& s, const double* cot, double2* jac, double
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_tan_prep(d, t, (const double2*)B, st); }));
     rc = doubled_greens(h, s, k, 0, st);
     if (rc) return rc;
-    // [I + Phi | dPhi] = [I + W - W Gc11 | dW - (dW Gc11 + W Gc12)], Fcat = [dW | W]
-    GemmParams g;
-    std::memset(&g, 0, sizeof(g));
-    g.W = W; g.role = 1; g.alpha = -1.0; g.c1 = 1.0;
-    g.sA = g.sP = t.bc_stride; g.sB = t.gs_stride; g.sC = d.aug_stride;
-    g.lda = g.ldp = s.ld2; g.ldb = ld; g.ldc = 2 * ld;
-    g.A = t.Fcat + M; g.P1 = t.Fcat + M; g.B = t.Gst; g.C = d.aug; g.cI = 1.0;
-    g.m = M; g.n = M; g.k = M; g.mpad = M; g.npad = ld;
-    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));
-    g.A = t.Fcat; g.P1 = t.Fcat; g.C = d.aug + ld; g.cI = 0.0; g.k = s.M2;
-    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));
-    ElimParams e;
-    e.aug = d.aug; e.stride = d.aug_stride; e.lda = 2 * ld; e.M = M; e.rhs_off = ld; e.nrhs = M;
-    e.W = W; e.pivot = 1; e.backsub = 1; e.lndet = nullptr; e.status = t.tstat;
-    e.piv = d.piv; e.ld = ld; e.tri = d.tri;
-    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_elim(e, st); }));
+    rc = ratio_solve(h, s, st);
+    if (rc) return rc;
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_tan_weight(d, t, k, st); }));
-    rc = doubled_push(h, s, st);
+    rc = doubled_push(h, s, st, false);
     if (rc) return rc;
   }
   int rc = doubled_greens(h, s, s.n, 1, st);                      // lambda: dG_n
@@ -903,6 +956,118 @@ int backward(ftafqmc_ctx* h, HostSys& s, const double* cot, double2* jac, double
 }
 
 hipStream_t lane_stream(ftafqmc_ctx* h, hipStream_t st, int lane) { return lane == 0 ? st : h->side[lane - 1]; }
+
+// ------------------------------------------------------------ pathwise ---
+// The literal doubled Green's function (I + diag(L, L) Rd)^{-1}, L = B_T^lexp, into Gd by the
+// forward path's scale-split solve on the doubled state (Yd, Dd and the inverse factor Tid).
+int pw_literal(ftafqmc_ctx* h, HostSys& s, int lexp, hipStream_t st) {
+  TanDev& t = s.tan;
+  SysDev pv = t.dd;
+  pv.Ti = t.Tid; pv.G = t.Gd; pv.lnbt = t.lnbt2; pv.lndetX = t.lndetX2;
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_greens_form(pv, lexp, st); }));
+  ElimParams e = ep_dd(s, 1, 1);
+  e.lndet = t.lndetX2;
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_elim(e, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_greens_post(pv, lexp, st); }));
+  return FTAFQMC_OK;
+}
+
+// B = K e^V K of the recorded slice (the forward path's own products, bit-identical) and, carried
+// alongside, K (d e^V) K for the Frechet derivative of e^V in the direction dV: with the
+// Paterson-Stockmeyer blocks of B_k = sum_r a_{4k+r} V^r,
+//   (V^2)' = V dV + dV V, (V^3)' = (V^2)' V + V^2 dV, (V^4)' = (V^2)' V^2 + V^2 (V^2)',
+//   B_k' = sum_{r>0} a_{4k+r} (V^r)', and each Horner step E <- E V^4 + B_k gives
+//   E' <- E' V^4 + E (V^4)' + B_k' (K on both sides at the last step).
+int pw_chain(ftafqmc_ctx* h, HostSys& s, hipStream_t st, void** B_out, double2** KdEK_out) {
+  SysDev& d = s.dev;
+  TanDev& t = s.tan;
+  int rc = form_propagator(h, s, d, st, nullptr, false);          // V^2, V^3, V^4 and the blocks
+  if (rc) return rc;
+  const int nb = s.taylor_nb, deg = 4 * nb;
+  auto prod = [&](const void* A, const void* B, void* C, const void* P1, const double* rs) -> int {
+    GemmParams g = gp_base(s, d);
+    g.tile = s.tile_chain;
+    g.A = A; g.B = B; g.C = C;
+    if (P1 == C) g.beta = 1.0;                          // accumulate into C
+    else if (P1) { g.P1 = P1; g.c1 = 1.0; }
+    if (rs) { g.rs = rs; g.cs = rs; }
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));
+    return FTAFQMC_OK;
+  };
+  if ((rc = prod(d.V, t.dV, t.dV2, nullptr, nullptr))) return rc;       // (V^2)'
+  if ((rc = prod(t.dV, d.V, t.dV2, t.dV2, nullptr))) return rc;
+  if ((rc = prod(t.dV2, d.V, t.dV3, nullptr, nullptr))) return rc;      // (V^3)'
+  if ((rc = prod(d.V2, t.dV, t.dV3, t.dV3, nullptr))) return rc;
+  if ((rc = prod(t.dV2, d.V2, t.dV4, nullptr, nullptr))) return rc;     // (V^4)'
+  if ((rc = prod(d.V2, t.dV2, t.dV4, t.dV4, nullptr))) return rc;
+  PwBlocks b;
+  std::memset(&b, 0, sizeof(b));
+  b.nb = nb;
+  for (int k = 0; k < nb; ++k) {
+    b.c[k][0] = k == nb - 1 ? inv_fact(deg) : 0.0;
+    for (int r = 1; r < 4; ++r) b.c[k][r] = inv_fact(4 * k + r);
+  }
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_pw_blocks(d, t, b, st); }));
+  void* cur = d.E0;
+  void* nxt = d.E1;
+  double2* dcur = t.dE0;
+  double2* dnxt = t.dE1;
+  for (int k = nb - 2; k >= 0; --k) {
+    if ((rc = prod(dcur, d.V4, dnxt, t.dBk[k], nullptr))) return rc;
+    if ((rc = prod(cur, t.dV4, dnxt, dnxt, k == 0 ? d.kh : nullptr))) return rc;
+    if ((rc = horner_step(h, s, d, cur, nxt, k, st))) return rc;
+    std::swap(cur, nxt);
+    std::swap(dcur, dnxt);
+  }
+  *B_out = cur;
+  *KdEK_out = dcur;
+  return FTAFQMC_OK;
+}
+
+// Pathwise derivatives of <E> and <N> at tau = beta in mu and lambda: the raw fields of the path
+// held fixed, the force bias (hence V_k, e^{V_k} and the exponent of eq. import) following G_k.
+// One pass per direction over the recorded slices.
+int backward_pathwise(ftafqmc_ctx* h, HostSys& s, const double* cot, double2* jac, double* grad, double2* walker,
+                      hipStream_t st) {
+  SysDev& d = s.dev;
+  TanDev& t = s.tan;
+  const long long mat = d.mat_stride;
+  const double2* fields = (const double2*)s.fields;
+  HIPCHK(launch_tan_init(d, t, st));
+  for (int dir = 0; dir < 2; ++dir) {
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_pw_reset(d, t, st); }));
+    for (int k = 0; k < s.n; ++k) {
+      HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_coef_replay(d, k, st); }));
+      int rc = pw_literal(h, s, s.n - k, st);                         // G_k and dG_k
+      if (rc) return rc;
+      HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_pw_extract(d, t, nullptr, st); }));
+      SysDev gv = d;
+      gv.G = t.Gk; gv.r = t.rk;
+      HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_rq(gv, st); }));
+      SysDev dv = d;
+      dv.G = t.dGk; dv.r = t.drk;
+      HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_rq(dv, st); }));
+      HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_pw_coef(d, t, fields, k, st); }));
+      SysDev fv = d;
+      fv.cq = t.dcq;
+      HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_fill_v(fv, t.dV, 0, st); }));
+      void* B = nullptr;
+      double2* KdEK = nullptr;
+      if ((rc = pw_chain(h, s, st, &B, &KdEK))) return rc;
+      HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_pw_prep(d, t, (const double2*)B, KdEK, dir, st); }));
+      if ((rc = doubled_greens(h, s, k, 0, st))) return rc;
+      if ((rc = ratio_solve(h, s, st))) return rc;
+      HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_pw_weight(d, t, k, dir, st); }));
+      if ((rc = doubled_push(h, s, st, true))) return rc;
+    }
+    int rc = pw_literal(h, s, 0, st);                                   // dG_n at tau = beta
+    if (rc) return rc;
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_pw_extract(d, t, t.dG + (long long)dir * d.W * mat, st); }));
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_energy_tangent(d, t, dir, st); }));
+  }
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_tan_mean(d, t, cot, jac, grad, walker, st); }));
+  return FTAFQMC_OK;
+}
 
 // The launch sequence of ftafqmc_propagate for n_slices slices (eager, or under graph capture).
 // Each system runs on its own lanes: the side lanes start after the work already queued on the
@@ -929,6 +1094,8 @@ int run_slices(ftafqmc_ctx* h, const void* const* d_fields, int n_slices, hipStr
       any = true;
       const hipStream_t s0 = lane_stream(h, st, s.lane0);
       if (timing && !started[i]) { HIPCHK(hipEventRecord(s.t0, s0)); started[i] = 1; }
+      if (s.k == 0) { s.fields = d_fields[i]; s.fields_ok = true; }
+      else if (d_fields[i] != s.fields) s.fields_ok = false;
       const bool last = j + 1 == n_slices || s.k + 1 == s.n;
       rc = step(h, s, views[i], (const double2*)d_fields[i], last, st);
       if (rc) break;
@@ -1095,6 +1262,7 @@ int init_ueg_impl(const ftafqmc_params* p, int n_sys, void* d_workspace, size_t 
     if (e == hipSuccess) e = up(d.rbidx, s.rbidx.data(), sizeof(int) * s.rbidx.size());
     if (e == hipSuccess) e = up(d.grid, s.grid.data(), sizeof(short) * s.grid.size());
     if (e == hipSuccess) e = up(d.flat, s.flat.data(), sizeof(int) * s.M);
+    if (e == hipSuccess && s.ckpt) e = up(s.tan.lnbt2, s.lnbt2.data(), sizeof(double) * s.ld2);
     // the host tables are no longer needed once the copies have completed
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { ftafqmc_destroy(h); return lib_init_error(FTAFQMC_E_HIP, "table upload failed"); }
@@ -1214,11 +1382,16 @@ int ftafqmc_backward(ftafqmc_t h, int sys, int mode, const double* d_cot, void* 
                      void* d_walker, void* stream) {
   int rc = check_handle(h, sys);
   if (rc) return rc;
-  if (mode != FTAFQMC_FROZEN_PATH) return h->set(FTAFQMC_E_UNSUPPORTED, "only the frozen-path mode is built");
+  if (mode != FTAFQMC_FROZEN_PATH && mode != FTAFQMC_PATHWISE) return h->set(FTAFQMC_E_ARG, "unknown mode");
   HostSys& s = h->sys[sys];
   if (!s.ckpt) return h->set(FTAFQMC_E_STATE, "the system was initialised without FTAFQMC_CHECKPOINT");
   if (s.k != s.n) return h->set(FTAFQMC_E_STATE, "the path has not reached tau = beta");
   if (d_grad && !d_cot) return h->set(FTAFQMC_E_ARG, "d_grad needs d_cot");
+  if (mode == FTAFQMC_PATHWISE) {
+    if (!s.fields_ok || !s.fields)
+      return h->set(FTAFQMC_E_STATE, "the pathwise mode reads the path's fields: one buffer must serve every slice");
+    return backward_pathwise(h, s, d_cot, (double2*)d_jac, d_grad, (double2*)d_walker, (hipStream_t)stream);
+  }
   return backward(h, s, d_cot, (double2*)d_jac, d_grad, (double2*)d_walker, (hipStream_t)stream);
 }
 
@@ -1379,6 +1552,14 @@ int ftafqmc_system_times(ftafqmc_t h, double* h_ms) {
     if (e != hipSuccess) return h->set(FTAFQMC_E_HIP, std::string("system times: ") + hipGetErrorString(e));
     h_ms[i] = ms;
   }
+  return FTAFQMC_OK;
+}
+
+int ftafqmc_kink_flags(ftafqmc_t h, int sys, double threshold, int* d_flags, void* stream) {
+  int rc = check_handle(h, sys);
+  if (rc) return rc;
+  if (!d_flags) return h->set(FTAFQMC_E_ARG, "null flags");
+  HIPCHK(launch_kink_flags(h->sys[sys].dev, threshold, d_flags, (hipStream_t)stream));
   return FTAFQMC_OK;
 }
 

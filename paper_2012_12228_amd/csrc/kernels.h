@@ -123,6 +123,18 @@ struct TanDev {
   double2* lndet_dummy;   // [W] (the stabilisation records a permutation parity there)
   long long bc_stride;    // ld*ld2
   long long gs_stride;    // ld2*ld
+  // pathwise mode (raw fields fixed, force bias recomputed)
+  double2* Tid;           // [W][ld2][ld2] inverse of Td (carried like the forward's T^{-1})
+  double2* Gd;            // [W][ld2][ld2] literal doubled Green's function at the current slice
+  double* lnbt2;          // [ld2] ln diag B_T repeated for both halves
+  double2* lndetX2;       // [W] (the elimination records its ln det there)
+  double2* Gk; double2* dGk;   // [W][ld][ld] G_k and dG_k (blocks of Gd)
+  double2* rk; double2* drk;   // [W][NQ] r_Q of G_k and its derivative
+  double2* dcq;           // [W][NQ] derivative of the shifted coefficients
+  double2* dexpo;         // [W] derivative of the exponent of eq. import for the current slice
+  double2* dV; double2* dV2; double2* dV3; double2* dV4;   // [W][ld][ld] derivatives of V^j
+  double2* dE0; double2* dE1;                               // [W][ld][ld] Horner derivatives
+  double2* dBk[5];        // [W][ld][ld] derivatives of the Paterson-Stockmeyer blocks
 };
 
 hipError_t launch_coef_replay(const SysDev& s, int k, hipStream_t st);             // V from rec_c[k]
@@ -135,6 +147,16 @@ hipError_t launch_permute_rows(const TanDev& t, hipStream_t st);                
 hipError_t launch_energy_tangent(const SysDev& s, const TanDev& t, int dir, hipStream_t st);
 hipError_t launch_tan_mean(const SysDev& s, const TanDev& t, const double* cot, double2* jac,
                            double* grad, double2* walker, hipStream_t st);
+// pathwise mode
+hipError_t launch_pw_reset(const SysDev& s, const TanDev& t, hipStream_t st);   // Yd, Td, Tid = I, Dd = 1
+hipError_t launch_pw_extract(const SysDev& s, const TanDev& t, double2* dG_out, hipStream_t st);  // Gk, dGk
+hipError_t launch_pw_coef(const SysDev& s, const TanDev& t, const double2* fields, int k, hipStream_t st);
+struct PwBlocks { int nb; double c[6][4]; };   // dB_k = c1 dV + c2 dV2 + c3 dV3 (+ c0 dV4 for the top)
+hipError_t launch_pw_blocks(const SysDev& s, const TanDev& t, const PwBlocks& b, hipStream_t st);
+hipError_t launch_pw_prep(const SysDev& s, const TanDev& t, const double2* B, const double2* KdEK, int dir,
+                          hipStream_t st);
+hipError_t launch_pw_weight(const SysDev& s, const TanDev& t, int k, int dir, hipStream_t st);
+hipError_t launch_kink_flags(const SysDev& s, double threshold, int* flags, hipStream_t st);
 
 // Truncation check of the Taylor polynomial of e^V: per-chunk column 1-norms of V and V^4 into
 // tnorm (the weight kernel turns them into a bound on the remainder and flags the walker).
@@ -151,6 +173,7 @@ size_t pop_select_lds(int W);
 hipError_t launch_record_stats(const SysDev& s, int nrec, double* stats, double* avg, hipStream_t st);
 hipError_t launch_init_state(const SysDev& s, hipStream_t st);
 hipError_t launch_coef_v(const SysDev& s, const double2* fields, int k, int mixed, hipStream_t st);
+hipError_t launch_fill_v(const SysDev& s, void* V, int mixed, hipStream_t st);   // V from s.cq
 // G of (I + B_T^lexp R)^{-1}: the transposed augmented system, and G from its solution
 hipError_t launch_greens_form(const SysDev& s, int lexp, hipStream_t st);
 hipError_t launch_greens_post(const SysDev& s, int lexp, hipStream_t st);

@@ -827,6 +827,12 @@ hipError_t launch_init_state(const SysDev& s, hipStream_t st) {
   init_state_kernel<<<1024, NT, 0, st>>>(s);
   return hipGetLastError();
 }
+hipError_t launch_fill_v(const SysDev& s, void* V, int mixed, hipStream_t st) {
+  const int chunks = (s.ld + V_ROWS - 1) / V_ROWS;
+  if (mixed) fill_v_kernel<float2><<<tiles_blocks(s, chunks), NT, 0, st>>>(s, (float2*)V, chunks);
+  else fill_v_kernel<double2><<<tiles_blocks(s, chunks), NT, 0, st>>>(s, (double2*)V, chunks);
+  return hipGetLastError();
+}
 hipError_t launch_coef_v(const SysDev& s, const double2* fields, int k, int mixed, hipStream_t st) {
   coef_kernel<<<s.W, NT, 0, st>>>(s, fields, k);
   hipError_t e = hipGetLastError();

@@ -368,6 +368,152 @@ __global__ __launch_bounds__(NT) void tan_mean_kernel(SysDev s, TanDev t, const 
   }
 }
 
+// ------------------------------------------------------------ pathwise ---
+// Raw fields held fixed while mu or lambda moves: the force bias of every slice follows G_k, so
+// V_k, e^{V_k} (Frechet derivative), B_k and the exponent of eq. import move too.  One pass per
+// direction carries the doubled product with its inverse triangular factor Tid (so that the
+// literal doubled Green's function (I + diag(L, L) Rd)^{-1} at every slice comes from the forward
+// path's own scale-split solve), whose blocks are G_k and dG_k.
+
+__global__ __launch_bounds__(NT) void pw_reset_kernel(SysDev s, TanDev t) {
+  const long long mat = (long long)t.ld2 * t.ld2;
+  const long long total = (long long)s.W * mat;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < total; e += (long long)gridDim.x * NT) {
+    const long long loc = e % mat;
+    const int i = (int)(loc / t.ld2), j = (int)(loc % t.ld2);
+    const double2 v = (i == j && i < t.M2) ? make_double2(1.0, 0.0) : zero2();
+    t.dd.Y[e] = v;
+    t.Td[e] = v;
+    t.Tid[e] = v;
+  }
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < (long long)s.W * t.ld2; e += (long long)gridDim.x * NT)
+    t.dd.D[e] = ((int)(e % t.ld2) < t.M2) ? 1.0 : 0.0;
+  for (long long w = (long long)blockIdx.x * NT + threadIdx.x; w < s.W; w += (long long)gridDim.x * NT) {
+    t.alive[w] = 1;
+    t.lndet_dummy[w] = zero2();
+  }
+}
+
+// Gk = Gd[:M, :M], dGk = Gd[:M, M:2M] (and dG_out = dGk when given)
+__global__ __launch_bounds__(NT) void pw_extract_kernel(SysDev s, TanDev t, double2* dG_out) {
+  const long long per = (long long)s.ld * s.ld;
+  const long long total = (long long)s.W * per;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < total; e += (long long)gridDim.x * NT) {
+    const long long w = e / per;
+    const int loc = (int)(e - w * per);
+    const int i = loc / s.ld, j = loc - i * s.ld;
+    double2 g = zero2(), dg = zero2();
+    if (i < s.M && j < s.M) {
+      const double2* Gd = t.Gd + w * t.dd.mat_stride + (long long)i * t.ld2;
+      g = Gd[j];
+      dg = Gd[s.M + j];
+    }
+    t.Gk[e] = g;
+    t.dGk[e] = dg;
+    if (dG_out) dG_out[e] = dg;
+  }
+}
+
+// dc_Q = -2 dtau v_Q dr_-Q (the derivative of c_Q = i s_Q (z_Q + conj z_-Q) - 2 dtau v_Q r_-Q) and
+// d(exponent) = sum_Q (x_A - xbar_A) dxbar_A + (x_B - xbar_B) dxbar_B with
+// xbar_A = -2i s_Q (r_Q + r_-Q), xbar_B = 2 s_Q (r_Q - r_-Q) and their derivatives in dr.
+__global__ __launch_bounds__(NT) void pw_coef_kernel(SysDev s, TanDev t, const double2* fields, int k) {
+  __shared__ double red[8];
+  const int w = blockIdx.x;
+  if (w >= s.W) return;
+  const double2* z = fields + ((long long)w * s.n + k) * s.NQ;
+  const double2* r = t.rk + (long long)w * s.NQ;
+  const double2* dr = t.drk + (long long)w * s.NQ;
+  double2 acc = zero2();
+  for (int q = threadIdx.x; q < s.NQ; q += NT) {
+    const int nq = s.neg[q];
+    const double sqv = s.sq[q];
+    const double2 rq = r[q], rn = r[nq], dq = dr[q], dn = dr[nq], zq = z[q];
+    t.dcq[(long long)w * s.NQ + q] = cscale(dn, -2.0 * s.dtau * s.vq[q]);
+    const double2 sp = cadd(rq, rn), sm = csub(rq, rn), dsp = cadd(dq, dn), dsm = csub(dq, dn);
+    const double2 xa = make_double2(2.0 * sqv * sp.y, -2.0 * sqv * sp.x);      // -2i s (r_q + r_-q)
+    const double2 xb = cscale(sm, 2.0 * sqv);
+    const double2 dxa = make_double2(2.0 * sqv * dsp.y, -2.0 * sqv * dsp.x);
+    const double2 dxb = cscale(dsm, 2.0 * sqv);
+    const double2 ua = make_double2(zq.x - xa.x, -xa.y), ub = make_double2(zq.y - xb.x, -xb.y);
+    acc = cadd(acc, cadd(cmul(ua, dxa), cmul(ub, dxb)));
+  }
+  acc = block_csum_256(acc, red);
+  if (threadIdx.x == 0) t.dexpo[w] = acc;
+}
+
+// dB_k = c[k][1] dV + c[k][2] dV2 + c[k][3] dV3 for k < nb - 1 (into dBk[k]); the top term
+// c[nb-1][0] dV4 + c[nb-1][1] dV + c[nb-1][2] dV2 + c[nb-1][3] dV3 into dE0.
+__global__ __launch_bounds__(NT) void pw_blocks_kernel(SysDev s, TanDev t, PwBlocks b) {
+  const long long total = (long long)s.W * s.mat_stride;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < total; e += (long long)gridDim.x * NT) {
+    const double2 v1 = t.dV[e], v2 = t.dV2[e], v3 = t.dV3[e], v4 = t.dV4[e];
+    for (int k = 0; k < b.nb; ++k) {
+      double2 x = cadd(cscale(v1, b.c[k][1]), cadd(cscale(v2, b.c[k][2]), cscale(v3, b.c[k][3])));
+      if (k == b.nb - 1) t.dE0[e] = cadd(x, cscale(v4, b.c[k][0]));
+      else t.dBk[k][e] = x;
+    }
+  }
+}
+
+// Bcat = [B | dB], Fcat = [dB B_T^{-1} | B B_T^{-1} - I] with dB = K dE K + dK E K + K E dK:
+// along mu (dir 0) dK = dtau/2 K, along lambda (dir 1) dK = -dtau/2 eps K.
+__global__ __launch_bounds__(NT) void pw_prep_kernel(SysDev s, TanDev t, const double2* B, const double2* KdEK, int dir) {
+  const long long per = (long long)s.ld * t.ld2;
+  const long long total = (long long)s.W * per;
+  const int M = s.M;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < total; e += (long long)gridDim.x * NT) {
+    const long long w = e / per;
+    const int loc = (int)(e - w * per);
+    const int i = loc / t.ld2, c = loc - i * t.ld2;
+    double2 bc = zero2(), fc = zero2();
+    if (i < M && c < 2 * M) {
+      const int j = c < M ? c : c - M;
+      const long long o = w * s.mat_stride + (long long)i * s.ld + j;
+      const double2 b = B[o];
+      const double btinv = exp(-s.lnbt[j]);
+      const double f = dir == 0 ? s.dtau : -0.5 * s.dtau * (s.eps[i] + s.eps[j]);
+      const double2 db = cadd(cscale(b, f), KdEK[o]);
+      if (c < M) { bc = b; fc = cscale(db, btinv); }
+      else { bc = db; fc = cscale(b, btinv); if (i == j) fc.x -= 1.0; }
+    }
+    t.Bcat[e] = bc;
+    t.Fcat[e] = fc;
+  }
+}
+
+// d ln S_k = 2 tr((I + Phi)^{-1} dPhi) from the solve; d ln w (direction dir) +=
+// Re d ln S + Re d(exponent) - tan(theta_k) Im d ln S while the walker survives the slice.
+__global__ __launch_bounds__(NT) void pw_weight_kernel(SysDev s, TanDev t, int k, int dir) {
+  __shared__ double red[8];
+  const int w = blockIdx.x;
+  if (w >= s.W) return;
+  const double2* aug = s.aug + (long long)w * s.aug_stride;
+  double2 tr = zero2();
+  for (int i = threadIdx.x; i < s.M; i += NT) tr = cadd(tr, aug[(long long)i * 2 * s.ld + s.ld + i]);
+  tr = block_csum_256(tr, red);
+  if (threadIdx.x != 0 || !t.alive[w]) return;
+  const double th = s.slice_theta[(long long)w * s.n + k];
+  const double2 d = cscale(tr, 2.0);
+  const double2 de = t.dexpo[w];
+  if (!(cos(th) > 0.0) || !isfinite(d.x) || !isfinite(d.y)) { t.alive[w] = 0; return; }
+  t.dlnw[2 * w + dir] += d.x + de.x - tan(th) * d.y;
+}
+
+// flags[w] = 1 when the smallest cos(theta_k) over the slices walker w survived is below
+// `threshold` (its weight is not differentiable at a phaseless kill), else 0.
+__global__ __launch_bounds__(NT) void kink_kernel(SysDev s, double threshold, int* flags) {
+  const int w = blockIdx.x * NT + threadIdx.x;
+  if (w >= s.W) return;
+  int f = 0;
+  for (int k = 0; k < s.n; ++k) {
+    const double c = cos(s.slice_theta[(long long)w * s.n + k]);
+    if (!(c > 0.0)) break;                      // the forward killed it here
+    if (c < threshold) { f = 1; break; }
+  }
+  flags[w] = f;
+}
+
 int grid_for(long long total) {
   const long long b = (total + NT - 1) / NT;
   return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
@@ -418,5 +564,35 @@ hipError_t launch_energy_tangent(const SysDev& s, const TanDev& t, int dir, hipS
 hipError_t launch_tan_mean(const SysDev& s, const TanDev& t, const double* cot, double2* jac, double* grad,
                            double2* walker, hipStream_t st) {
   tan_mean_kernel<<<1, NT, 0, st>>>(s, t, cot, jac, grad, walker);
+  return hipGetLastError();
+}
+hipError_t launch_pw_reset(const SysDev& s, const TanDev& t, hipStream_t st) {
+  pw_reset_kernel<<<grid_for((long long)s.W * t.ld2 * t.ld2), NT, 0, st>>>(s, t);
+  return hipGetLastError();
+}
+hipError_t launch_pw_extract(const SysDev& s, const TanDev& t, double2* dG_out, hipStream_t st) {
+  pw_extract_kernel<<<grid_for((long long)s.W * s.ld * s.ld), NT, 0, st>>>(s, t, dG_out);
+  return hipGetLastError();
+}
+hipError_t launch_pw_coef(const SysDev& s, const TanDev& t, const double2* fields, int k, hipStream_t st) {
+  pw_coef_kernel<<<s.W, NT, 0, st>>>(s, t, fields, k);
+  return hipGetLastError();
+}
+hipError_t launch_pw_blocks(const SysDev& s, const TanDev& t, const PwBlocks& b, hipStream_t st) {
+  if (b.nb < 1 || b.nb > 6) return hipErrorInvalidValue;
+  pw_blocks_kernel<<<grid_for((long long)s.W * s.mat_stride), NT, 0, st>>>(s, t, b);
+  return hipGetLastError();
+}
+hipError_t launch_pw_prep(const SysDev& s, const TanDev& t, const double2* B, const double2* KdEK, int dir,
+                          hipStream_t st) {
+  pw_prep_kernel<<<grid_for((long long)s.W * s.ld * t.ld2), NT, 0, st>>>(s, t, B, KdEK, dir);
+  return hipGetLastError();
+}
+hipError_t launch_pw_weight(const SysDev& s, const TanDev& t, int k, int dir, hipStream_t st) {
+  pw_weight_kernel<<<s.W, NT, 0, st>>>(s, t, k, dir);
+  return hipGetLastError();
+}
+hipError_t launch_kink_flags(const SysDev& s, double threshold, int* flags, hipStream_t st) {
+  kink_kernel<<<(s.W + NT - 1) / NT, NT, 0, st>>>(s, threshold, flags);
   return hipGetLastError();
 }

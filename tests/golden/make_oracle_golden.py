@@ -5,9 +5,11 @@ sampled walker it runs the FP64 oracle over the whole path and keeps, at every
 energy record (each stabilisation boundary and the last slice): E_1, E_2, E, N,
 ln w and the status; plus the final Green's function's diagonal and first rows.
 For the derivative workload it also keeps each sampled walker's frozen-path
-derivatives (d ln w, dE, dN in mu and in lambda) from oracle.tangent.
+derivatives (d ln w, dE, dN in mu and in lambda) from oracle.tangent, and (mode pathwise)
+their pathwise derivatives with the raw fields held fixed.
 Usage: python tests/golden/make_oracle_golden.py [workload ...]
        python tests/golden/make_oracle_golden.py tangent
+       python tests/golden/make_oracle_golden.py pathwise
 """
 import os
 import sys
@@ -53,13 +55,18 @@ def one(args):
 
 
 def one_tangent(args):
-    name, w = args
+    name, w, mode = args
     from threadpoolctl import threadpool_limits
     sd = si.WORKLOADS[name]["systems"][0]
     s = ueg.UEGSystem(sd["n_elec"], sd["rs"], sd["theta"], sd["nmax2"], sd["dtau"], stab_every=sd["stab_every"])
     z = si.walker_fields(si.system_seed(name, 0), w, s.n_slices, s.NQ)
-    with threadpool_limits(2):
-        fwd, tans = tangent.walker_tangents(s, z)
+    with threadpool_limits(1):
+        if mode == "pathwise":
+            tans = {}
+            for p in ("mu", "kscale"):
+                fwd, tans[p] = tangent.pathwise_tangent(s, z, p)
+        else:
+            fwd, tans = tangent.walker_tangents(s, z)
     out = dict(logw=fwd["logw"], status=fwd["status"], E=fwd["E"]["E"], N=fwd["E"]["N"])
     for p, t in tans.items():
         for k in ("dlogw", "dE", "dN", "dE1", "dE2"):
@@ -68,17 +75,17 @@ def one_tangent(args):
     return out
 
 
-def main_tangent():
-    jobs = [(n, w) for n, ws in TANGENT_SAMPLES.items() for w in ws]
+def main_tangent(mode="tangent"):
+    jobs = [(n, w, mode) for n, ws in TANGENT_SAMPLES.items() for w in ws]
     with ProcessPoolExecutor(max_workers=min(4, len(jobs))) as ex:
         results = list(ex.map(one_tangent, jobs))
     for n in TANGENT_SAMPLES:
         arrays = {}
-        for (jn, w), r in zip(jobs, results):
+        for (jn, w, _), r in zip(jobs, results):
             if jn == n:
                 for k, v in r.items():
                     arrays["w%d_%s" % (w, k)] = np.asarray(v)
-        fn = os.path.join(HERE, "oracle_tangent_%s.npz" % n)
+        fn = os.path.join(HERE, "oracle_%s_%s.npz" % (mode, n))
         np.savez_compressed(fn, **arrays)
         print("wrote", fn, os.path.getsize(fn), "bytes")
 
@@ -102,7 +109,7 @@ def main(names):
 
 
 if __name__ == "__main__":
-    if sys.argv[1:] == ["tangent"]:
-        main_tangent()
+    if sys.argv[1:] in (["tangent"], ["pathwise"]):
+        main_tangent(sys.argv[1])
     else:
         main(sys.argv[1:] or list(SAMPLES))

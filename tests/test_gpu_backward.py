@@ -1,7 +1,9 @@
-"""Frozen-path derivatives on the GPU (ftafqmc_backward, through the C ABI) against the oracle.
+"""Derivatives on the GPU (ftafqmc_backward, through the C ABI) against the oracle, in both
+modes: the frozen path (shifted fields fixed) and the pathwise derivative (raw fields fixed,
+the force bias following G_k).
 
-The oracle's tangent (oracle.tangent, pinned by central differences, closed forms and
-80-digit products in test_oracle_tangent.py) runs on the same seeded fields.  Both sides
+The oracle's tangents (oracle.tangent, pinned by central differences, closed forms and
+80-digit products in test_oracle_tangent.py) run on the same seeded fields.  Both sides
 differentiate their own recorded path; the two paths agree to the FP64 parity bar, and so
 must the derivatives:
   per walker  d ln w, dE, dN along mu and lambda: |gpu - oracle| <= 1e-10 max(1, |oracle|);
@@ -11,6 +13,7 @@ import os
 
 import numpy as np
 import pytest
+from threadpoolctl import threadpool_limits
 
 torch = pytest.importorskip("torch")
 
@@ -40,26 +43,38 @@ def oracle_system(sd):
                          stab_every=sd.get("stab_every", 10), mu=sd.get("mu"), kscale=sd.get("kscale", 1.0))
 
 
-def gpu_backward(F, sd, flds):
+def gpu_backward(F, sd, flds, mode=0, kink=None):
     sd = dict(sd, precision=F.FTAFQMC_FP64, flags=F.FTAFQMC_CHECKPOINT)
     ctx = F.Context(sd)
-    ctx.propagate(torch.from_numpy(np.ascontiguousarray(flds)).cuda())
+    dev_fields = torch.from_numpy(np.ascontiguousarray(flds)).cuda()   # held: the pathwise mode re-reads it
+    ctx.propagate(dev_fields)
     e = ctx.energy()
-    b = ctx.backward(cot=[0.7, -1.3])
+    b = ctx.backward(cot=[0.7, -1.3], mode=mode)
+    flags = ctx.kink_flags(kink) if kink is not None else None
     torch.cuda.synchronize()
     out = dict(local=e["local"].cpu().numpy(), mean=e["mean"].cpu().numpy(), logw=e["logw"].cpu().numpy(),
                status=e["status"].cpu().numpy(), jac=b["jac"].cpu().numpy(), grad=b["grad"].cpu().numpy(),
                walker=b["walker"].cpu().numpy())
+    if flags is not None:
+        out["kink"] = flags.cpu().numpy()
     ctx.close()
     return out
 
 
-def check_against_oracle(s, flds, g, label):
+def pathwise_tangents(s, z):
+    out = {}
+    for p in ("mu", "kscale"):
+        fwd, out[p] = tangent.pathwise_tangent(s, z, p)
+    return fwd, out
+
+
+def check_against_oracle(s, flds, g, label, walker_fn=tangent.walker_tangents):
     W = flds.shape[0]
     lw, st, E, N = [], [], [], []
     d = {p: dict(dlogw=[], dE=[], dN=[]) for p in ("mu", "kscale")}
     for w in range(W):
-        fwd, tans = tangent.walker_tangents(s, flds[w])
+        with threadpool_limits(1):          # small dense products: BLAS threads only add overhead
+            fwd, tans = walker_fn(s, flds[w])
         lw.append(fwd["logw"]); st.append(fwd["status"]); E.append(fwd["E"]["E"]); N.append(fwd["E"]["N"])
         assert g["status"][w] == fwd["status"], (label, w)
         for j, p in enumerate(("mu", "kscale")):
@@ -108,18 +123,19 @@ def test_backward_at_cond_1e30():
     check_against_oracle(s, flds, gpu_backward(F, sd, flds), "m7")
 
 
-def test_backward_m123_full_size_sampled():
-    """The derivative workload at full size (M = 123, n = 174, 128 walkers): sampled walkers
-    against stored oracle derivatives, and the ensemble reduction against the GPU's own
-    per-walker values."""
+@pytest.mark.parametrize("mode", ["tangent", "pathwise"])
+def test_backward_m123_full_size_sampled(mode):
+    """The derivative workload at full size (M = 123, n = 174, 128 walkers), frozen path and
+    pathwise: sampled walkers against stored oracle derivatives, and the ensemble reduction
+    against the GPU's own per-walker values."""
     F = _F()
     name = "ueg_n38_m123"
     sd = si.WORKLOADS[name]["systems"][0]
     s = oracle_system(sd)
     W = sd["walkers"]
     flds = si.fields(si.system_seed(name, 0), W, s.n_slices, s.NQ)
-    g = gpu_backward(F, sd, flds)
-    gold = np.load(os.path.join(GOLDEN, "oracle_tangent_%s.npz" % name))
+    g = gpu_backward(F, sd, flds, mode=F.PATHWISE if mode == "pathwise" else F.FROZEN_PATH)
+    gold = np.load(os.path.join(GOLDEN, "oracle_%s_%s.npz" % (mode, name)))
     ws = sorted({int(k.split("_")[0][1:]) for k in gold.files})
     assert ws
     for w in ws:
@@ -178,3 +194,102 @@ def test_autograd_function_contracts_the_cotangents():
     ctx.close()
     assert float(gmu) == pytest.approx(2.0 * jac[0].real - 0.5 * jac[1].real, rel=1e-13)
     assert float(glam) == pytest.approx(2.0 * jac[2].real - 0.5 * jac[3].real, rel=1e-13)
+
+
+# ------------------------------------------------------------------ pathwise ---
+
+def test_pathwise_m19_all_walkers():
+    """Raw fields fixed: V_k, e^{V_k} and the exponent of eq. import follow G_k; every walker of
+    the M = 19 workload against oracle.tangent.pathwise_tangent, and the kink flags against the
+    oracle's smallest cos(theta_k)."""
+    F = _F()
+    sd = si.WORKLOADS["ueg_n14_m19"]["systems"][0]
+    s = oracle_system(sd)
+    flds = si.fields(si.system_seed("ueg_n14_m19", 0), sd["walkers"], s.n_slices, s.NQ)
+    g = gpu_backward(F, sd, flds, mode=F.PATHWISE, kink=0.5)
+    check_against_oracle(s, flds, g, "pw m19", walker_fn=pathwise_tangents)
+    with threadpool_limits(1):
+        margins = [tangent.kink_margin(path.run_walker(s, z)) for z in flds]
+    for w, m in enumerate(margins):
+        if m != -1.0 and abs(m - 0.5) > 1e-9:          # -1: no slice survived, nothing to flag
+            assert g["kink"][w] == int(m < 0.5), (w, m, g["kink"][w])
+
+
+def test_pathwise_ragged_m57_kscale_mu():
+    """M = 57 (2M = 114, ragged against the tiles), lambda != 1, explicit mu, stabilisation
+    every 4 slices in the forward (the doubled product is re-factorised every slice)."""
+    F = _F()
+    sd = dict(n_elec=38, rs=1.0, theta=0.25, nmax2=5, dtau=0.05, stab_every=4, walkers=6, kscale=0.9, mu=1.5)
+    s = oracle_system(sd)
+    flds = si.fields(4242, sd["walkers"], s.n_slices, s.NQ)
+    check_against_oracle(s, flds, gpu_backward(F, sd, flds, mode=F.PATHWISE), "pw m57",
+                         walker_fn=pathwise_tangents)
+
+
+def test_pathwise_at_cond_1e30():
+    """M = 7, Theta = 0.035: the doubled literal Green's function at every slice comes from the
+    scale-split solve across ~30 decades."""
+    F = _F()
+    sd = dict(n_elec=2, rs=0.5, theta=0.035, nmax2=1, dtau=0.05, stab_every=1, walkers=8)
+    s = oracle_system(sd)
+    flds = si.fields(5, sd["walkers"], s.n_slices, s.NQ)
+    check_against_oracle(s, flds, gpu_backward(F, sd, flds, mode=F.PATHWISE), "pw m7",
+                         walker_fn=pathwise_tangents)
+
+
+def test_pathwise_needs_one_field_buffer():
+    """The pathwise mode re-reads the raw fields: a path propagated in two calls on the same
+    buffer differentiates like one call; a path whose slices came from two buffers is refused."""
+    F = _F()
+    sd = dict(si.WORKLOADS["ueg_n14_m19"]["systems"][0], walkers=8)
+    s = oracle_system(sd)
+    flds = torch.from_numpy(si.fields(3, 8, s.n_slices, s.NQ)).cuda()
+    cfg = dict(sd, flags=F.FTAFQMC_CHECKPOINT)
+    ctx = F.Context(cfg)
+    ctx.propagate(flds)
+    ctx.energy()
+    whole = ctx.backward(mode=F.PATHWISE)["walker"].cpu().numpy()
+    ctx.close()
+    ctx = F.Context(cfg)
+    ctx.propagate(flds, n_slices=5)
+    ctx.propagate(flds, n_slices=s.n_slices - 5)
+    ctx.energy()
+    split = ctx.backward(mode=F.PATHWISE)["walker"].cpu().numpy()
+    ctx.close()
+    assert np.array_equal(whole, split)
+    ctx = F.Context(cfg)
+    ctx.propagate(flds, n_slices=5)
+    ctx.propagate(flds.clone(), n_slices=s.n_slices - 5)
+    ctx.energy()
+    with pytest.raises(RuntimeError, match="E_STATE"):
+        ctx.backward(mode=F.PATHWISE)
+    ctx.close()
+    ctx = F.Context(cfg)
+    ctx.propagate(flds)
+    with pytest.raises(RuntimeError, match="E_ARG"):
+        ctx.backward(mode=7)
+    ctx.close()
+
+
+def test_pathwise_autograd_function():
+    """PathwiseMeans: torch.autograd gradients equal the contraction of the pathwise Jacobian
+    with the cotangents, and differ from the frozen-path ones."""
+    F = _F()
+    sd = dict(si.WORKLOADS["ueg_n14_m19"]["systems"][0], walkers=16)
+    s = oracle_system(sd)
+    flds = torch.from_numpy(si.fields(77, 16, s.n_slices, s.NQ)).cuda()
+    grads = {}
+    for fn in (F.PathwiseMeans, F.FrozenPathMeans):
+        mu = torch.tensor(s.mu_T + 0.1, dtype=torch.float64, device="cuda", requires_grad=True)
+        lam = torch.tensor(1.05, dtype=torch.float64, device="cuda", requires_grad=True)
+        E, N = fn.apply(mu, lam, sd, flds)
+        grads[fn] = [float(x) for x in torch.autograd.grad(2.0 * E - 0.5 * N, (mu, lam))]
+    ctx = F.Context(dict(sd, mu=s.mu_T + 0.1, kscale=1.05, flags=F.FTAFQMC_CHECKPOINT))
+    ctx.propagate(flds)
+    ctx.energy()
+    jac = ctx.backward(mode=F.PATHWISE)["jac"].cpu().numpy()
+    ctx.close()
+    gp = grads[F.PathwiseMeans]
+    assert gp[0] == pytest.approx(2.0 * jac[0].real - 0.5 * jac[1].real, rel=1e-13)
+    assert gp[1] == pytest.approx(2.0 * jac[2].real - 0.5 * jac[3].real, rel=1e-13)
+    assert abs(gp[0] - grads[F.FrozenPathMeans][0]) > 1e-6 * abs(gp[0])
