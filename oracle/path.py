@@ -193,13 +193,15 @@ def shifted_one_body(sys, G, z_k):
 
 
 def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, stop_after=None,
-               record_path=False, modified=False):
+               record_path=False, modified=False, make_walker=None):
     """Propagate one walker from tau = 0 to tau = beta with fields z[k, q].
 
     stop_after: end the path after that many slices (a bounded sample for timing).
     record_path: also return the sampled path, i.e. the shifted one-body matrix V_k and the
     weight exponent of every slice (out["path"]), so that replay_walker can re-run it.
     modified: the constraint of the modified overlap ratio, eq. ztfix (see Walker).
+    make_walker: a factory for the walker object (default Walker(sys, modified)); the low-rank
+    variant of Sec. "Exploiting the low-rank structure" plugs in here.
 
     z: complex [n_slices, NQ]; Re z = field of A(Q), Im z = field of B(Q).
     Measures the local energy (energy_fn(sys, G)) after slice k+1 when
@@ -216,7 +218,7 @@ def run_walker(sys, z, measure_every=None, energy_fn=None, keep_greens=False, st
             expos.append(expo)
         return V, expo
 
-    out = _walk(sys, shifted, measure_every, energy_fn, keep_greens, stop_after, modified)
+    out = _walk(sys, shifted, measure_every, energy_fn, keep_greens, stop_after, modified, make_walker)
     if record_path:
         out["path"] = dict(V=Vs, expo=expos)
     return out
@@ -249,9 +251,15 @@ class Walker:
         self.sys = sys
         self.k = 0
         self.modified = modified
-        self.right = RightBlock(sys.M)
-        self.G, self.ell = greens_at(sys, self.right, 0, self._lexp(0))
+        self.right = self._new_right()
+        self.G, self.ell = self._greens(0, self._lexp(0))
         self.logw, self.status = 0.0, ALIVE
+
+    def _new_right(self):
+        return RightBlock(self.sys.M)
+
+    def _greens(self, k, lexp):
+        return greens_at(self.sys, self.right, k, lexp)
 
     def _lexp(self, k):
         return self.sys.n_slices if self.modified else self.sys.n_slices - k
@@ -260,7 +268,7 @@ class Walker:
         """G_k = (I + B_T^{n-k} R_k)^{-1}, the Green's function of the estimators."""
         if not self.modified:
             return self.G
-        return greens_at(self.sys, self.right, self.k)[0]
+        return self._greens(self.k, self.sys.n_slices - self.k)[0]
 
     def copy(self):
         w = Walker.__new__(Walker)
@@ -280,7 +288,7 @@ class Walker:
         kh = np.exp(-0.5 * sys.dtau * sys.h1_diag())
         B = kh[:, None] * sla.expm(V) * kh[None, :]          # eq. B
         self.right.push(B)
-        self.G, ell_new = greens_at(sys, self.right, k + 1, self._lexp(k + 1))
+        self.G, ell_new = self._greens(k + 1, self._lexp(k + 1))
         lnS = 2.0 * (ell_new - self.ell)
         self.ell = ell_new
         theta = float(wrap_angle(lnS.imag))
@@ -296,10 +304,10 @@ class Walker:
         return lnS, theta, lnI
 
 
-def _walk(sys, shifted, measure_every, energy_fn, keep_greens, stop_after, modified=False):
+def _walk(sys, shifted, measure_every, energy_fn, keep_greens, stop_after, modified=False, make_walker=None):
     n = sys.n_slices
     s = sys.stab_every if measure_every is None else measure_every
-    wk = Walker(sys, modified)
+    wk = Walker(sys, modified) if make_walker is None else make_walker()
     ell0 = wk.ell
     lnS_all = np.zeros(n, dtype=np.complex128)
     theta_all = np.zeros(n)
@@ -322,4 +330,4 @@ def _walk(sys, shifted, measure_every, energy_fn, keep_greens, stop_after, modif
                 greens.append(wk.measure_greens().copy())
     return dict(G=wk.measure_greens(), G_constraint=wk.G, lndet=wk.ell, lndet0=ell0, logw=wk.logw, status=wk.status, lnS=lnS_all,
                 theta=theta_all, lnI=lnI_all, alive=alive_after, records=records, greens=greens,
-                greens_all=greens_all, right=wk.right)
+                greens_all=greens_all, right=wk.right, walker=wk)
