@@ -27,6 +27,9 @@ Readings taken here:
   * The one-body density matrix is P = I - G^T = t^T d_s (d_b + d_s t q)^{-T} q^T, of rank m_T.
   * m_R, m_T and the compression of a slice are those of the Green's function formed after
     that slice's propagator is inserted; the initial slice (R_0 = I) has m_R = M.
+  * The two thresholds can be set apart (right_threshold): 0 keeps the whole right block and
+    truncates the left block only.  That variant is the one whose result does not depend on how
+    the right block is factorised (the left block is diagonal, its kept set is exact).
 """
 import numpy as np
 import scipy.linalg as sla
@@ -50,6 +53,7 @@ class LowRankRight:
 
     def __init__(self, M, threshold):
         self.threshold = threshold
+        self.last_D = np.ones(M)          # |D| of the last stratification before the truncation
         self.Q = np.eye(M, dtype=np.complex128)
         self.D = np.ones(M, dtype=np.complex128)
         self.T = np.eye(M, dtype=np.complex128)
@@ -66,6 +70,7 @@ class LowRankRight:
         Q, R, piv = sla.qr(C, pivoting=True, mode="economic")
         D = np.diagonal(R).copy()
         T = (R / D[:, None]) @ self.T[piv, :]
+        self.last_D = np.abs(D)
         keep = np.abs(D) >= self.threshold
         self.Q, self.D, self.T = Q[:, keep], D[keep], T[keep, :]
 
@@ -124,27 +129,34 @@ def compression(m, M):
 
 class LowRankWalker(_path.Walker):
     """A walker whose Green's function and ln det come from the truncated reduced-rank product.
-    `ranks` lists (m_L, m_R, m_T) of every Green's function formed (index 0: before slice 1)."""
+    `ranks` lists (m_L, m_R, m_T) of every Green's function formed (index 0: before slice 1);
+    `right_D` the |D| spectrum of the right block's stratification at each (before eq. thresh)."""
 
-    def __init__(self, sys, threshold=THRESHOLD):
+    def __init__(self, sys, threshold=THRESHOLD, right_threshold=None):
         self.threshold = threshold
+        self.right_threshold = threshold if right_threshold is None else right_threshold
         self.ranks = []
+        self.right_D = []
         self.lowrank_P = None
         super().__init__(sys, modified=False)
 
     def _new_right(self):
-        return LowRankRight(self.sys.M, self.threshold)
+        return LowRankRight(self.sys.M, self.right_threshold)
 
     def _greens(self, k, lexp):
         G, lndet, P, ranks = lowrank_greens(self.sys, self.right, lexp, self.threshold)
         self.ranks.append(ranks)
+        self.right_D.append(self.right.last_D.copy())
         self.lowrank_P = P
         return G, lndet
 
 
-def run_walker_lowrank(sys, z, threshold=THRESHOLD, energy_fn=None, measure_every=None, keep_greens=False):
-    """path.run_walker with the low-rank walker; adds out["ranks"] [n + 1][3] = (m_L, m_R, m_T)."""
+def run_walker_lowrank(sys, z, threshold=THRESHOLD, energy_fn=None, measure_every=None, keep_greens=False,
+                       right_threshold=None):
+    """path.run_walker with the low-rank walker; adds out["ranks"] [n + 1][3] = (m_L, m_R, m_T)
+    and out["right_D"] (the right block's |D| before truncation at every formation)."""
     out = _path.run_walker(sys, z, measure_every=measure_every, energy_fn=energy_fn, keep_greens=keep_greens,
-                           make_walker=lambda: LowRankWalker(sys, threshold))
+                           make_walker=lambda: LowRankWalker(sys, threshold, right_threshold))
     out["ranks"] = np.array(out["walker"].ranks, dtype=int)
+    out["right_D"] = out["walker"].right_D
     return out

@@ -35,8 +35,9 @@ def test_threshold_zero_is_the_full_rank_path(kw, seed):
         assert np.all(lr["ranks"] == s.M)
 
 
+@pytest.mark.parametrize("right_threshold", [None, 0.0], ids=["both", "left_only"])
 @pytest.mark.parametrize("kw", [COND30, M57_LOWT])
-def test_zero_fields_closed_form(kw):
+def test_zero_fields_closed_form(kw, right_threshold):
     """Zero fields: R_k = diag(e^{-k dtau h}) and A_k = diag(B_T^{n-k} R_k).  The left block keeps
     (n-k) ln B_T >= ln thr, the right block every K with -j dtau h_K >= ln thr for all j <= k
     (a dropped column never returns), m_T = min(m_L, m_R), and G_KK = 1/(1 + A_KK) on the kept
@@ -45,17 +46,17 @@ def test_zero_fields_closed_form(kw):
     thr = lowrank.THRESHOLD
     n, M = s.n_slices, s.M
     z = np.zeros((n, s.NQ), dtype=np.complex128)
-    out = lowrank.run_walker_lowrank(s, z, keep_greens="all")
+    out = lowrank.run_walker_lowrank(s, z, keep_greens="all", right_threshold=right_threshold)
     # keep_greens="all" records G after every slice through the walker's greens
     lt, h = s.log_trial_diag(), s.h1_diag()
     lnthr = np.log(thr)
     assert out["status"] == path.ALIVE
     ranks = out["ranks"]
     truncated_somewhere = False
-    wk = lowrank.LowRankWalker(s, thr)
+    wk = lowrank.LowRankWalker(s, thr, right_threshold)
     for k in range(n + 1):
         keepL = (n - k) * lt >= lnthr
-        keepR = np.ones(M, dtype=bool) if k == 0 else np.all(
+        keepR = np.ones(M, dtype=bool) if k == 0 or right_threshold == 0.0 else np.all(
             [-j * s.dtau * h >= lnthr for j in range(1, k + 1)], axis=0)
         mL, mR = int(keepL.sum()), int(keepR.sum())
         assert tuple(ranks[k]) == (mL, mR, min(mL, mR)), k
