@@ -230,7 +230,38 @@ def bench_workload(F, torch, workload, precs, steps, warmup, overlap=False):
         del os.environ["FTAFQMC_SERIAL_SYSTEMS"]
         results["mixed"]["serial_systems_walker_slices_per_s"] = ser["walker_slices_per_s"]
         results["mixed"]["serial_systems_ms"] = ser["system_ms"]
+    results["energies"] = energies
     return results, fields
+
+
+def time_lowrank(F, torch, workload, fields, full, precision="mixed"):
+    """The low-rank truncation (FTAFQMC_LOW_RANK) on one workload beside the full-rank run `full`
+    (bench_workload's record of the same precision and fields): throughput, per-class times, the
+    mean compressions c_L, c_R, c_T over slices and walkers, and the truncation's effect on the
+    weighted means."""
+    wl = si.WORKLOADS[workload]
+    systems = [dict(sd, precision=0 if precision == "fp64" else 1, flags=F.FTAFQMC_LOW_RANK) for sd in wl["systems"]]
+    ctx, out, en = run_precision(F, torch, systems, fields, 1, 1)
+    M = ctx.info()["M"]
+    mL, mR = ctx.lowrank_ranks()
+    mL = np.asarray(mL, dtype=float)
+    mR = mR.cpu().numpy().astype(float)
+    mT = np.minimum(mL[None, :], mR)
+    ctx.close()
+    torch.cuda.empty_cache()
+    ma, mb = full["energies"][precision][0]["mean"], en[0]["mean"]
+    base = full[precision]["profile_ms_per_step"]
+    return {"workload": workload, "precision": precision,
+            "walker_slices_per_s": out["walker_slices_per_s"], "ms_per_step": out["ms_per_step"],
+            "full_rank_walker_slices_per_s": full[precision]["walker_slices_per_s"],
+            "profile_ms_per_step": out["profile_ms_per_step"],
+            "elim_ms_saved": base["elim"] - out["profile_ms_per_step"]["elim"],
+            "greens_ms_saved": base["greens_transpose"] - out["profile_ms_per_step"]["greens_transpose"],
+            "compression_pct_mean": {"c_L": float(100 * (1 - mL.mean() / M)), "c_R": float(100 * (1 - mR.mean() / M)),
+                                     "c_T": float(100 * (1 - mT.mean() / M))},
+            "m_L_min": int(mL.min()),
+            "rel_diff_mean_E1E2_vs_full_rank": float(abs((mb[0] + mb[1]) - (ma[0] + ma[1])) / abs(ma[0] + ma[1])),
+            "rel_diff_mean_N_vs_full_rank": float(abs(mb[3] - ma[3]) / abs(ma[3]))}
 
 
 def time_graph(F, torch, systems, fields, steps):
@@ -415,6 +446,10 @@ def main():
             if name == args.workload:
                 continue
             res, flds = bench_workload(F, torch, name, ["fp64", "mixed"], 1, 1)
+            if name == "ueg_n114_m485":
+                line["lowrank"] = time_lowrank(F, torch, name, flds, res)
+                print("bench: low-rank %s %.1f walker*slices/s" % (name, line["lowrank"]["walker_slices_per_s"]),
+                      file=sys.stderr, flush=True)
             del flds
             torch.cuda.empty_cache()
             extra[name] = {

@@ -81,7 +81,8 @@ typedef struct {
   double kscale;   /* lambda in H_1 = lambda T + h (1 = the physical Hamiltonian) */
   int precision;   /* FTAFQMC_FP64 or FTAFQMC_MIXED */
   int flags;       /* 0, or any of FTAFQMC_CHECKPOINT, FTAFQMC_OVERLAP, FTAFQMC_GRAPH,
-                      FTAFQMC_TRIAL_THF, FTAFQMC_MODIFIED_OVERLAP, FTAFQMC_MEASURE_EVERY_SLICE */
+                      FTAFQMC_TRIAL_THF, FTAFQMC_MODIFIED_OVERLAP, FTAFQMC_MEASURE_EVERY_SLICE,
+                      FTAFQMC_LOW_RANK */
 } ftafqmc_params;
 
 /* flags: record the sampled path (the shifted coefficients c_Q and tr G of every slice) so
@@ -114,6 +115,17 @@ typedef struct {
 /* flags: an energy record after every slice (for time-slice averages, ftafqmc_record_stats)
  * instead of every stab_every slices; stabilisation keeps its own interval. */
 #define FTAFQMC_MEASURE_EVERY_SLICE 32
+/* flags: low-rank truncation of the Green's function solve (Sec. "Exploiting the low-rank
+ * structure", eq. thresh, threshold FTAFQMC_LOW_RANK_THRESHOLD as in Sec. "Computational
+ * Details").  The diagonal left block B_T^{n-k} keeps the m_L plane waves whose factor is at
+ * least the threshold; the others' rows of G are the identity and drop out of the solve, which
+ * then has m_L right-hand sides instead of M (the saving).  The right block keeps all of its
+ * columns: which of them fall below the threshold depends on how the product is factorised,
+ * and dropping them would make the result depend on it too; its rank m_R is reported.  The
+ * per-slice ranks are read with ftafqmc_lowrank_ranks.  Not with FTAFQMC_CHECKPOINT or
+ * FTAFQMC_MODIFIED_OVERLAP. */
+#define FTAFQMC_LOW_RANK 64
+#define FTAFQMC_LOW_RANK_THRESHOLD 1e-6
 /* ftafqmc_backward modes */
 #define FTAFQMC_FROZEN_PATH 0
 #define FTAFQMC_PATHWISE 1
@@ -245,6 +257,17 @@ int ftafqmc_records(ftafqmc_t h, int sys, void* d_trace, double* d_logw, int* h_
  * different field buffers; E_ARG for an unknown mode. */
 int ftafqmc_backward(ftafqmc_t h, int sys, int mode, const double* d_cot, void* d_jac,
                      double* d_grad, void* d_walker, void* stream);
+
+/* Ranks of the low-rank truncation (system initialised with FTAFQMC_LOW_RANK) at every Green's
+ * function formation k = 0..n (k = 0: the initial one; k: after slice k):
+ *   h_mL [n+1] host int: left rank m_L (plane waves with B_T^{n-k} >= threshold), the same for
+ *        every walker;
+ *   d_mR [W][n+1] device int: right rank m_R, the columns of the walker's stabilised
+ *        factorisation R = Y D T with |D| >= threshold (D of the last stabilisation);
+ * m_T = min(m_L, m_R) and the compression c_i = (1 - m_i / M) 100% (Sec. "Efficacy of the
+ * Low-Rank Truncation") follow.  Entries after the slice reached so far are stale.  Either
+ * pointer may be NULL.  Errors: E_STATE for a system without the flag. */
+int ftafqmc_lowrank_ranks(ftafqmc_t h, int sys, int* d_mR, int* h_mL, void* stream);
 
 /* Walkers whose recorded path came within `threshold` of the phaseless kill: d_flags [W] int
  * (device), 1 where cos theta_k < threshold on some slice k the walker survived (eq. theta;

@@ -25,6 +25,8 @@ FTAFQMC_GRAPH = 4          # params flag: replay whole-path propagation from a c
 FTAFQMC_TRIAL_THF = 8      # params flag: thermal Hartree-Fock trial instead of the free-electron one
 FTAFQMC_MODIFIED_OVERLAP = 16     # params flag: constraint from the modified overlap ratio (eq. ztfix)
 FTAFQMC_MEASURE_EVERY_SLICE = 32  # params flag: an energy record after every slice
+FTAFQMC_LOW_RANK = 64      # params flag: low-rank truncation of the Green's function solve (eq. thresh)
+LOW_RANK_THRESHOLD = 1e-6  # FTAFQMC_LOW_RANK_THRESHOLD
 FTAFQMC_PROFILE_ONLY = 256  # ftafqmc_profile: record only the classes in the low bits
 FROZEN_PATH = 0            # ftafqmc_backward modes: shifted fields held fixed
 PATHWISE = 1               #   raw fields held fixed, the force bias follows G_k
@@ -34,7 +36,7 @@ STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NUMERIC", -4: "E_STATE", -5:
 
 ABI_SYMBOLS = ["ftafqmc_workspace_bytes", "ftafqmc_init_ueg", "ftafqmc_init_ueg_static", "ftafqmc_query",
                "ftafqmc_reset", "ftafqmc_propagate", "ftafqmc_greens", "ftafqmc_energy", "ftafqmc_records",
-               "ftafqmc_backward", "ftafqmc_kink_flags", "ftafqmc_population_control", "ftafqmc_record_stats",
+               "ftafqmc_backward", "ftafqmc_kink_flags", "ftafqmc_lowrank_ranks", "ftafqmc_population_control", "ftafqmc_record_stats",
                "ftafqmc_density_correlation", "ftafqmc_qvectors", "ftafqmc_set_mu", "ftafqmc_tune_mu",
                "ftafqmc_system_times", "ftafqmc_profile",
                "ftafqmc_last_error", "ftafqmc_destroy"]
@@ -90,6 +92,7 @@ def load_library():
     lib.ftafqmc_records.argtypes = [vp, ip, vp, vp, ctypes.POINTER(ctypes.c_int), vp]
     lib.ftafqmc_backward.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp]
     lib.ftafqmc_kink_flags.argtypes = [vp, ip, ctypes.c_double, vp, vp]
+    lib.ftafqmc_lowrank_ranks.argtypes = [vp, ip, vp, ctypes.POINTER(ctypes.c_int), vp]
     lib.ftafqmc_population_control.argtypes = [vp, ip, ip, vp, vp, vp]
     lib.ftafqmc_record_stats.argtypes = [vp, ip, vp, vp, vp]
     lib.ftafqmc_density_correlation.argtypes = [vp, ip, vp, vp, vp]
@@ -213,6 +216,12 @@ def ftafqmc_backward(handle, sys, mode, cot, jac, grad, walker, device):
 
 def ftafqmc_kink_flags(handle, sys, threshold, flags, device):
     _check(load_library().ftafqmc_kink_flags(handle, sys, float(threshold), _ptr(flags), _stream(device)), handle)
+
+
+def ftafqmc_lowrank_ranks(handle, sys, m_right, n_slices, device):
+    m_left = (ctypes.c_int * (n_slices + 1))()
+    _check(load_library().ftafqmc_lowrank_ranks(handle, sys, _ptr(m_right), m_left, _stream(device)), handle)
+    return list(m_left)
 
 
 def ftafqmc_population_control(handle, sys, method, uniforms, parent, device):
@@ -361,6 +370,14 @@ class Context:
             grad = torch.empty(2, dtype=torch.float64, device=self.device)
         ftafqmc_backward(self.handle, sys, mode, cot, jac, grad, walker, self.device)
         return dict(jac=jac, walker=walker, grad=grad)
+
+    def lowrank_ranks(self, sys=0):
+        """(m_L [n+1] list, m_R [W][n+1] int32 tensor) of a FTAFQMC_LOW_RANK system at every
+        Green's function formation (index 0: the initial one, k: after slice k)."""
+        inf = self.infos[sys]
+        m_right = torch.empty((inf["n_walkers"], inf["n_slices"] + 1), dtype=torch.int32, device=self.device)
+        m_left = ftafqmc_lowrank_ranks(self.handle, sys, m_right, inf["n_slices"], self.device)
+        return m_left, m_right
 
     def kink_flags(self, threshold, sys=0):
         """int32 [W]: 1 where the walker's recorded path had cos(theta_k) < threshold on a slice

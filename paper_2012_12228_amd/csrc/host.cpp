@@ -29,6 +29,7 @@ constexpr int MAX_NQ = 8192;           // the shifted coefficients of one walker
 // estimate nu is below TAYLOR_APRIORI_TOL; every slice then checks the rigorous 1-norm bound
 // of the remainder on the device against TAYLOR_CHECK_TOL and flags the walker otherwise.
 constexpr int TAYLOR_MAX_NB = 6;
+constexpr double LOW_RANK_THRESHOLD = FTAFQMC_LOW_RANK_THRESHOLD;
 constexpr double TAYLOR_APRIORI_TOL[2] = {1e-14, 1e-8};   // FP64, mixed
 // The check tolerance sits at the level of each precision's own product rounding: the 1-norm
 // bound is measured 50-400x above the true truncation error on the workloads (M=485: bound
@@ -75,6 +76,9 @@ struct HostSys {
   TanDev tan;
   int taylor_nb = 4;                    // Paterson-Stockmeyer blocks of 4: degree 4 taylor_nb
   bool modified = false;                // constraint from the modified overlap ratio (eq. ztfix)
+  bool lowrank = false;                 // low-rank truncation of the Green's function solve (eq. thresh)
+  std::vector<int> lr_order, lr_pos;    // plane waves by decreasing ln B_T, and the inverse order
+  std::vector<int> lr_mL;               // [n + 1] left rank of the solve after slice k
   bool every = false;                   // energy record after every slice
   double* small = nullptr;              // [32] device doubles for host-driven loops (mu tuning)
   int lane0 = 0;                        // first stream lane of this system (its groups follow)
@@ -97,8 +101,11 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
   if (p.precision != FTAFQMC_FP64 && p.precision != FTAFQMC_MIXED) return "unknown precision";
   if (!std::isfinite(p.kscale)) return "kscale must be finite";
   if (p.flags & ~(FTAFQMC_CHECKPOINT | FTAFQMC_OVERLAP | FTAFQMC_GRAPH | FTAFQMC_TRIAL_THF | FTAFQMC_MODIFIED_OVERLAP |
-                  FTAFQMC_MEASURE_EVERY_SLICE))
+                  FTAFQMC_MEASURE_EVERY_SLICE | FTAFQMC_LOW_RANK))
     return "unknown flags";
+  s.lowrank = (p.flags & FTAFQMC_LOW_RANK) != 0;
+  if (s.lowrank && (p.flags & (FTAFQMC_CHECKPOINT | FTAFQMC_MODIFIED_OVERLAP)))
+    return "the low-rank truncation is built for the standard overlap ratio without the derivative record";
   s.modified = (p.flags & FTAFQMC_MODIFIED_OVERLAP) != 0;
   s.every = (p.flags & FTAFQMC_MEASURE_EVERY_SLICE) != 0;
   if (s.modified && (p.flags & FTAFQMC_CHECKPOINT))
@@ -216,6 +223,21 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
   }
   s.lnbt2.assign(s.ld2, 0.0);
   for (int i = 0; i < s.M2; ++i) s.lnbt2[i] = s.lnbt[i % s.M];
+  if (s.lowrank) {
+    // eq. thresh on the diagonal left block B_T^lexp: the kept plane waves are a prefix of the
+    // order of decreasing ln B_T (lexp >= 0), of length lr_mL[n - lexp] for the solve after slice k
+    s.lr_order.resize(s.M);
+    for (int i = 0; i < s.M; ++i) s.lr_order[i] = i;
+    std::stable_sort(s.lr_order.begin(), s.lr_order.end(), [&](int a, int b) { return s.lnbt[a] > s.lnbt[b]; });
+    s.lr_pos.assign(s.M, 0);
+    for (int c = 0; c < s.M; ++c) s.lr_pos[s.lr_order[c]] = c;
+    s.lr_mL.assign(s.n + 1, 0);
+    for (int k = 0; k <= s.n; ++k) {
+      int m = 0;
+      for (int i = 0; i < s.M; ++i) m += (double)(s.n - k) * s.lnbt[i] >= std::log(LOW_RANK_THRESHOLD) ? 1 : 0;
+      s.lr_mL[k] = m;
+    }
+  }
   // pairs of each Q as flat indices of G_{r p} (K_p - K_r = Q)
   s.qptr.assign(s.NQ + 1, 0);
   for (int i = 0; i < s.M; ++i)
@@ -320,6 +342,14 @@ size_t layout(HostSys& s, char* base, size_t off) {
   d.rbidx = (const int*)take(sizeof(int) * (size_t)M * (M - 1));
   d.grid = (const short*)take(sizeof(short) * s.grid.size());
   d.flat = (const int*)take(sizeof(int) * M);
+  if (s.lowrank) {
+    d.lr_order = (const int*)take(sizeof(int) * M);
+    d.lr_pos = (const int*)take(sizeof(int) * M);
+    d.lr_mR = (int*)take(sizeof(int) * (size_t)W * (s.n + 1));
+    d.lr_thr = LOW_RANK_THRESHOLD;
+    d.lr_lnthr = std::log(LOW_RANK_THRESHOLD);
+    d.lr_mL = M;
+  }
   d.Y = (double2*)take(sizeof(double2) * mat * W);
   d.Ti = (double2*)take(sizeof(double2) * mat * W);
   d.G = (double2*)take(sizeof(double2) * mat * W);
@@ -469,6 +499,7 @@ SysDev walker_view(const HostSys& s, int w0, int nw) {
   if (v.tnorm) v.tnorm += w * 16;
   if (v.rec_c) v.rec_c += w * s.n * (long long)s.NQ;
   if (v.rec_trG) v.rec_trG += w * (s.n + 1);
+  if (v.lr_mR) v.lr_mR += w * (s.n + 1);
   v.W = nw; v.w_off = w0; v.rec_W = s.p.n_walkers;
   return v;
 }
@@ -642,10 +673,13 @@ int stabilise(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st) {
 }
 
 // (I + B_T^lexp R)^{-1} into d.G with ln det X of the eliminated block (Sec. "Numerical Stabilization").
-int greens_solve(ftafqmc_ctx* h, HostSys& s, SysDev& d, int lexp, hipStream_t st) {
+// Low-rank: only the plane waves kept in the left block are right-hand sides.
+int greens_solve(ftafqmc_ctx* h, HostSys& s, SysDev& d0, int lexp, hipStream_t st) {
+  SysDev d = d0;
+  if (s.lowrank) d.lr_mL = s.lr_mL[s.n - lexp];
   HIPCHK(timed(h, FTAFQMC_PROF_GREENS, st, [&] { return launch_greens_form(d, lexp, st); }));
   ElimParams e;
-  e.aug = d.aug; e.stride = d.aug_stride; e.lda = 2 * s.ld; e.M = s.M; e.rhs_off = s.ld; e.nrhs = s.M;
+  e.aug = d.aug; e.stride = d.aug_stride; e.lda = 2 * s.ld; e.M = s.M; e.rhs_off = s.ld; e.nrhs = s.lowrank ? d.lr_mL : s.M;
   e.W = d.W; e.pivot = 1; e.backsub = 1; e.lndet = d.lndetX; e.status = d.status;
   e.piv = d.piv; e.ld = s.ld; e.tri = d.tri;
   HIPCHK(timed(h, FTAFQMC_PROF_ELIM, st, [&] { return launch_elim(e, st); }));
@@ -661,6 +695,7 @@ int greens(ftafqmc_ctx* h, HostSys& s, SysDev& d, int k, int init, bool measure,
   if (!s.modified) {
     int rc = greens_solve(h, s, d, s.n - k, st);
     if (rc) return rc;
+    if (s.lowrank) HIPCHK(timed(h, FTAFQMC_PROF_GREENS, st, [&] { return launch_lr_rank(d, k, st); }));
     const double slb = sum_ln_lb(s, s.n - k);
     HIPCHK(timed(h, FTAFQMC_PROF_WEIGHT, st, [&] { return launch_weight(d, k, slb, init, st); }));
     return FTAFQMC_OK;
@@ -1263,6 +1298,8 @@ int init_ueg_impl(const ftafqmc_params* p, int n_sys, void* d_workspace, size_t 
     if (e == hipSuccess) e = up(d.grid, s.grid.data(), sizeof(short) * s.grid.size());
     if (e == hipSuccess) e = up(d.flat, s.flat.data(), sizeof(int) * s.M);
     if (e == hipSuccess && s.ckpt) e = up(s.tan.lnbt2, s.lnbt2.data(), sizeof(double) * s.ld2);
+    if (e == hipSuccess && s.lowrank) e = up((void*)d.lr_order, s.lr_order.data(), sizeof(int) * s.M);
+    if (e == hipSuccess && s.lowrank) e = up((void*)d.lr_pos, s.lr_pos.data(), sizeof(int) * s.M);
     // the host tables are no longer needed once the copies have completed
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { ftafqmc_destroy(h); return lib_init_error(FTAFQMC_E_HIP, "table upload failed"); }
@@ -1552,6 +1589,18 @@ int ftafqmc_system_times(ftafqmc_t h, double* h_ms) {
     if (e != hipSuccess) return h->set(FTAFQMC_E_HIP, std::string("system times: ") + hipGetErrorString(e));
     h_ms[i] = ms;
   }
+  return FTAFQMC_OK;
+}
+
+int ftafqmc_lowrank_ranks(ftafqmc_t h, int sys, int* d_mR, int* h_mL, void* stream) {
+  int rc = check_handle(h, sys);
+  if (rc) return rc;
+  HostSys& s = h->sys[sys];
+  if (!s.lowrank) return h->set(FTAFQMC_E_STATE, "the system was initialised without FTAFQMC_LOW_RANK");
+  if (h_mL) std::memcpy(h_mL, s.lr_mL.data(), sizeof(int) * (s.n + 1));
+  if (d_mR)
+    HIPCHK(hipMemcpyAsync(d_mR, s.dev.lr_mR, sizeof(int) * (size_t)s.p.n_walkers * (s.n + 1), hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream));
   return FTAFQMC_OK;
 }
 

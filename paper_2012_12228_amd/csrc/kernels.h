@@ -95,6 +95,13 @@ struct SysDev {
   double* pop_logw;       // [W] population control: new ln w of each slot
   int taylor_deg;         // degree of the Taylor polynomial of e^V (a multiple of 4)
   double taylor_tol;      // a walker whose truncation bound exceeds this is flagged numeric
+  // low-rank truncation (eq. thresh), or lr_order == null: the kept left plane waves are the first
+  // lr_mL of lr_order (decreasing ln B_T); lr_pos is its inverse; lr_thr counts the right rank
+  const int* lr_order;    // [M]
+  const int* lr_pos;      // [M]
+  int lr_mL;              // left rank of the current solve
+  double lr_thr, lr_lnthr;
+  int* lr_mR;             // [W][n+1] right rank at every Green's function formation, or null
   double2* rec_c;         // [W][n][NQ] shifted coefficients c_Q of every slice (path record), or null
   double2* rec_trG;       // [W][n+1] tr G_k of every slice, or null
   int w_off, rec_W;       // walker offset of this view and walker count of the record arrays
@@ -177,6 +184,7 @@ hipError_t launch_fill_v(const SysDev& s, void* V, int mixed, hipStream_t st);  
 // G of (I + B_T^lexp R)^{-1}: the transposed augmented system, and G from its solution
 hipError_t launch_greens_form(const SysDev& s, int lexp, hipStream_t st);
 hipError_t launch_greens_post(const SysDev& s, int lexp, hipStream_t st);
+hipError_t launch_lr_rank(const SysDev& s, int k, hipStream_t st);   // right rank into lr_mR[w][k]
 hipError_t launch_rq(const SysDev& s, hipStream_t st);                // r_Q of s.G into s.r
 hipError_t launch_weight(const SysDev& s, int k, double sum_lnLb, int init, hipStream_t st);
 int rq_block_elems();     // complex entries of G per row block of the r_Q kernel (rows * ld at most)

@@ -191,7 +191,11 @@ FT_DEV void split_D(double d, double* db, double* ds) {
   else { *db = 1.0; *ds = d; }
 }
 
-// aug[i][j] = X[j][i], aug[i][ld + j] = (Ti D_b)[j][i]  (transposed through LDS)
+// aug[i][j] = X[j][i], aug[i][ld + j] = (Ti D_b)[j][i]  (transposed through LDS).
+// Low-rank truncation (eq. thresh) of the diagonal left block: plane waves with B_T^lexp below the
+// threshold drop out (L_s = 0: their rows of X are those of Ti D_b, so the same rows of G are the
+// identity and their columns of the solution are known); only the lr_mL kept plane waves, in
+// lr_order, are right-hand sides.
 __global__ __launch_bounds__(NT) void greens_form_kernel(SysDev s, int lexp) {
   __shared__ double2 tX[TT][TT + 1];
   __shared__ double2 tU[TT][TT + 1];
@@ -202,6 +206,7 @@ __global__ __launch_bounds__(NT) void greens_form_kernel(SysDev s, int lexp) {
   const double2* Y = s.Y + (long long)w * s.mat_stride;
   const double2* Ti = s.Ti + (long long)w * s.mat_stride;
   const double* D = s.D + (long long)w * s.ld;
+  const bool lr = s.lr_order != nullptr;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
   for (int yy = ty; yy < TT; yy += 8) {
     const int row = tj * TT + yy, col = ti * TT + tx;   // element (row=j, col=i) of Y and Ti
@@ -210,9 +215,11 @@ __global__ __launch_bounds__(NT) void greens_form_kernel(SysDev s, int lexp) {
       double lb, ls, db, ds;
       split_L(s, row, lexp, &lb, &ls);
       split_D(D[col], &db, &ds);
+      if (lr && (double)lexp * s.lnbt[row] < s.lr_lnthr) ls = 0.0;
       const double2 tv = Ti[(long long)row * s.ld + col], yv = Y[(long long)row * s.ld + col];
       u = cscale(tv, db);
       x = make_double2(lb * u.x + ls * ds * yv.x, lb * u.y + ls * ds * yv.y);
+      if (lr) u = row < s.lr_mL ? cscale(Ti[(long long)s.lr_order[row] * s.ld + col], db) : zero2();
     }
     tX[yy][tx] = x;
     tU[yy][tx] = u;
@@ -228,7 +235,8 @@ __global__ __launch_bounds__(NT) void greens_form_kernel(SysDev s, int lexp) {
   }
 }
 
-// G[i][j] = H[j][i] L_b[j] with H = aug right block (= X^{-T} (Ti D_b)^T)
+// G[i][j] = H[j][i] L_b[j] with H = aug right block (= X^{-T} (Ti D_b)^T).  Low-rank: column i of
+// H is solved column lr_pos[i] when i is kept, else e_i (row i of G is the identity).
 __global__ __launch_bounds__(NT) void greens_post_kernel(SysDev s, int lexp) {
   __shared__ double2 tH[TT][TT + 1];
   const int nt = (s.ld + TT - 1) / TT;
@@ -243,7 +251,10 @@ __global__ __launch_bounds__(NT) void greens_post_kernel(SysDev s, int lexp) {
     if (row < s.M && col < s.M) {
       double lb, ls;
       split_L(s, row, lexp, &lb, &ls);
-      h = cscale(aug[(long long)row * 2 * s.ld + s.ld + col], lb);
+      int c = col;
+      if (s.lr_order) c = s.lr_pos[col] < s.lr_mL ? s.lr_pos[col] : -1;
+      if (c >= 0) h = cscale(aug[(long long)row * 2 * s.ld + s.ld + c], lb);
+      else if (row == col) h = make_double2(lb, 0.0);
     }
     tH[yy][tx] = h;
   }
@@ -253,6 +264,18 @@ __global__ __launch_bounds__(NT) void greens_post_kernel(SysDev s, int lexp) {
     const int i = ti * TT + yy, j = tj * TT + tx;
     if (i < s.ld && j < s.ld) G[(long long)i * s.ld + j] = tH[tx][yy];
   }
+}
+
+// Right rank of the Green's function formed after slice k: the columns with |D| >= threshold.
+__global__ __launch_bounds__(NT) void lr_rank_kernel(SysDev s, int k) {
+  __shared__ double red[8];
+  const int w = blockIdx.x;
+  if (w >= s.W) return;
+  const double* D = s.D + (long long)w * s.ld;
+  double c = 0.0;
+  for (int i = threadIdx.x; i < s.M; i += NT) c += fabs(D[i]) >= s.lr_thr ? 1.0 : 0.0;
+  c = block_sum_256(c, red);
+  if (threadIdx.x == 0) s.lr_mR[(long long)w * (s.n + 1) + k] = (int)c;
 }
 
 // r_Q = sum over pairs K_p - K_r = Q of P_pr = -G_rp: one Q per thread, NT Q per workgroup, the
@@ -862,6 +885,11 @@ hipError_t launch_greens_form(const SysDev& s, int lexp, hipStream_t st) {
 }
 hipError_t launch_greens_post(const SysDev& s, int lexp, hipStream_t st) {
   greens_post_kernel<<<tiles_blocks(s, tt_tiles(s)), NT, 0, st>>>(s, lexp);
+  return hipGetLastError();
+}
+hipError_t launch_lr_rank(const SysDev& s, int k, hipStream_t st) {
+  if (!s.lr_mR) return hipSuccess;
+  lr_rank_kernel<<<s.W, NT, 0, st>>>(s, k);
   return hipGetLastError();
 }
 int rq_block_elems() { return RQ_ELEMS; }

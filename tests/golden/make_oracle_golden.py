@@ -6,10 +6,14 @@ energy record (each stabilisation boundary and the last slice): E_1, E_2, E, N,
 ln w and the status; plus the final Green's function's diagonal and first rows.
 For the derivative workload it also keeps each sampled walker's frozen-path
 derivatives (d ln w, dE, dN in mu and in lambda) from oracle.tangent, and (mode pathwise)
-their pathwise derivatives with the raw fields held fixed.
+their pathwise derivatives with the raw fields held fixed.  Mode lowrank keeps the same
+per-record values for the low-rank truncated path (oracle.lowrank) of the sampled walkers of
+the large low-temperature workload, truncating the left block (the variant whose result does
+not depend on how the right block is factorised), with the ranks of every slice.
 Usage: python tests/golden/make_oracle_golden.py [workload ...]
        python tests/golden/make_oracle_golden.py tangent
        python tests/golden/make_oracle_golden.py pathwise
+       python tests/golden/make_oracle_golden.py lowrank
 """
 import os
 import sys
@@ -20,7 +24,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from oracle import ueg, path, energy, tangent  # noqa: E402
+from oracle import ueg, path, energy, tangent, lowrank  # noqa: E402
 import synthinputs as si  # noqa: E402
 
 SAMPLES = {
@@ -30,20 +34,26 @@ SAMPLES = {
     "ueg_n114_m485": {0: [0, 511]},
 }
 G_ROWS = 8
+LOWRANK_SAMPLES = {"ueg_n114_m485": {0: [0, 511]}}
 TANGENT_SAMPLES = {"ueg_n38_m123": [0, 63, 127]}
 
 
 def one(args):
-    name, sidx, w = args
+    name, sidx, w = args[:3]
+    low_rank = len(args) > 3 and args[3]
     from threadpoolctl import threadpool_limits
     wl = si.WORKLOADS[name]
     sd = wl["systems"][sidx]
     s = ueg.UEGSystem(sd["n_elec"], sd["rs"], sd["theta"], sd["nmax2"], sd["dtau"], stab_every=sd["stab_every"])
     z = si.walker_fields(si.system_seed(name, sidx), w, s.n_slices, s.NQ)
     with threadpool_limits(2):
-        out = path.run_walker(s, z, energy_fn=energy.local_energy)
+        if low_rank:
+            out = lowrank.run_walker_lowrank(s, z, energy_fn=energy.local_energy, right_threshold=0.0)
+        else:
+            out = path.run_walker(s, z, energy_fn=energy.local_energy)
     recs = out["records"]
-    return dict(
+    extra = dict(ranks=out["ranks"]) if low_rank else {}
+    return dict(**extra,
         system=sidx, walker=w,
         slices=np.array([r["slice"] for r in recs]),
         E=np.array([[r["E1"], r["E2"], r["E"], r["N"]] for r in recs]),
@@ -90,20 +100,21 @@ def main_tangent(mode="tangent"):
         print("wrote", fn, os.path.getsize(fn), "bytes")
 
 
-def main(names):
-    jobs = [(n, sidx, w) for n in names for sidx, ws in SAMPLES[n].items() for w in ws]
+def main(names, low_rank=False):
+    samples = LOWRANK_SAMPLES if low_rank else SAMPLES
+    jobs = [(n, sidx, w, low_rank) for n in names for sidx, ws in samples[n].items() for w in ws]
     with ProcessPoolExecutor(max_workers=min(4, len(jobs))) as ex:
         results = list(ex.map(one, jobs))
     for n in names:
         arrays = {}
-        for (jn, sidx, w), r in zip(jobs, results):
+        for (jn, sidx, w, _), r in zip(jobs, results):
             if jn != n:
                 continue
             key = "s%d_w%d" % (sidx, w)
             for k, v in r.items():
                 if k not in ("system", "walker"):
                     arrays[key + "_" + k] = v
-        fn = os.path.join(HERE, "oracle_%s.npz" % n)
+        fn = os.path.join(HERE, ("oracle_lowrank_%s.npz" if low_rank else "oracle_%s.npz") % n)
         np.savez_compressed(fn, **arrays)
         print("wrote", fn, os.path.getsize(fn), "bytes")
 
@@ -111,5 +122,7 @@ def main(names):
 if __name__ == "__main__":
     if sys.argv[1:] in (["tangent"], ["pathwise"]):
         main_tangent(sys.argv[1])
+    elif sys.argv[1:] == ["lowrank"]:
+        main(list(LOWRANK_SAMPLES), low_rank=True)
     else:
         main(sys.argv[1:] or list(SAMPLES))

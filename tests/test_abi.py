@@ -48,10 +48,12 @@ def test_invalid_parameters_are_rejected(bad):
         F.ftafqmc_workspace_bytes([sysdef])
 
 
-@pytest.mark.parametrize("bad", [dict(flags=1024), dict(flags=1, precision=1), dict(flags=1, nmax2=11, n_elec=66, theta=0.125)])
+@pytest.mark.parametrize("bad", [dict(flags=1024), dict(flags=1, precision=1), dict(flags=1, nmax2=11, n_elec=66, theta=0.125),
+                                 dict(flags=64 | 1), dict(flags=64 | 16)])
 def test_invalid_flags_are_rejected(bad):
-    """Unknown flag bits, a path record with mixed precision, and a path record whose doubled
-    system would exceed the elimination's 512 rows (M = 171 is fine; M > 256 is not)."""
+    """Unknown flag bits, a path record with mixed precision, a path record whose doubled
+    system would exceed the elimination's 512 rows (M = 171 is fine; M > 256 is not), and the
+    low-rank truncation with the path record or the modified overlap ratio."""
     _lib()
     sysdef = dict(si.WORKLOADS["ueg_n14_m19"]["systems"][0])
     sysdef.update(bad)
@@ -66,7 +68,8 @@ def test_flag_values_match_the_header():
     for name, val in (("FTAFQMC_CHECKPOINT", F.FTAFQMC_CHECKPOINT), ("FTAFQMC_OVERLAP", F.FTAFQMC_OVERLAP),
                       ("FTAFQMC_GRAPH", F.FTAFQMC_GRAPH), ("FTAFQMC_FROZEN_PATH", F.FROZEN_PATH),
                       ("FTAFQMC_PROFILE_ONLY", F.FTAFQMC_PROFILE_ONLY), ("FTAFQMC_TRIAL_THF", F.FTAFQMC_TRIAL_THF),
-                      ("FTAFQMC_POP_COMB", F.POP_COMB), ("FTAFQMC_POP_PAIR_BRANCH", F.POP_PAIR_BRANCH)):
+                      ("FTAFQMC_POP_COMB", F.POP_COMB), ("FTAFQMC_POP_PAIR_BRANCH", F.POP_PAIR_BRANCH),
+                      ("FTAFQMC_PATHWISE", F.PATHWISE), ("FTAFQMC_LOW_RANK", F.FTAFQMC_LOW_RANK)):
         m = re.search(r"#define\s+%s\s+(\d+)" % name, text)
         assert m and int(m.group(1)) == val, name
 
