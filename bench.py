@@ -8,7 +8,9 @@ the local energy at every stabilisation boundary and at slice n; then the weight
 energy means.  Inputs (fields) are resident in HBM before the timed region.  Both
 precisions run on the same seeded fields; the mixed path's energy error is measured
 against the FP64 path on every walker, and `value` is the mixed throughput when that
-error is within 1e-6, else the FP64 throughput.  The FP64 oracle is timed on the
+error is within 1e-6, else the FP64 throughput, under the faster of the two schedules
+(one stream per system, or FTAFQMC_OVERLAP's two walker groups, whose results are
+bit-identical; config.schedule names it).  The FP64 oracle is timed on the
 host cores on a bounded sample of the same workload (`cpu_baseline`).
 """
 import argparse
@@ -343,12 +345,29 @@ def time_backward(F, torch, workload="ueg_n38_m123"):
     t4 = time.perf_counter()
     jp = bp["jac"].cpu().numpy()
     ctx.close()
+    # the same two passes with everything on the caller's stream (no second stream)
+    os.environ["FTAFQMC_SERIAL_BACKWARD"] = "1"
+    cs = F.Context(sd)
+    del os.environ["FTAFQMC_SERIAL_BACKWARD"]
+    cs.propagate(f)
+    cs.energy()
+    cs.backward()
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    cs.backward()
+    torch.cuda.synchronize()
+    t6 = time.perf_counter()
+    cs.backward(mode=F.PATHWISE)
+    torch.cuda.synchronize()
+    t7 = time.perf_counter()
+    cs.close()
     ws = inf["n_walkers"] * inf["n_slices"]
     return {"workload": workload, "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
             "walker_slices_per_s_backward": ws / (t2 - t1),
             "profile_ms": {k: v[0] for k, v in prof.items() if v[1]},
             "d<E>/dmu": jac[0].real, "d<N>/dmu": jac[1].real, "d<E>/dlambda": jac[2].real, "d<N>/dlambda": jac[3].real,
             "pathwise_s": t4 - t3, "pathwise_over_forward": (t4 - t3) / (t1 - t0),
+            "one_stream_backward_s": t6 - t5, "one_stream_pathwise_s": t7 - t6,
             "pathwise": {"d<E>/dmu": jp[0].real, "d<N>/dmu": jp[1].real, "d<E>/dlambda": jp[2].real,
                          "d<N>/dlambda": jp[3].real}}
 
@@ -423,16 +442,22 @@ def main():
     r = results[use]
     prec_key = "f32" if use == "mixed" else "f64"
     achieved = r["gemm_tflops"]
+    # the schedule of the headline: one stream, or the two walker groups of FTAFQMC_OVERLAP when
+    # they are faster on this workload (bit-identical results, so the same mixed-vs-FP64 gate)
+    best, schedule, groups = r, "one stream per system", r["walker_groups"]
+    ov = r.get("overlap_schedule")
+    if ov is not None and ov["walker_slices_per_s"] > r["walker_slices_per_s"]:
+        best, schedule, groups = ov, "two walker groups on two streams (FTAFQMC_OVERLAP)", ov["walker_groups"]
     line = {
         "metric": "walker*slices/s incl. stabilised G+energy, FP64 vs mixed at <=1e-6 rel error",
-        "value": r["walker_slices_per_s"], "unit": "walker*slices/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "value": best["walker_slices_per_s"], "unit": "walker*slices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64-fp32mfma+f64" if use == "mixed" else "f64",
         "data": "synthetic (seeded N(0,1) auxiliary fields, free-electron trial)",
         "config": {"workload": args.workload, "systems": [
             {k: v for k, v in sd.items()} for sd in wl["systems"]], "precision_reported": use,
-            "walker_groups": r["walker_groups"]},
+            "schedule": schedule, "walker_groups": groups},
         "roofline": {"bound": "mfma", "kernel": "propagator complex GEMM (%s MFMA)" % prec_key,
                      "achieved": achieved, "peak": PEAK_TFLOPS[prec_key], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[prec_key],

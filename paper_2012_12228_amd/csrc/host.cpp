@@ -411,6 +411,9 @@ size_t layout(HostSys& s, char* base, size_t off) {
     t.dd.E0 = take(sizeof(double2) * mat2 * W);
     t.dd.E1 = take(sizeof(double2) * mat2 * W);
     t.dd.aug = (double2*)take(sizeof(double2) * 2 * mat2 * W);
+    t.caug = (double2*)take(sizeof(double2) * 2 * mat2 * W);
+    t.cpiv = (int*)take(sizeof(int) * ld2 * W);
+    t.ctri = (double2*)take(sizeof(double2) * elim_tri_elems(s.M2) * W);
     t.tstat = (int*)take(sizeof(int) * W);
     t.lndet_dummy = (double2*)take(sizeof(double2) * W);
     t.dd.status = t.tstat;
@@ -532,6 +535,10 @@ struct ftafqmc_ctx {
   std::vector<const void*> gfields;     // field buffers the captured path reads
   struct SysAfter { int k, nrec; std::vector<int> rec_slice; double2* Y; double2* Ynew; };
   std::vector<SysAfter> gafter;         // host-side state of every system after the path
+  // ftafqmc_backward's second stream (default priority) and its fork/join events, created when a
+  // system records its path and side streams are allowed
+  hipStream_t bwd = nullptr;
+  hipEvent_t bwd_ev[4] = {};
   int set(int code, const std::string& m) { err = m; return code; }
 };
 
@@ -881,14 +888,24 @@ ElimParams ep_dd(const HostSys& s, int pivot, int backsub) {
   return e;
 }
 
-// Doubled Green's function (cyclic at slice k, or literal at tau = beta) into Gst / the lambda dG.
-int doubled_greens(ftafqmc_ctx* h, HostSys& s, int k, int literal, hipStream_t st) {
+// Doubled Green's function (cyclic at slice k, or literal at tau = beta) into Gst / the lambda dG,
+// in its own augmented system (caug, cpiv, ctri).  The form step reads the doubled state; the
+// solve step reads only caug.
+int doubled_greens_form(ftafqmc_ctx* h, HostSys& s, int k, int literal, hipStream_t st) {
+  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_cyc_form(s.dev, s.tan, k, literal, st); }));
+  return FTAFQMC_OK;
+}
+int doubled_greens_solve(ftafqmc_ctx* h, HostSys& s, int k, int literal, hipStream_t st) {
   TanDev& t = s.tan;
-  HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_cyc_form(s.dev, t, k, literal, st); }));
-  const ElimParams e = ep_dd(s, 1, 1);
+  ElimParams e = ep_dd(s, 1, 1);
+  e.aug = t.caug; e.piv = t.cpiv; e.tri = t.ctri;
   HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_elim(e, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_cyc_post(s.dev, t, k, literal, st); }));
   return FTAFQMC_OK;
+}
+int doubled_greens(ftafqmc_ctx* h, HostSys& s, int k, int literal, hipStream_t st) {
+  int rc = doubled_greens_form(h, s, k, literal, st);
+  return rc ? rc : doubled_greens_solve(h, s, k, literal, st);
 }
 
 // One slice of the doubled product: Rd <- [[B, dB], [0, B]] Rd, then the pre-pivoted
@@ -963,21 +980,29 @@ int backward(ftafqmc_ctx* h, HostSys& s, const double* cot, double2* jac, double
              hipStream_t st) {
   SysDev& d = s.dev;
   TanDev& t = s.tan;
-  const int M = s.M, ld = s.ld, W = s.p.n_walkers;
   HIPCHK(launch_tan_init(d, t, st));
+  // With the handle's backward stream, the re-factorisation of the doubled product (which needs
+  // only B and the state) runs beside the cyclic solve and the ratio of the same slice (which
+  // need only the state and their own scratch): the form step reads the state first.
+  const hipStream_t side = h->bwd;
   for (int k = 0; k < s.n; ++k) {
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_coef_replay(d, k, st); }));
     void* B = nullptr;
     int rc = form_propagator(h, s, d, st, &B, false);
     if (rc) return rc;
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_tan_prep(d, t, (const double2*)B, st); }));
-    rc = doubled_greens(h, s, k, 0, st);
-    if (rc) return rc;
-    rc = ratio_solve(h, s, st);
-    if (rc) return rc;
+    if ((rc = doubled_greens_form(h, s, k, 0, st))) return rc;
+    if (side) {
+      HIPCHK(hipEventRecord(h->bwd_ev[0], st));
+      HIPCHK(hipStreamWaitEvent(side, h->bwd_ev[0], 0));
+      if ((rc = doubled_push(h, s, side, false))) return rc;
+      HIPCHK(hipEventRecord(h->bwd_ev[1], side));
+    }
+    if ((rc = doubled_greens_solve(h, s, k, 0, st))) return rc;
+    if ((rc = ratio_solve(h, s, st))) return rc;
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_tan_weight(d, t, k, st); }));
-    rc = doubled_push(h, s, st, false);
-    if (rc) return rc;
+    if (side) HIPCHK(hipStreamWaitEvent(st, h->bwd_ev[1], 0));
+    else if ((rc = doubled_push(h, s, st, false))) return rc;
   }
   int rc = doubled_greens(h, s, s.n, 1, st);                      // lambda: dG_n
   if (rc) return rc;
@@ -1069,11 +1094,22 @@ int backward_pathwise(ftafqmc_ctx* h, HostSys& s, const double* cot, double2* ja
   const long long mat = d.mat_stride;
   const double2* fields = (const double2*)s.fields;
   HIPCHK(launch_tan_init(d, t, st));
+  // With the handle's backward stream: the cyclic solve of slice k (state only) runs beside the
+  // literal solve and the propagator chain; the re-factorisation (state and [B | dB]) beside the
+  // ratio and the weight.
+  const hipStream_t side = h->bwd;
   for (int dir = 0; dir < 2; ++dir) {
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_pw_reset(d, t, st); }));
     for (int k = 0; k < s.n; ++k) {
+      int rc;
+      if (side) {
+        HIPCHK(hipEventRecord(h->bwd_ev[0], st));
+        HIPCHK(hipStreamWaitEvent(side, h->bwd_ev[0], 0));
+        if ((rc = doubled_greens(h, s, k, 0, side))) return rc;
+        HIPCHK(hipEventRecord(h->bwd_ev[1], side));
+      }
       HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_coef_replay(d, k, st); }));
-      int rc = pw_literal(h, s, s.n - k, st);                         // G_k and dG_k
+      rc = pw_literal(h, s, s.n - k, st);                             // G_k and dG_k
       if (rc) return rc;
       HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_pw_extract(d, t, nullptr, st); }));
       SysDev gv = d;
@@ -1090,10 +1126,19 @@ int backward_pathwise(ftafqmc_ctx* h, HostSys& s, const double* cot, double2* ja
       double2* KdEK = nullptr;
       if ((rc = pw_chain(h, s, st, &B, &KdEK))) return rc;
       HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_pw_prep(d, t, (const double2*)B, KdEK, dir, st); }));
-      if ((rc = doubled_greens(h, s, k, 0, st))) return rc;
+      if (side) {
+        HIPCHK(hipEventRecord(h->bwd_ev[2], st));
+        HIPCHK(hipStreamWaitEvent(side, h->bwd_ev[2], 0));
+        if ((rc = doubled_push(h, s, side, true))) return rc;
+        HIPCHK(hipEventRecord(h->bwd_ev[3], side));
+        HIPCHK(hipStreamWaitEvent(st, h->bwd_ev[1], 0));
+      } else if ((rc = doubled_greens(h, s, k, 0, st))) {
+        return rc;
+      }
       if ((rc = ratio_solve(h, s, st))) return rc;
       HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_pw_weight(d, t, k, dir, st); }));
-      if ((rc = doubled_push(h, s, st, true))) return rc;
+      if (side) HIPCHK(hipStreamWaitEvent(st, h->bwd_ev[3], 0));
+      else if ((rc = doubled_push(h, s, st, true))) return rc;
     }
     int rc = pw_literal(h, s, 0, st);                                   // dG_n at tau = beta
     if (rc) return rc;
@@ -1271,6 +1316,12 @@ int init_ueg_impl(const ftafqmc_params* p, int n_sys, void* d_workspace, size_t 
          hipEventCreateWithFlags(&h->join[l - 1], hipEventDisableTiming) == hipSuccess;
   for (auto& s : h->sys)
     ok = ok && hipEventCreate(&s.t0) == hipSuccess && hipEventCreate(&s.t1) == hipSuccess;
+  bool any_ckpt = false;
+  for (auto& s : h->sys) any_ckpt = any_ckpt || s.ckpt;
+  if (ok && any_ckpt && !no_side_streams && !std::getenv("FTAFQMC_SERIAL_BACKWARD")) {
+    ok = hipStreamCreateWithFlags(&h->bwd, hipStreamNonBlocking) == hipSuccess;
+    for (int e = 0; ok && e < 4; ++e) ok = hipEventCreateWithFlags(&h->bwd_ev[e], hipEventDisableTiming) == hipSuccess;
+  }
   if (!ok) { ftafqmc_destroy(h); return lib_init_error(FTAFQMC_E_HIP, "event or stream creation failed"); }
   h->ws = (char*)d_workspace;
   h->ws_bytes = ws_bytes;
@@ -1659,6 +1710,9 @@ void ftafqmc_destroy(ftafqmc_t h) {
     if (h->join[g]) (void)hipEventDestroy(h->join[g]);
   }
   if (h->fork) (void)hipEventDestroy(h->fork);
+  if (h->bwd) { (void)hipStreamSynchronize(h->bwd); (void)hipStreamDestroy(h->bwd); }
+  for (auto& e : h->bwd_ev)
+    if (e) (void)hipEventDestroy(e);
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   if (h->cap) { (void)hipStreamSynchronize(h->cap); (void)hipStreamDestroy(h->cap); }
   delete h;

@@ -135,6 +135,11 @@ struct TanDev {
   double2* Gd;            // [W][ld2][ld2] literal doubled Green's function at the current slice
   double* lnbt2;          // [ld2] ln diag B_T repeated for both halves
   double2* lndetX2;       // [W] (the elimination records its ln det there)
+  // the cyclic doubled solve's own augmented system and elimination scratch, so that it can run
+  // beside the re-factorisation of the doubled product (which uses dd.aug, dd.piv, dd.tri)
+  double2* caug;          // [W][ld2][2 ld2]
+  int* cpiv;              // [W][ld2]
+  double2* ctri;          // [W][elim_tri_elems(2M)]
   double2* Gk; double2* dGk;   // [W][ld][ld] G_k and dG_k (blocks of Gd)
   double2* rk; double2* drk;   // [W][NQ] r_Q of G_k and its derivative
   double2* dcq;           // [W][NQ] derivative of the shifted coefficients

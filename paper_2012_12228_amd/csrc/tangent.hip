@@ -117,7 +117,7 @@ __global__ __launch_bounds__(NT) void cyc_form_kernel(SysDev s, TanDev t, int k,
     tY[yy][tx] = (row < M2 && col < M2) ? Y[(long long)row * ld2 + col] : zero2();
   }
   __syncthreads();
-  double2* aug = t.dd.aug + (long long)w * t.dd.aug_stride;
+  double2* aug = t.caug + (long long)w * t.dd.aug_stride;
   for (int yy = ty; yy < TT; yy += 8) {
     const int i = ti * TT + yy, j = tj * TT + tx;
     if (i >= ld2 || j >= ld2) continue;
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(NT) void cyc_post_kernel(SysDev s, TanDev t, int k,
     const long long w = e / per;
     const int loc = (int)(e - w * per);
     const int r = loc / ld, j = loc - r * ld;
-    const double2* Z = t.dd.aug + w * t.dd.aug_stride + ld2;   // Z[i][c] at i * 2 ld2 + c
+    const double2* Z = t.caug + w * t.dd.aug_stride + ld2;     // Z[i][c] at i * 2 ld2 + c
     double2 v = zero2();
     if (literal) {
       if (r < M && j < M) v = Z[(long long)r * 2 * ld2 + M + j];

@@ -293,3 +293,20 @@ def test_pathwise_autograd_function():
     assert gp[0] == pytest.approx(2.0 * jac[0].real - 0.5 * jac[1].real, rel=1e-13)
     assert gp[1] == pytest.approx(2.0 * jac[2].real - 0.5 * jac[3].real, rel=1e-13)
     assert abs(gp[0] - grads[F.FrozenPathMeans][0]) > 1e-6 * abs(gp[0])
+
+
+@pytest.mark.parametrize("mode", ["frozen", "pathwise"])
+def test_backward_side_stream_schedule_is_bit_identical(mode, monkeypatch):
+    """The backward pass runs the doubled re-factorisation (and, pathwise, the cyclic solve) on a
+    second stream; FTAFQMC_SERIAL_BACKWARD=1 keeps everything on the caller's stream.  Both
+    schedules do the same arithmetic: identical bits."""
+    F = _F()
+    sd = dict(n_elec=38, rs=1.0, theta=0.25, nmax2=5, dtau=0.05, stab_every=4, walkers=6, kscale=0.9, mu=1.5)
+    s = oracle_system(sd)
+    flds = si.fields(4242, sd["walkers"], s.n_slices, s.NQ)
+    m = F.PATHWISE if mode == "pathwise" else F.FROZEN_PATH
+    a = gpu_backward(F, sd, flds, mode=m)
+    monkeypatch.setenv("FTAFQMC_SERIAL_BACKWARD", "1")
+    b = gpu_backward(F, sd, flds, mode=m)
+    assert np.array_equal(a["walker"], b["walker"], equal_nan=True)
+    assert np.array_equal(a["jac"], b["jac"])
