@@ -465,6 +465,23 @@ def main():
                      "avg_launch_ms": r["gemm_avg_ms"]},
         "fp64": results.get("fp64"), "mixed": results.get("mixed"), "mixed_vs_fp64": cmp,
     }
+    if not args.no_extra_workloads and args.workload == "ueg_n66_m171":
+        # the mixed path with its propagator products on the BF16 matrix cores (split operands)
+        fl = load_fields(F, torch, args.workload)
+        systems = [dict(sd, precision=1, flags=F.FTAFQMC_BF16_SPLIT) for sd in wl["systems"]]
+        ctx, rb, enb = run_precision(F, torch, systems, fl, args.steps, args.warmup)
+        ctx.close()
+        del fl
+        torch.cuda.empty_cache()
+        issued = 6 * rb["gemm_tflops"]
+        line["bf16_split"] = {
+            "walker_slices_per_s": rb["walker_slices_per_s"], "ms_per_step": rb["ms_per_step"],
+            "gemm_ms_per_step": rb["profile_ms_per_step"]["gemm"],
+            "fp32_mfma_gemm_ms_per_step": results["mixed"]["profile_ms_per_step"]["gemm"],
+            "gemm_useful_tflops": rb["gemm_tflops"], "gemm_issued_bf16_tflops": issued,
+            "gemm_frac_of_bf16_peak_issued": issued / 2500.0,
+            "vs_fp64": mixed_vs_fp64(results["energies"]["fp64"], enb)}
+        print("bench: bf16 split %.1f walker*slices/s" % rb["walker_slices_per_s"], file=sys.stderr, flush=True)
     if not args.no_extra_workloads:
         extra = {}
         for name in ("ueg_uneven4", "ueg_n114_m485"):

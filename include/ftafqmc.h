@@ -82,7 +82,7 @@ typedef struct {
   int precision;   /* FTAFQMC_FP64 or FTAFQMC_MIXED */
   int flags;       /* 0, or any of FTAFQMC_CHECKPOINT, FTAFQMC_OVERLAP, FTAFQMC_GRAPH,
                       FTAFQMC_TRIAL_THF, FTAFQMC_MODIFIED_OVERLAP, FTAFQMC_MEASURE_EVERY_SLICE,
-                      FTAFQMC_LOW_RANK */
+                      FTAFQMC_LOW_RANK, FTAFQMC_BF16_SPLIT */
 } ftafqmc_params;
 
 /* flags: record the sampled path (the shifted coefficients c_Q and tr G of every slice) so
@@ -126,6 +126,12 @@ typedef struct {
  * FTAFQMC_MODIFIED_OVERLAP. */
 #define FTAFQMC_LOW_RANK 64
 #define FTAFQMC_LOW_RANK_THRESHOLD 1e-6
+/* flags (FTAFQMC_MIXED only): the propagator products (the Taylor chain of e^V and its
+ * application to Y) on the BF16 matrix cores with every FP32 operand split into three bf16
+ * parts and the six split products down to 2^-16 of the leading one kept, FP32 accumulation
+ * (the same 24-bit operand precision as the FP32 products it replaces; results differ from them
+ * at the rounding level).  Everything else as FTAFQMC_MIXED. */
+#define FTAFQMC_BF16_SPLIT 128
 /* ftafqmc_backward modes */
 #define FTAFQMC_FROZEN_PATH 0
 #define FTAFQMC_PATHWISE 1

@@ -27,6 +27,7 @@ FTAFQMC_MODIFIED_OVERLAP = 16     # params flag: constraint from the modified ov
 FTAFQMC_MEASURE_EVERY_SLICE = 32  # params flag: an energy record after every slice
 FTAFQMC_LOW_RANK = 64      # params flag: low-rank truncation of the Green's function solve (eq. thresh)
 LOW_RANK_THRESHOLD = 1e-6  # FTAFQMC_LOW_RANK_THRESHOLD
+FTAFQMC_BF16_SPLIT = 128   # params flag (mixed only): propagator products on BF16 matrix cores, split operands
 FTAFQMC_PROFILE_ONLY = 256  # ftafqmc_profile: record only the classes in the low bits
 FROZEN_PATH = 0            # ftafqmc_backward modes: shifted fields held fixed
 PATHWISE = 1               #   raw fields held fixed, the force bias follows G_k

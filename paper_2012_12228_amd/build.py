@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libftafqmc.so")
-SOURCES = ["host.cpp", "gemm.hip", "elim.hip", "slice.hip", "tangent.hip", "static_ws.hip", "popctl.hip"]
+SOURCES = ["host.cpp", "gemm.hip", "gemm_bf16.hip", "elim.hip", "slice.hip", "tangent.hip", "static_ws.hip", "popctl.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-munsafe-fp-atomics"]

@@ -77,6 +77,7 @@ struct HostSys {
   int taylor_nb = 4;                    // Paterson-Stockmeyer blocks of 4: degree 4 taylor_nb
   bool modified = false;                // constraint from the modified overlap ratio (eq. ztfix)
   bool lowrank = false;                 // low-rank truncation of the Green's function solve (eq. thresh)
+  bool bf16 = false;                    // mixed propagator products on BF16 matrix cores, split operands
   std::vector<int> lr_order, lr_pos;    // plane waves by decreasing ln B_T, and the inverse order
   std::vector<int> lr_mL;               // [n + 1] left rank of the solve after slice k
   bool every = false;                   // energy record after every slice
@@ -101,8 +102,10 @@ std::string build_tables(HostSys& s, const ftafqmc_params& p) {
   if (p.precision != FTAFQMC_FP64 && p.precision != FTAFQMC_MIXED) return "unknown precision";
   if (!std::isfinite(p.kscale)) return "kscale must be finite";
   if (p.flags & ~(FTAFQMC_CHECKPOINT | FTAFQMC_OVERLAP | FTAFQMC_GRAPH | FTAFQMC_TRIAL_THF | FTAFQMC_MODIFIED_OVERLAP |
-                  FTAFQMC_MEASURE_EVERY_SLICE | FTAFQMC_LOW_RANK))
+                  FTAFQMC_MEASURE_EVERY_SLICE | FTAFQMC_LOW_RANK | FTAFQMC_BF16_SPLIT))
     return "unknown flags";
+  s.bf16 = (p.flags & FTAFQMC_BF16_SPLIT) != 0;
+  if (s.bf16 && p.precision != FTAFQMC_MIXED) return "the split-BF16 products belong to the mixed precision";
   s.lowrank = (p.flags & FTAFQMC_LOW_RANK) != 0;
   if (s.lowrank && (p.flags & (FTAFQMC_CHECKPOINT | FTAFQMC_MODIFIED_OVERLAP)))
     return "the low-rank truncation is built for the standard overlap ratio without the derivative record";
@@ -592,6 +595,13 @@ int horner_step(ftafqmc_ctx* h, HostSys& s, SysDev& d, void* cur, void* nxt, int
 // step reads one matrix; blocks below those (nb > 4) come from an elementwise pass.  With
 // `check`, the column norms of V and V^4 are taken for the device-side truncation bound.
 // Forms B = K e^V K from d.V; *B_out points at the buffer that holds it (E0 or E1).
+// One product of the propagator chain: FP64 or FP32 MFMA, or with FTAFQMC_BF16_SPLIT the mixed
+// path's products on the BF16 matrix cores with three-way split operands.
+hipError_t chain_gemm(const HostSys& s, const GemmParams& g, int prec, hipStream_t st) {
+  if (s.bf16 && prec != GEMM_Z64) return launch_zgemm_bf16x6(g, prec == GEMM_C32_Z64B, st);
+  return launch_zgemm(g, prec, st);
+}
+
 int form_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st, void** B_out, bool check) {
   const bool mixed = s.p.precision == FTAFQMC_MIXED;
   const int prec = mixed ? GEMM_C32 : GEMM_Z64;
@@ -600,9 +610,9 @@ int form_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st, void*
   GemmParams g = gp_base(s, d);
   g.tile = s.tile_chain;
   g.A = d.V; g.B = d.V; g.C = d.V2;
-  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));   // V^2
+  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return chain_gemm(s, g, prec, st); }));   // V^2
   g.A = d.V2; g.B = d.V; g.C = d.V3;
-  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));   // V^3
+  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return chain_gemm(s, g, prec, st); }));   // V^3
   g.A = d.V2; g.B = d.V2; g.C = d.V4;                                                  // V^4 and the blocks
   g.tile = s.tile_epi;
   g.P1 = d.V; g.P2 = d.V2; g.P3 = d.V3;
@@ -612,7 +622,7 @@ int form_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st, void*
   for (int k = nb - 2; k >= 0 && ne < 4; --k, ++ne)
     g.extra[ne] = GemmOut{d.Bk[k], 0.0, inv_fact(4 * k), inv_fact(4 * k + 1), inv_fact(4 * k + 2), inv_fact(4 * k + 3)};
   g.nextra = ne;
-  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(g, prec, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return chain_gemm(s, g, prec, st); }));
   const int nlo = nb - ne;                      // blocks B_0 .. B_{nlo-1} not written by the epilogue
   if (nlo > 0) {
     TaylorLow t;
@@ -642,7 +652,7 @@ int horner_step(ftafqmc_ctx* h, HostSys& s, SysDev& d, void* cur, void* nxt, int
   e.A = cur; e.B = d.V4; e.C = nxt;
   e.P1 = d.Bk[k]; e.c1 = 1.0;
   if (k == 0) { e.rs = d.kh; e.cs = d.kh; }            // K e^V K
-  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(e, mixed ? GEMM_C32 : GEMM_Z64, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return chain_gemm(s, e, mixed ? GEMM_C32 : GEMM_Z64, st); }));
   return FTAFQMC_OK;
 }
 
@@ -654,7 +664,7 @@ int apply_propagator(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st) {
   GemmParams a = gp_base(s, d);
   a.tile = s.tile_apply;
   a.A = cur; a.B = d.Y; a.C = d.Ynew;
-  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return launch_zgemm(a, mixed ? GEMM_C32_Z64B : GEMM_Z64, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_GEMM, st, [&] { return chain_gemm(s, a, mixed ? GEMM_C32_Z64B : GEMM_Z64, st); }));
   std::swap(d.Y, d.Ynew);
   return FTAFQMC_OK;
 }

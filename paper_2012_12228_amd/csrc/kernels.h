@@ -25,6 +25,9 @@ struct GemmParams {
   int skip0, skip1;          // role 1: rows [skip0, skip1) of C are not written
 };
 hipError_t launch_zgemm(const GemmParams& p, int prec, hipStream_t s);
+// The mixed propagator's products on the BF16 matrix cores with three-way split operands
+// (complex64 A; B complex128 when wide_b, else complex64; C as B); role 0, A and B as stored.
+hipError_t launch_zgemm_bf16x6(const GemmParams& p, bool wide_b, hipStream_t s);
 int gemm_tile_count();
 bool gemm_tile_supported(int tile, int prec);   // shapes built for this precision
 bool gemm_tile_walker_sized(int tile);           // one workgroup per walker (fills every CU at W >= 256)

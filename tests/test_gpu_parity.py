@@ -412,11 +412,11 @@ def _check_golden(gold, key, trace, logw, G, slices, mixed=False):
     assert rel_mat(G[:rows.shape[0]], rows) < tol
 
 
-def _full_size(name, precision):
+def _full_size(name, precision, flags=0):
     F = _F()
     wl = si.WORKLOADS[name]
     gold = _golden(name)
-    systems = [dict(sd, precision=precision) for sd in wl["systems"]]
+    systems = [dict(sd, precision=precision, flags=flags) for sd in wl["systems"]]
     oss = [oracle_system(sd) for sd in systems]
     flds = [si.fields(si.system_seed(name, i), sd["walkers"], s.n_slices, s.NQ)
             for i, (sd, s) in enumerate(zip(systems, oss))]
@@ -439,6 +439,36 @@ def test_m171_full_size_fp64():
 
 def test_m171_full_size_mixed():
     _full_size("ueg_n66_m171", 1)
+
+
+def test_m171_full_size_mixed_bf16_split():
+    """The mixed path with its propagator products on the BF16 matrix cores (three-way split
+    operands, FTAFQMC_BF16_SPLIT) to the same mixed-precision bars."""
+    F = _F()
+    _full_size("ueg_n66_m171", 1, F.FTAFQMC_BF16_SPLIT)
+
+
+def test_m19_all_walkers_mixed_bf16_split():
+    F = _F()
+    wl = si.WORKLOADS["ueg_n14_m19"]
+    sd = dict(wl["systems"][0], precision=1, flags=F.FTAFQMC_BF16_SPLIT)
+    s = oracle_system(sd)
+    W = sd["walkers"]
+    flds = si.fields(si.system_seed("ueg_n14_m19", 0), W, s.n_slices, s.NQ)
+    ctx, _ = gpu_run(F, [sd], [flds])
+    rec = ctx.records()
+    trace, logw = rec["trace"].cpu().numpy(), rec["logw"].cpu().numpy()
+    G = ctx.greens().cpu().numpy()
+    for w in range(W):
+        ref = path.run_walker(s, flds[w], energy_fn=energy.local_energy)
+        check_walker(trace[:, w], logw[:, w], G[w], ref, mixed=True, label="walker %d" % w)
+
+
+def test_bf16_split_needs_the_mixed_precision():
+    F = _F()
+    sd = dict(si.WORKLOADS["ueg_n14_m19"]["systems"][0], precision=0, flags=F.FTAFQMC_BF16_SPLIT)
+    with pytest.raises(RuntimeError, match="E_ARG"):
+        F.ftafqmc_workspace_bytes([sd])
 
 
 def test_m123_full_size_fp64():
