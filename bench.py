@@ -392,6 +392,11 @@ def main():
     ap.add_argument("--profile-run", action="store_true",
                     help="one warm-up path and one path of --precision (mixed when 'both') with no HIP events and "
                          "no other measurement: the program rocprofv3 kernel-trace and counter passes run")
+    ap.add_argument("--profile-flags", type=int, default=0,
+                    help="with --profile-run: params flags of the profiled systems (e.g. 64 low rank, 128 split BF16)")
+    ap.add_argument("--profile-backward", choices=["frozen", "pathwise"], default=None,
+                    help="one warm-up and one derivative pass of that mode on the M=123 workload, nothing else "
+                         "(the program of the backward kernel-trace pass)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -410,10 +415,27 @@ def main():
         torch.cuda.synchronize()
         del src_t, dst_t
     wl = si.WORKLOADS[args.workload]
+    if args.profile_backward:
+        name = "ueg_n38_m123"
+        sd = dict(si.WORKLOADS[name]["systems"][0], precision=0, flags=F.FTAFQMC_CHECKPOINT)
+        ctx = F.Context(sd)
+        inf = ctx.info()
+        f = torch.from_numpy(si.fields(si.system_seed(name, 0), sd["walkers"], inf["n_slices"], inf["n_q"])).cuda()
+        ctx.propagate(f)
+        ctx.energy()
+        mode = F.PATHWISE if args.profile_backward == "pathwise" else F.FROZEN_PATH
+        ctx.backward(mode=mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.backward(mode=mode)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_backward": args.profile_backward, "seconds": time.perf_counter() - t0}))
+        ctx.close()
+        return
     if args.profile_run:
         p = "mixed" if args.precision == "both" else args.precision
         fields = load_fields(F, torch, args.workload)
-        ctx = F.Context([dict(sd, precision=0 if p == "fp64" else 1) for sd in wl["systems"]])
+        ctx = F.Context([dict(sd, precision=0 if p == "fp64" else 1, flags=args.profile_flags) for sd in wl["systems"]])
         _path(ctx, fields, len(wl["systems"]))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
