@@ -459,6 +459,9 @@ size_t layout(HostSys& s, char* base, size_t off) {
   s.bytes = off - s.off_begin;
   d.M = M; d.ld = ld; d.NQ = NQ; d.W = W; d.n = s.n; d.grid_dim = s.gdim; d.grid_c0 = s.gc0;
   d.rq_rows = s.rq_rows; d.rq_nblk = s.rq_nblk;
+  // the gather form of r_Q serves N_Q above 4096 (M near 512); FTAFQMC_RQ_GATHER=1 selects it
+  // everywhere (its test)
+  d.rq_gather = std::getenv("FTAFQMC_RQ_GATHER") && std::atoi(std::getenv("FTAFQMC_RQ_GATHER")) == 1;
   d.dtau = s.dtau; d.kscale = s.p.kscale; d.e_madelung = s.EM;
   d.taylor_deg = 4 * s.taylor_nb;
   d.taylor_tol = TAYLOR_CHECK_TOL[s.p.precision == FTAFQMC_MIXED ? 1 : 0];

@@ -68,6 +68,7 @@ struct SysDev {
   const int* rbptr;       // [rq_nblk (NQ+1)]
   const int* rbidx;       // [M(M-1)]
   int rq_rows, rq_nblk;
+  int rq_gather;          // 1: r_Q by the per-Q gather kernel even where the LDS-streamed one applies
   const short* grid;      // [grid_dim^3] basis index of an integer vector, -1 outside
   const int* flat;        // [M] flat offset of each basis vector in the lookup grid
   // state

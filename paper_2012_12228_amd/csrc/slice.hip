@@ -894,7 +894,7 @@ hipError_t launch_lr_rank(const SysDev& s, int k, hipStream_t st) {
 }
 int rq_block_elems() { return RQ_ELEMS; }
 hipError_t launch_rq(const SysDev& s, hipStream_t st) {
-  if (s.NQ > 0 && s.NQ <= RQ_QPT * RQ_NT && s.rq_rows * s.ld <= RQ_ELEMS) {
+  if (!s.rq_gather && s.NQ > 0 && s.NQ <= RQ_QPT * RQ_NT && s.rq_rows * s.ld <= RQ_ELEMS) {
     rq_stream_kernel<<<s.W, RQ_NT, 0, st>>>(s);
   } else {
     const int chunks = (s.NQ + NT - 1) / NT;

@@ -608,3 +608,27 @@ def test_concurrent_systems_match_serial_schedule(monkeypatch):
         a, b = conc.energy(i), ser.energy(i)
         assert torch.equal(a["local"], b["local"]) and torch.equal(a["logw"], b["logw"]), i
         assert torch.equal(conc.greens(i), ser.greens(i)), i
+
+
+def test_rq_gather_kernel_matches_the_streamed_one(monkeypatch):
+    """r_Q has two kernels: the LDS-streamed one (N_Q <= 4096, every workload here) and the per-Q
+    gather for larger N_Q.  FTAFQMC_RQ_GATHER=1 runs the gather form on a ragged M=57 path and on
+    M=19: the oracle's bar holds for both, and the two agree to rounding."""
+    F = _F()
+    for sd, seed in ((dict(n_elec=38, rs=1.0, theta=0.25, nmax2=5, dtau=0.05, stab_every=4, walkers=4), 8),
+                     (dict(si.WORKLOADS["ueg_n14_m19"]["systems"][0], walkers=8), 9)):
+        s = oracle_system(sd)
+        flds = si.fields(seed, sd["walkers"], s.n_slices, s.NQ)
+        a, _ = gpu_run(F, [sd], [flds])
+        monkeypatch.setenv("FTAFQMC_RQ_GATHER", "1")
+        b, _ = gpu_run(F, [sd], [flds])
+        monkeypatch.delenv("FTAFQMC_RQ_GATHER")
+        ta, tb = a.records()["trace"].cpu().numpy(), b.records()["trace"].cpu().numpy()
+        assert rel_mat(tb, ta) < 1e-12
+        Gb = b.greens().cpu().numpy()
+        lw = b.records()["logw"].cpu().numpy()
+        for w in range(sd["walkers"]):
+            ref = path.run_walker(s, flds[w], energy_fn=energy.local_energy)
+            check_walker(tb[:, w], lw[:, w], Gb[w], ref, label=("gather", w))
+        a.close()
+        b.close()
