@@ -15,7 +15,18 @@
  *   - the phaseless weight w <- |I| max(0, cos theta) (eq. import, eq. phimport,
  *     eq. theta) with S = det(I + A_{k+1})^2 / det(I + A_k)^2;
  *   - the local energy E_M + E_1 + E_2 with Hartree and exchange parts (Sec.
- *     "Uniform Electron Gas", Gamma_Q and Lambda_Q) and the electron number.
+ *     "Uniform Electron Gas", Gamma_Q and Lambda_Q) and the electron number;
+ * and around that path (each declared below with its passage):
+ *   - derivatives of <E> and <N> at tau = beta in mu and lambda, along the frozen path
+ *     or pathwise (ftafqmc_backward);
+ *   - population control by the comb or pair branching, record statistics and time-slice
+ *     averages, <rho(Q) rho(-Q)> (Sec. "Computational Details", "Comparison to Other
+ *     Approaches");
+ *   - chemical-potential tuning by bracketing with a weighted line fit, or by Newton steps
+ *     from d<N>/dmu (ftafqmc_tune_mu);
+ *   - the thermal Hartree-Fock trial, the modified overlap ratio (eq. ztfix), the low-rank
+ *     truncation of the Green's function solve (eq. thresh) and the mixed-precision
+ *     propagator (flags of ftafqmc_params).
  *
  * Conventions shared by every entry point:
  *   - Spin-restricted: one M x M block per walker serves both spins; det(I + A)
