@@ -142,6 +142,7 @@ def run_precision(F, torch, systems, fields, steps, warmup):
     assert gemm_n == want_n, (gemm_n, want_n)
     flops = steps * sum(pr * inf["n_slices"] * 8.0 * inf["M"] ** 3 * inf["n_walkers"] for pr, inf in zip(prods, infos))
     out["taylor_degree"] = [inf["taylor_degree"] for inf in infos]
+    out["sizes"] = [{"M": inf["M"], "n": inf["n_slices"], "W": inf["n_walkers"]} for inf in infos]
     out["gemm_products_per_slice"] = prods
     out["gemm_avg_ms"] = gemm_ms / max(gemm_n, 1)
     out["gemm_flops_per_launch"] = flops / max(gemm_n, 1)
@@ -155,6 +156,28 @@ def run_precision(F, torch, systems, fields, steps, warmup):
     out["gemm_tiles"] = [(inf["gemm_tile_chain"], inf["gemm_tile_epilogue"], inf["gemm_tile_horner"],
                           inf["gemm_tile_apply"]) for inf in infos]
     return ctx, out, energies
+
+
+def end_to_end(wl, r, precision):
+    """End-to-end roofline of the one-stream path: the method's algorithmic FP64-equivalent flops
+    per walker-slice, F = 8 M^3 g + 14.7 M^3 + 13.3 M^3 / s + 2.6 M^3 / s (g propagator products:
+    the Paterson-Stockmeyer chain and the apply; one LU-class solve with its right-hand sides per
+    slice; QR, Q formation and T update, and the exchange sums, every s slices), times W n, over
+    the path time and the time-weighted peak (the propagator GEMMs' time at the peak of their MFMA
+    type, the rest at the FP64 peak)."""
+    flops = 0.0
+    for sd, deg, sz in zip(wl["systems"], r["taylor_degree"], r["sizes"]):
+        M = sz["M"]
+        g = deg // 4 + 3
+        F = 8 * M ** 3 * g + 14.7 * M ** 3 + (13.3 + 2.6) * M ** 3 / sd["stab_every"]
+        flops += F * sz["W"] * sz["n"]
+    t = r["ms_per_step"] * 1e-3
+    t_gemm = r["profile_ms_per_step"]["gemm"] * 1e-3
+    peak_gemm = PEAK_TFLOPS["f32" if precision == "mixed" else "f64"]
+    peak = (min(t_gemm, t) * peak_gemm + max(t - t_gemm, 0.0) * PEAK_TFLOPS["f64"]) / t
+    achieved = flops / t / 1e12
+    return {"flops_per_step": flops, "achieved_tflops": achieved, "time_weighted_peak_tflops": peak,
+            "frac": achieved / peak}
 
 
 def mixed_vs_fp64(en64, enmx):
@@ -486,6 +509,7 @@ def main():
                      "traffic": measured_traffic(args.workload, use),
                      "avg_launch_ms": r["gemm_avg_ms"]},
         "fp64": results.get("fp64"), "mixed": results.get("mixed"), "mixed_vs_fp64": cmp,
+        "end_to_end": end_to_end(wl, r, use),
     }
     if not args.no_extra_workloads and args.workload == "ueg_n66_m171":
         # the mixed path with its propagator products on the BF16 matrix cores (split operands)
