@@ -39,7 +39,7 @@ def test_workspace_sizes_of_the_workloads():
 
 @pytest.mark.parametrize("bad", [dict(n_elec=13), dict(n_elec=0), dict(nmax2=0), dict(walkers=0),
                                  dict(stab_every=0), dict(rs=-1.0), dict(theta=0.0), dict(dtau=0.0),
-                                 dict(nmax2=30), dict(precision=7), dict(n_elec=200, nmax2=1)])
+                                 dict(nmax2=30), dict(nmax2=25), dict(precision=7), dict(n_elec=200, nmax2=1)])
 def test_invalid_parameters_are_rejected(bad):
     _lib()
     sysdef = dict(si.WORKLOADS["ueg_n14_m19"]["systems"][0])
