@@ -547,15 +547,20 @@ def test_overlapped_walker_groups_give_identical_results():
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("overlap", [0, 1], ids=["one_stream", "overlap"])
+@pytest.mark.parametrize("overlap", [0, 1, 2], ids=["one_stream", "overlap", "lowrank_mixed_bf16"])
 def test_graph_replays_match_eager_paths(overlap):
     """FTAFQMC_GRAPH: the first whole-path call is captured, later calls replay the graph.  Every
     replay, with eager work (energy, G copies, a reset) between replays and with new field values
-    written into the same buffer, gives bit-identical records and G to eager propagation."""
+    written into the same buffer, gives bit-identical records and G to eager propagation; also
+    with the low-rank solve and the mixed split-BF16 chain (whose per-slice ranks and kernels are
+    part of the captured sequence)."""
     F = _F()
-    extra = F.FTAFQMC_OVERLAP if overlap else 0
+    extra = {0: 0, 1: F.FTAFQMC_OVERLAP, 2: F.FTAFQMC_LOW_RANK | F.FTAFQMC_BF16_SPLIT}[overlap]
     sd = dict(n_elec=38, rs=1.0, theta=0.25, nmax2=5, dtau=0.05, stab_every=4, walkers=24)
     sd2 = dict(n_elec=14, rs=0.5, theta=0.0625, nmax2=2, dtau=0.05, stab_every=10, walkers=9)
+    if overlap == 2:                                  # a low-temperature system whose solve truncates
+        sd = dict(n_elec=14, rs=1.0, theta=0.0625, nmax2=5, dtau=0.05, stab_every=10, walkers=16, precision=1)
+        sd2 = dict(sd2, precision=1)
     s1, s2 = oracle_system(sd), oracle_system(sd2)
     fa = [si.fields(s, sdx["walkers"], so.n_slices, so.NQ) for s, sdx, so in ((61, sd, s1), (62, sd2, s2))]
     fb = [si.fields(s, sdx["walkers"], so.n_slices, so.NQ) for s, sdx, so in ((71, sd, s1), (72, sd2, s2))]
