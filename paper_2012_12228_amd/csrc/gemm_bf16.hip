@@ -12,9 +12,13 @@
 // at 16 times the FP32 rate per instruction-cycle.
 //
 // Tile: 64 x 64 outputs per workgroup of 4 waves (2 x 2 waves of 32 x 32, 2 x 2 blocks of 16 x 16
-// each), K staged through LDS 32 deep as six bf16 planes (re0, re1, re2, im0, im1, im2) per
-// operand, k-contiguous for both operands so that each lane reads its 8 k-consecutive values of
-// a block row (A) or block column (B) with one 16-byte LDS load per plane.
+// each), K staged through LDS 32 deep as complex64, k-contiguous for both operands (A as [m][k],
+// B transposed to [n][k]), so that each lane reads the 8 k-consecutive entries of its block row
+// (A) or block column (B) as 64 contiguous bytes and splits them into the six bf16 planes
+// (re0, re1, re2, im0, im1, im2) in registers with packed conversions.  The staging is
+// double-buffered in 68 KB (two workgroups per CU): the next chunk's global loads are issued
+// before the current chunk's MFMAs and written to the other buffer after them, one barrier per
+// chunk.
 // Epilogue and parameters as the other GEMMs of the propagator (GemmParams, role 0): C (complex64
 // or complex128) = diag(rs) [alpha A B + beta C + cI I + c1 P1 + c2 P2 + c3 P3] diag(cs), with up
 // to four extra outputs from the same product.  A is complex64, B complex64 or complex128
@@ -30,17 +34,27 @@ namespace {
 
 constexpr int BM = 64, BN = 64, BK = 32, WM = 32, WN = 32, NT = 256;
 constexpr int FM = WM / 16, FN = WN / 16;
-constexpr int KP = BK + 8;                // LDS row: 32 bf16 of k plus 16 bytes against bank conflicts
+constexpr int KP = BK + 2;                // LDS row: 32 complex64 of k plus 16 bytes against bank conflicts
 
-struct Split3 { __bf16 h[3]; };
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-FT_DEV Split3 split3(float x) {
-  Split3 s;
-  s.h[0] = (__bf16)x;
-  const float r1 = x - (float)s.h[0];
-  s.h[1] = (__bf16)r1;
-  s.h[2] = (__bf16)(r1 - (float)s.h[1]);
-  return s;
+// Two FP32 values to a packed bf16 pair, round to nearest even (one v_cvt_pk_bf16_f32); element 0
+// in the low half.
+FT_DEV unsigned cvt2(float a, float b) {
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+}
+// The three-way split of a pair: h0 = bf16(x), h1 = bf16(x - h0), h2 = bf16(x - h0 - h1), each a
+// packed pair (a bf16 widens to FP32 by a 16-bit shift, so the residuals are exact FP32 differences).
+FT_DEV void split2(float a, float b, unsigned& h0, unsigned& h1, unsigned& h2) {
+  h0 = cvt2(a, b);
+  a -= __uint_as_float(h0 << 16);
+  b -= __uint_as_float(h0 & 0xffff0000u);
+  h1 = cvt2(a, b);
+  a -= __uint_as_float(h1 << 16);
+  b -= __uint_as_float(h1 & 0xffff0000u);
+  h2 = cvt2(a, b);
 }
 
 FT_DEV float2 as_f2(float2 v) { return v; }
@@ -56,9 +70,8 @@ FT_DEV f32x4 mma(bf16x8 a, bf16x8 b, f32x4 c) { return __builtin_amdgcn_mfma_f32
 
 template <typename TB, typename TC>
 __global__ __launch_bounds__(NT) void zgemm_bf16x6_kernel(GemmParams p) {
-  // planes 0..2: the real part's splits, 3..5: the imaginary part's
-  __shared__ __attribute__((aligned(16))) __bf16 As[6][BM][KP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[6][BN][KP];
+  __shared__ __attribute__((aligned(16))) float2 As[2][BM][KP];
+  __shared__ __attribute__((aligned(16))) float2 Bs[2][BN][KP];
 
   int w, tile;
   if (!xcd_walker_tile(blockIdx.x, p.W, p.tiles_m * p.tiles_n, &w, &tile)) return;
@@ -93,25 +106,28 @@ __global__ __launch_bounds__(NT) void zgemm_bf16x6_kernel(GemmParams p) {
       rb[e] = ok ? as_f2(v) : make_float2(0.f, 0.f);
     }
   };
-  auto stage = [&]() {
-    bf16x8 pa[6], pb[6];
+  auto stage = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const Split3 xr = split3(ra[e].x), xi = split3(ra[e].y);
-      const Split3 yr = split3(rb[e].x), yi = split3(rb[e].y);
+    for (int e = 0; e < 8; e += 2) {
+      *(float4*)&As[buf][ar][ak + e] = make_float4(ra[e].x, ra[e].y, ra[e + 1].x, ra[e + 1].y);
+      *(float4*)&Bs[buf][bn][bk + e] = make_float4(rb[e].x, rb[e].y, rb[e + 1].x, rb[e + 1].y);
+    }
+  };
+  // a fragment: 8 k-consecutive complex64 entries, split into the six bf16 planes (dword d of a
+  // plane holds the entries 2d and 2d + 1)
+  auto frag = [&](const float2* src, bf16x8 (&out)[6]) {
+    u32x4 pl[6];
 #pragma unroll
-      for (int s = 0; s < 3; ++s) {
-        pa[s][e] = xr.h[s];
-        pa[3 + s][e] = xi.h[s];
-        pb[s][e] = yr.h[s];
-        pb[3 + s][e] = yi.h[s];
-      }
+    for (int d = 0; d < 4; ++d) {
+      const float4 v = *(const float4*)(src + 2 * d);   // re_2d, im_2d, re_2d+1, im_2d+1
+      unsigned h[6];
+      split2(v.x, v.z, h[0], h[1], h[2]);
+      split2(v.y, v.w, h[3], h[4], h[5]);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) pl[q][d] = h[q];
     }
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      *(bf16x8*)&As[s][ar][ak] = pa[s];
-      *(bf16x8*)&Bs[s][bn][bk] = pb[s];
-    }
+    for (int q = 0; q < 6; ++q) out[q] = __builtin_bit_cast(bf16x8, pl[q]);
   };
 
   // the leading split product a0 b0 and the five smaller ones accumulate apart, so that the small
@@ -134,18 +150,16 @@ __global__ __launch_bounds__(NT) void zgemm_bf16x6_kernel(GemmParams p) {
   const int li = lane & 15, lk = 8 * (lane >> 4);
   const int nk = (Kd + BK - 1) / BK;
   load(0);
-  stage();
+  stage(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load(kt + 1);
     bf16x8 a[FM][6], b[FN][6];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FM; ++i) frag(&As[buf][wr * WM + i * 16 + li][lk], a[i]);
 #pragma unroll
-      for (int s = 0; s < 6; ++s) a[i][s] = *(const bf16x8*)&As[s][wr * WM + i * 16 + li][lk];
-#pragma unroll
-    for (int j = 0; j < FN; ++j)
-#pragma unroll
-      for (int s = 0; s < 6; ++s) b[j][s] = *(const bf16x8*)&Bs[s][wc * WN + j * 16 + li][lk];
+    for (int j = 0; j < FN; ++j) frag(&Bs[buf][wc * WN + j * 16 + li][lk], b[j]);
     // the imaginary planes of B negated once: re -= a.im b.im as a.im (-b.im)
 #pragma unroll
     for (int j = 0; j < FN; ++j)
@@ -178,12 +192,8 @@ __global__ __launch_bounds__(NT) void zgemm_bf16x6_kernel(GemmParams p) {
           I = mma(a[i][s], neg8(b[j][3 + u]), I);   // + a.re b.im
         }
     }
+    if (kt + 1 < nk) stage(buf ^ 1);
     __syncthreads();
-    if (kt + 1 < nk) {
-      load(kt + 1);
-      stage();
-      __syncthreads();
-    }
   }
 
   TC* C = (TC*)p.C + (long long)w * p.sC;
