@@ -28,6 +28,7 @@
 #include "common.h"
 #include "kernels.h"
 #include <climits>
+#include <cstdlib>
 #include <cstring>
 
 namespace {
@@ -49,6 +50,13 @@ struct PanelParams {
 constexpr long long TRI_T1 = 0, TRI_T2 = NB * NB, TRI_TL = 2 * NB * NB;
 constexpr long long TRI_ELEMS = 2 * NB * NB + 4 * NB * NB;
 constexpr int GJ_WIDE_MIN_M = 256;      // 64-column Gauss-Jordan steps above this order (measured)
+
+// The order above which the solve takes 64-column steps; FTAFQMC_GJ_WIDE_MIN_M=<order> in the
+// environment overrides it (for experiments; read at every solve).
+int gj_wide_min_m() {
+  const char* env = std::getenv("FTAFQMC_GJ_WIDE_MIN_M");
+  return env ? std::atoi(env) : GJ_WIDE_MIN_M;
+}
 
 template <int NT>
 struct PanelShared {
@@ -408,6 +416,192 @@ __global__ __launch_bounds__(NT) void panel_gj_kernel(PanelParams p) {
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Gauss-Jordan panel, column-split layout.  The same elimination as panel_gj_kernel with the
+// work laid out the other way: NW = NB / CPW waves, wave w holding panel columns
+// [w CPW, (w+1) CPW) of every row (lane l, slot s: row j0 + l + 64 s).  Column C belongs to
+// one wave, which searches the pivot alone (no cross-wave reduction) and computes the
+// multiplier of every row; the multipliers reach the other waves through LDS, one entry per
+// row, and each wave takes the pivot row's entries in its own columns from its own registers
+// (readlane).  Per column that moves one entry per row through LDS instead of the whole pivot
+// row to every thread.  The pivot choice (per group of 64 rows the lowest row among the
+// largest keys, then the lowest label among the groups), the multipliers and every update are
+// those of panel_gj_kernel, operation for operation, so the two give identical results.
+template <int SL>
+struct GjSplitShared {
+  double2 g[2][SL][64];             // multipliers of column C, by column parity
+  double2 pv[2];
+  int info[2][4];                   // pivot label, its lane and slot, found
+  double2 pivv[NB];
+  int swapped[NB];
+};
+
+FT_DEV double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+FT_DEV int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <int SL, int CPW>
+__global__ __launch_bounds__(64 * (NB / CPW)) void panel_gj_split_kernel(PanelParams p) {
+  constexpr int NW = NB / CPW;
+  __shared__ GjSplitShared<SL> sh;
+  const int w = blockIdx.x;
+  if (w >= p.W) return;
+  double2* aug = p.aug + (long long)w * p.stride;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int M = p.M, j0 = p.j0, jb = p.jb, lda = p.lda;
+  const int cw = wid * CPW;                // this wave's first panel column
+  double2 a[SL][CPW];
+  int label[SL];
+  bool chosen[SL];
+  double2 mypv[SL];
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    const int r = j0 + lane + 64 * s;
+    label[s] = r;
+    chosen[s] = false;
+    mypv[s] = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < CPW; ++i)
+      a[s][i] = (r < M && cw + i < jb) ? aug[(long long)r * lda + j0 + cw + i] : make_double2(0.0, 0.0);
+  }
+  int* piv = p.piv + (long long)w * p.ld;
+#pragma unroll 1
+  for (int grp = 0; grp < NW && grp * CPW < jb; ++grp) {
+#pragma unroll
+    for (int cc = 0; cc < CPW; ++cc) {
+      const int C = grp * CPW + cc;
+      if (C >= jb) break;                  // uniform
+      const int col = j0 + C, buf = C & 1;
+      double2 g[SL], ncol[SL];
+      if (wid == grp) {                    // the wave holding column C
+        double2 f[SL];
+        int key[SL], kmax = -1;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+          f[s] = a[s][cc];
+          const bool cand = label[s] >= col && label[s] < M;
+          const double bv = cabs2(f[s]);
+          key[s] = (cand && bv == bv) ? __double2hiint(bv) : -1;
+          kmax = max(kmax, key[s]);
+        }
+        const int mk = wave_max_int(kmax);
+        int bi = INT_MAX, bl = 0, bs = 0;
+        const bool ok = mk >= 0;
+        if (ok) {
+#pragma unroll
+          for (int s = 0; s < SL; ++s) {
+            const unsigned long long hit = __ballot(key[s] == mk);
+            if (hit) {
+              const int lead = __ffsll((long long)hit) - 1;
+              const int ix = __builtin_amdgcn_readlane(label[s], lead);
+              if (ix < bi) { bi = ix; bl = lead; bs = s; }
+            }
+          }
+        }
+        const int prow = ok ? bi : col;
+        double2 pv = make_double2(NAN, NAN);
+        if (ok) {
+#pragma unroll
+          for (int s = 0; s < SL; ++s)
+            if (s == bs) pv = make_double2(readlane_d(f[s].x, bl), readlane_d(f[s].y, bl));
+        }
+        const double2 rc = crecip_newton(pv);
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+          const bool ispiv = ok && label[s] == prow;
+          const bool upd = ok && j0 + lane + 64 * s < M && !ispiv;
+          const double2 q = cmul(f[s], rc);
+          g[s] = upd ? q : make_double2(0.0, 0.0);
+          sh.g[buf][s][lane] = g[s];
+          ncol[s] = upd ? make_double2(-g[s].x, -g[s].y) : (ispiv ? make_double2(1.0, 0.0) : f[s]);
+        }
+        if (lane == 0) {
+          sh.info[buf][0] = prow;
+          sh.info[buf][1] = bl;
+          sh.info[buf][2] = bs;
+          sh.info[buf][3] = ok ? 1 : 0;
+          sh.pv[buf] = pv;
+          piv[col] = prow;
+          sh.pivv[C] = pv;
+          sh.swapped[C] = prow != col;
+        }
+      }
+      __syncthreads();
+      const int prow = uniform_i(sh.info[buf][0]), bl = uniform_i(sh.info[buf][1]);
+      const int bs = uniform_i(sh.info[buf][2]);
+      const bool ok = uniform_i(sh.info[buf][3]) != 0;
+      const double2 pv = sh.pv[buf];
+      if (wid != grp) {
+#pragma unroll
+        for (int s = 0; s < SL; ++s) g[s] = sh.g[buf][s][lane];
+      }
+      // the pivot row's entries in this wave's columns (it is not updated in this column)
+      double2 pr[CPW];
+#pragma unroll
+      for (int i = 0; i < CPW; ++i) pr[i] = make_double2(0.0, 0.0);
+      if (ok) {
+#pragma unroll
+        for (int s = 0; s < SL; ++s)
+          if (s == bs) {
+#pragma unroll
+            for (int i = 0; i < CPW; ++i) pr[i] = make_double2(readlane_d(a[s][i].x, bl), readlane_d(a[s][i].y, bl));
+          }
+      }
+#pragma unroll
+      for (int s = 0; s < SL; ++s) {
+#pragma unroll
+        for (int i = 0; i < CPW; ++i) a[s][i] = cfnms(a[s][i], g[s], pr[i]);
+      }
+      if (wid == grp) {
+#pragma unroll
+        for (int s = 0; s < SL; ++s) a[s][cc] = ncol[s];
+      }
+#pragma unroll
+      for (int s = 0; s < SL; ++s) {
+        const bool ispiv = ok && label[s] == prow;
+        if (ispiv) { label[s] = col; chosen[s] = true; mypv[s] = pv; }
+        else if (ok && label[s] == col) label[s] = prow;
+      }
+    }
+  }
+  // the row chosen for column c holds pv_c times row c of A11^{-1}
+  double2* tri = p.tri + (long long)w * p.tri_stride;
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    if (chosen[s]) {
+      const int c = label[s] - j0;
+      const double2 sc = crecip(mypv[s]);
+#pragma unroll
+      for (int i = 0; i < CPW; ++i) tri[c * NB + cw + i] = cw + i < jb ? cmul(a[s][i], sc) : make_double2(0.0, 0.0);
+    }
+  }
+  __syncthreads();                         // pivv / swapped of the last column
+  double lx = 0.0, ly = 0.0, nsw = 0.0, badv = 0.0;
+  if (t < jb) {
+    const double2 pvt = sh.pivv[t];
+    const double2 lg = clog(pvt);
+    lx = lg.x;
+    ly = lg.y;
+    nsw = sh.swapped[t] ? 1.0 : 0.0;
+    if (!(cabs2(pvt) > 0.0) || !isfinite(pvt.x) || !isfinite(pvt.y)) badv = 1.0;
+  }
+  if (wid == 0) {
+    lx = wave_sum(lx); ly = wave_sum(ly); nsw = wave_sum(nsw); badv = wave_sum(badv);
+  }
+  if (t == 0) {
+    if (p.lndet) {
+      double2 acc = j0 == 0 ? make_double2(0.0, 0.0) : p.lndet[w];
+      acc.x += lx;
+      acc.y += ly + 3.14159265358979323846 * nsw;
+      p.lndet[w] = acc;
+    }
+    if (badv > 0.0 && p.status) p.status[w] = 2;
+  }
+}
+
 // Combined operator of a 64-column Gauss-Jordan step from its two 32-column halves.  With the
 // first half's pivot block A11 (inverse T1), the second half's pivot rows A21 (original values
 // in the first half's columns) and the inverse T2 of the second half's block after the first
@@ -566,9 +760,25 @@ hipError_t launch_panel(int rows, int W, const PanelParams& p, hipStream_t s, K6
   return hipGetLastError();
 }
 
-hipError_t gj_panel(const PanelParams& p, int M, int W, hipStream_t s) {
-  return launch_panel(M - p.j0, W, p, s, panel_gj_kernel<64>, panel_gj_kernel<128>, panel_gj_kernel<256>,
-                      panel_gj_kernel<512>);
+// FTAFQMC_GJ_ROW_PANEL=1 in the environment selects the row-per-thread panel kernel (for
+// comparisons: the two give identical results; read at every solve).
+bool gj_row_panel() {
+  const char* env = std::getenv("FTAFQMC_GJ_ROW_PANEL");
+  return env && std::atoi(env) == 1;
+}
+
+hipError_t gj_panel(const PanelParams& p, int M, int W, bool row_panel, hipStream_t s) {
+  const int rows = M - p.j0;
+  if (row_panel)
+    return launch_panel(rows, W, p, s, panel_gj_kernel<64>, panel_gj_kernel<128>, panel_gj_kernel<256>,
+                        panel_gj_kernel<512>);
+  if (rows <= 64) panel_gj_split_kernel<1, 8><<<W, 256, 0, s>>>(p);
+  else if (rows <= 128) panel_gj_split_kernel<2, 8><<<W, 256, 0, s>>>(p);
+  else if (rows <= 192) panel_gj_split_kernel<3, 8><<<W, 256, 0, s>>>(p);
+  else if (rows <= 256) panel_gj_split_kernel<4, 8><<<W, 256, 0, s>>>(p);
+  else if (rows <= 384) panel_gj_split_kernel<6, 4><<<W, 512, 0, s>>>(p);
+  else panel_gj_split_kernel<8, 4><<<W, 512, 0, s>>>(p);
+  return hipGetLastError();
 }
 
 hipError_t swap_rows(const PanelParams& p, int W, int c0, int c1, hipStream_t s) {
@@ -584,12 +794,13 @@ hipError_t swap_rows(const PanelParams& p, int W, int c0, int c1, hipStream_t s)
 // they are bound by the FP64 matrix cores and 32-column steps are faster.
 hipError_t launch_gj(const ElimParams& e, PanelParams p, int cend, bool wide, hipStream_t s) {
   const int M = e.M;
+  const bool row_panel = gj_row_panel();
   hipError_t err;
   for (int j0 = 0; j0 < M;) {
     if (!wide || M - j0 <= NB) {
       const int jb = M - j0 < NB ? M - j0 : NB, c0 = j0 + jb, ncols = cend - c0;
       p.j0 = j0; p.jb = jb; p.tri = e.tri + TRI_T1;
-      if ((err = gj_panel(p, M, e.W, s)) != hipSuccess) return err;
+      if ((err = gj_panel(p, M, e.W, row_panel, s)) != hipSuccess) return err;
       if ((err = swap_rows(p, e.W, j0, cend, s)) != hipSuccess) return err;   // panel columns too
       if (ncols > 0) {
         if ((err = launch_zgemm(tri_params(e, e.tri + TRI_T1, NB, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess) return err;
@@ -605,7 +816,7 @@ hipError_t launch_gj(const ElimParams& e, PanelParams p, int cend, bool wide, hi
     const int c2 = j0 + NB;               // the second half's columns [c2, c2 + jb2)
     // first half: pivots, T1, its step on the second half's columns only
     p.j0 = j0; p.jb = NB; p.tri = e.tri + TRI_T1;
-    if ((err = gj_panel(p, M, e.W, s)) != hipSuccess) return err;
+    if ((err = gj_panel(p, M, e.W, row_panel, s)) != hipSuccess) return err;
     if ((err = swap_rows(p, e.W, j0, cend, s)) != hipSuccess) return err;
     if ((err = launch_zgemm(tri_params(e, e.tri + TRI_T1, NB, j0, NB, c2, jb2), GEMM_Z64, s)) != hipSuccess) return err;
     {
@@ -616,7 +827,7 @@ hipError_t launch_gj(const ElimParams& e, PanelParams p, int cend, bool wide, hi
     }
     // second half: pivots among rows [c2, M), T2; its exchanges cover the first half's columns
     p.j0 = c2; p.jb = jb2; p.tri = e.tri + TRI_T2;
-    if ((err = gj_panel(p, M, e.W, s)) != hipSuccess) return err;
+    if ((err = gj_panel(p, M, e.W, row_panel, s)) != hipSuccess) return err;
     if ((err = swap_rows(p, e.W, j0, cend, s)) != hipSuccess) return err;
     CombineParams cp;
     cp.aug = e.aug; cp.stride = e.stride; cp.lda = e.lda; cp.tri = e.tri; cp.tri_stride = TRI_ELEMS;
@@ -651,7 +862,7 @@ hipError_t launch_elim(const ElimParams& e, hipStream_t s) {
   p.piv = e.piv; p.ld = e.ld; p.lndet = e.lndet; p.status = e.status; p.gj = e.backsub != 0 ? 1 : 0;
   p.tri = e.tri;
   p.tri_stride = TRI_ELEMS;
-  if (e.backsub) return launch_gj(e, p, cend, M > GJ_WIDE_MIN_M, s);   // a solve: Gauss-Jordan
+  if (e.backsub) return launch_gj(e, p, cend, M > gj_wide_min_m(), s);   // a solve: Gauss-Jordan
   hipError_t err;
   for (int j0 = 0; j0 < M; j0 += NB) {
     const int jb = M - j0 < NB ? M - j0 : NB;

@@ -637,3 +637,54 @@ def test_rq_gather_kernel_matches_the_streamed_one(monkeypatch):
             check_walker(tb[:, w], lw[:, w], Gb[w], ref, label=("gather", w))
         a.close()
         b.close()
+
+
+def _panel_case_outputs(F, systems, fields, n_slices=None, backward=False):
+    ctx, fds = gpu_run(F, systems, fields, n_slices)
+    out = []
+    for i in range(len(systems)):
+        rec = ctx.records(i)
+        out += [rec["trace"].cpu().numpy(), rec["logw"].cpu().numpy(), ctx.greens(i).cpu().numpy()]
+    if backward:
+        ctx.energy(0)
+        for mode in (F.FROZEN_PATH, F.PATHWISE):
+            r = ctx.backward(0, mode=mode)
+            out += [r["walker"].cpu().numpy(), r["jac"].cpu().numpy()]
+    torch.cuda.synchronize()
+    ctx.close()
+    del fds
+    return out
+
+
+def test_column_split_panel_matches_row_panel(monkeypatch):
+    """The Gauss-Jordan panel has two kernels with the same arithmetic and the same pivot choice:
+    one row per thread (FTAFQMC_GJ_ROW_PANEL=1) and the default column-split layout.  Every panel
+    shape the solves use (1 to 8 row slots, 32-column and 64-column steps, the last narrow panel,
+    the doubled 2M system of both derivative modes) gives bit-identical records, weights, G and
+    derivatives with either kernel."""
+    F = _F()
+    cases = []
+    # M = 19, 123, 171 in one handle (1, 2 and 3 row slots and their shrinking panels)
+    sds = [dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5, walkers=5),
+           dict(n_elec=38, rs=2.0, theta=0.25, nmax2=9, dtau=0.05, stab_every=10, walkers=4),
+           dict(n_elec=66, rs=1.0, theta=0.125, nmax2=11, dtau=0.025, stab_every=10, walkers=3)]
+    cases.append((sds, None, False))
+    # M = 257 (6 slots, 64-column steps) and M = 485 (8 slots), the first slices
+    cases.append(([dict(n_elec=66, rs=1.0, theta=0.5, nmax2=16, dtau=0.1, stab_every=4, walkers=2, precision=1)], 12, False))
+    cases.append(([dict(n_elec=114, rs=0.5, theta=0.0625, nmax2=24, dtau=0.02, stab_every=8, walkers=2)], 6, False))
+    # M = 123 with both derivative modes (the doubled system has 246 rows: 4 slots)
+    cases.append(([dict(n_elec=38, rs=2.0, theta=0.25, nmax2=9, dtau=0.05, stab_every=10, walkers=3,
+                        flags=F.FTAFQMC_CHECKPOINT)], None, True))
+    for k, (systems, n_slices, bwd) in enumerate(cases):
+        fields = []
+        for j, sd in enumerate(systems):
+            s = oracle_system(sd)
+            fields.append(si.fields(700 + 10 * k + j, sd["walkers"], s.n_slices, s.NQ))
+        print("panel case", k, [oracle_system(sd).M for sd in systems], flush=True)
+        split = _panel_case_outputs(F, systems, fields, n_slices, bwd)
+        monkeypatch.setenv("FTAFQMC_GJ_ROW_PANEL", "1")
+        row = _panel_case_outputs(F, systems, fields, n_slices, bwd)
+        monkeypatch.delenv("FTAFQMC_GJ_ROW_PANEL")
+        assert len(split) == len(row)
+        for i, (a, b) in enumerate(zip(split, row)):
+            assert np.array_equal(a, b, equal_nan=True), (k, i, np.nanmax(np.abs(a - b)))
