@@ -1005,13 +1005,15 @@ int backward(ftafqmc_ctx* h, HostSys& s, const double* cot, double2* jac, double
     if (rc) return rc;
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_tan_prep(d, t, (const double2*)B, st); }));
     if ((rc = doubled_greens_form(h, s, k, 0, st))) return rc;
+    if (side) HIPCHK(hipEventRecord(h->bwd_ev[0], st));
+    // the latency-bound solve is queued before the re-factorisation's GEMMs, which would
+    // otherwise take every CU first
+    if ((rc = doubled_greens_solve(h, s, k, 0, st))) return rc;
     if (side) {
-      HIPCHK(hipEventRecord(h->bwd_ev[0], st));
       HIPCHK(hipStreamWaitEvent(side, h->bwd_ev[0], 0));
       if ((rc = doubled_push(h, s, side, false))) return rc;
       HIPCHK(hipEventRecord(h->bwd_ev[1], side));
     }
-    if ((rc = doubled_greens_solve(h, s, k, 0, st))) return rc;
     if ((rc = ratio_solve(h, s, st))) return rc;
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_tan_weight(d, t, k, st); }));
     if (side) HIPCHK(hipStreamWaitEvent(st, h->bwd_ev[1], 0));
