@@ -418,7 +418,8 @@ __global__ __launch_bounds__(NT) void panel_gj_kernel(PanelParams p) {
 
 // ---------------------------------------------------------------------------------------
 // Gauss-Jordan panel, column-split layout.  The same elimination as panel_gj_kernel with the
-// work laid out the other way: NW = NB / CPW waves, wave w holding panel columns
+// work laid out the other way: a panel of PW = 32 or 64 columns, NW = PW / CPW waves, wave w
+// holding panel columns
 // [w CPW, (w+1) CPW) of every row (lane l, slot s: row j0 + l + 64 s).  Column C belongs to
 // one wave, which searches the pivot alone (no cross-wave reduction) and computes the
 // multiplier of every row; the multipliers reach the other waves through LDS, one entry per
@@ -427,13 +428,13 @@ __global__ __launch_bounds__(NT) void panel_gj_kernel(PanelParams p) {
 // row to every thread.  The pivot choice (per group of 64 rows the lowest row among the
 // largest keys, then the lowest label among the groups), the multipliers and every update are
 // those of panel_gj_kernel, operation for operation, so the two give identical results.
-template <int SL>
+template <int SL, int PW>
 struct GjSplitShared {
   double2 g[2][SL][64];             // multipliers of column C, by column parity
   double2 pv[2];
   int info[2][4];                   // pivot label, its lane and slot, found
-  double2 pivv[NB];
-  int swapped[NB];
+  double2 pivv[PW];
+  int swapped[PW];
 };
 
 FT_DEV double readlane_d(double v, int l) {
@@ -443,10 +444,10 @@ FT_DEV double readlane_d(double v, int l) {
 }
 FT_DEV int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-template <int SL, int CPW>
-__global__ __launch_bounds__(64 * (NB / CPW)) void panel_gj_split_kernel(PanelParams p) {
-  constexpr int NW = NB / CPW;
-  __shared__ GjSplitShared<SL> sh;
+template <int SL, int CPW, int PW>
+__global__ __launch_bounds__(64 * (PW / CPW)) void panel_gj_split_kernel(PanelParams p) {
+  constexpr int NW = PW / CPW;
+  __shared__ GjSplitShared<SL, PW> sh;
   const int w = blockIdx.x;
   if (w >= p.W) return;
   double2* aug = p.aug + (long long)w * p.stride;
@@ -575,7 +576,7 @@ __global__ __launch_bounds__(64 * (NB / CPW)) void panel_gj_split_kernel(PanelPa
       const int c = label[s] - j0;
       const double2 sc = crecip(mypv[s]);
 #pragma unroll
-      for (int i = 0; i < CPW; ++i) tri[c * NB + cw + i] = cw + i < jb ? cmul(a[s][i], sc) : make_double2(0.0, 0.0);
+      for (int i = 0; i < CPW; ++i) tri[c * PW + cw + i] = cw + i < jb ? cmul(a[s][i], sc) : make_double2(0.0, 0.0);
     }
   }
   __syncthreads();                         // pivv / swapped of the last column
@@ -660,15 +661,18 @@ __global__ __launch_bounds__(256) void gj_combine_kernel(CombineParams c) {
 // row whose contents it receives (tracing the exchanges backwards), then each thread reads its
 // column of all moved rows into registers (every load in flight at once), and after a barrier
 // writes them to their new places.  64 columns per workgroup, one per lane, four row groups.
-constexpr int SWAP_COLS = 64, SWAP_GROUPS = 4, SWAP_PER = 2 * NB / SWAP_GROUPS;
+// PW is the panel width (32, or 64 for the 64-column Gauss-Jordan panel).
+constexpr int SWAP_COLS = 64, SWAP_GROUPS = 4;
+template <int PW>
 __global__ __launch_bounds__(256) void swap_kernel(PanelParams p, int c0, int c1, int chunks) {
-  __shared__ int pv[NB];
-  __shared__ int src[2 * NB], dst[2 * NB];
+  constexpr int SWAP_PER = 2 * PW / SWAP_GROUPS;
+  __shared__ int pv[PW];
+  __shared__ int src[2 * PW], dst[2 * PW];
   __shared__ int nmov;
   const int w = blockIdx.x / chunks, ch = blockIdx.x - w * chunks;
   if (w >= p.W) return;
   const int t = threadIdx.x, j0 = p.j0, jb = p.jb, lda = p.lda;
-  if (t < NB) pv[t] = t < jb ? p.piv[(long long)w * p.ld + j0 + t] : j0 + t;
+  if (t < PW) pv[t] = t < jb ? p.piv[(long long)w * p.ld + j0 + t] : j0 + t;
   if (t == 0) nmov = 0;
   __syncthreads();
   if (t < 2 * jb) {
@@ -772,18 +776,38 @@ hipError_t gj_panel(const PanelParams& p, int M, int W, bool row_panel, hipStrea
   if (row_panel)
     return launch_panel(rows, W, p, s, panel_gj_kernel<64>, panel_gj_kernel<128>, panel_gj_kernel<256>,
                         panel_gj_kernel<512>);
-  if (rows <= 64) panel_gj_split_kernel<1, 8><<<W, 256, 0, s>>>(p);
-  else if (rows <= 128) panel_gj_split_kernel<2, 8><<<W, 256, 0, s>>>(p);
-  else if (rows <= 192) panel_gj_split_kernel<3, 8><<<W, 256, 0, s>>>(p);
-  else if (rows <= 256) panel_gj_split_kernel<4, 8><<<W, 256, 0, s>>>(p);
-  else if (rows <= 384) panel_gj_split_kernel<6, 4><<<W, 512, 0, s>>>(p);
-  else panel_gj_split_kernel<8, 4><<<W, 512, 0, s>>>(p);
+  if (rows <= 64) panel_gj_split_kernel<1, 8, NB><<<W, 256, 0, s>>>(p);
+  else if (rows <= 128) panel_gj_split_kernel<2, 8, NB><<<W, 256, 0, s>>>(p);
+  else if (rows <= 192) panel_gj_split_kernel<3, 8, NB><<<W, 256, 0, s>>>(p);
+  else if (rows <= 256) panel_gj_split_kernel<4, 8, NB><<<W, 256, 0, s>>>(p);
+  else if (rows <= 384) panel_gj_split_kernel<6, 4, NB><<<W, 512, 0, s>>>(p);
+  else panel_gj_split_kernel<8, 4, NB><<<W, 512, 0, s>>>(p);
   return hipGetLastError();
+}
+
+// A 64-column panel (at most 256 rows): 8 waves of 8 columns, pivot block inverse at TRI_TL
+// (row stride 64).
+hipError_t gj_panel64(const PanelParams& p, int M, int W, hipStream_t s) {
+  const int rows = M - p.j0;
+  if (rows <= 64) panel_gj_split_kernel<1, 8, 2 * NB><<<W, 512, 0, s>>>(p);
+  else if (rows <= 128) panel_gj_split_kernel<2, 8, 2 * NB><<<W, 512, 0, s>>>(p);
+  else if (rows <= 192) panel_gj_split_kernel<3, 8, 2 * NB><<<W, 512, 0, s>>>(p);
+  else if (rows <= 256) panel_gj_split_kernel<4, 8, 2 * NB><<<W, 512, 0, s>>>(p);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// FTAFQMC_GJ_PANEL64=0 in the environment keeps the solve on 32-column panels (read at every
+// solve).
+bool gj_panel64_on() {
+  const char* env = std::getenv("FTAFQMC_GJ_PANEL64");
+  return !env || std::atoi(env) != 0;
 }
 
 hipError_t swap_rows(const PanelParams& p, int W, int c0, int c1, hipStream_t s) {
   const int chunks = (c1 - c0 + SWAP_COLS - 1) / SWAP_COLS;
-  swap_kernel<<<W * chunks, SWAP_COLS * SWAP_GROUPS, 0, s>>>(p, c0, c1, chunks);
+  if (p.jb > NB) swap_kernel<2 * NB><<<W * chunks, SWAP_COLS * SWAP_GROUPS, 0, s>>>(p, c0, c1, chunks);
+  else swap_kernel<NB><<<W * chunks, SWAP_COLS * SWAP_GROUPS, 0, s>>>(p, c0, c1, chunks);
   return hipGetLastError();
 }
 
@@ -795,8 +819,25 @@ hipError_t swap_rows(const PanelParams& p, int W, int c0, int c1, hipStream_t s)
 hipError_t launch_gj(const ElimParams& e, PanelParams p, int cend, bool wide, hipStream_t s) {
   const int M = e.M;
   const bool row_panel = gj_row_panel();
+  const bool p64 = !row_panel && gj_panel64_on();
   hipError_t err;
   for (int j0 = 0; j0 < M;) {
+    if (p64 && M - j0 > NB && M - j0 <= 256) {
+      // one 64-column panel, its row exchanges, the pivot rows' product and one K = 64 update
+      const int jb = M - j0 < 2 * NB ? M - j0 : 2 * NB, c0 = j0 + jb, ncols = cend - c0;
+      p.j0 = j0; p.jb = jb; p.tri = e.tri + TRI_TL;
+      if ((err = gj_panel64(p, M, e.W, s)) != hipSuccess) return err;
+      if ((err = swap_rows(p, e.W, j0, cend, s)) != hipSuccess) return err;
+      if (ncols > 0) {
+        if ((err = launch_zgemm(tri_params(e, e.tri + TRI_TL, 2 * NB, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess) return err;
+        GemmParams g = update_params(e, 0, M, j0, jb, c0, ncols);
+        g.skip0 = j0;
+        g.skip1 = j0 + jb;
+        if ((err = launch_zgemm(g, GEMM_Z64, s)) != hipSuccess) return err;
+      }
+      j0 += jb;
+      continue;
+    }
     if (!wide || M - j0 <= NB) {
       const int jb = M - j0 < NB ? M - j0 : NB, c0 = j0 + jb, ncols = cend - c0;
       p.j0 = j0; p.jb = jb; p.tri = e.tri + TRI_T1;

@@ -663,6 +663,29 @@ def test_column_split_panel_matches_row_panel(monkeypatch):
     the doubled 2M system of both derivative modes) gives bit-identical records, weights, G and
     derivatives with either kernel."""
     F = _F()
+    monkeypatch.setenv("FTAFQMC_GJ_PANEL64", "0")      # both on 32-column panels
+    cases = _panel_cases(F)
+    for k, (systems, n_slices, bwd) in enumerate(cases):
+        fields = _panel_case_fields(k, systems)
+        print("panel case", k, [oracle_system(sd).M for sd in systems], flush=True)
+        split = _panel_case_outputs(F, systems, fields, n_slices, bwd)
+        monkeypatch.setenv("FTAFQMC_GJ_ROW_PANEL", "1")
+        row = _panel_case_outputs(F, systems, fields, n_slices, bwd)
+        monkeypatch.delenv("FTAFQMC_GJ_ROW_PANEL")
+        assert len(split) == len(row)
+        for i, (a, b) in enumerate(zip(split, row)):
+            assert np.array_equal(a, b, equal_nan=True), (k, i, np.nanmax(np.abs(a - b)))
+
+
+def _panel_case_fields(k, systems):
+    fields = []
+    for j, sd in enumerate(systems):
+        s = oracle_system(sd)
+        fields.append(si.fields(700 + 10 * k + j, sd["walkers"], s.n_slices, s.NQ))
+    return fields
+
+
+def _panel_cases(F):
     cases = []
     # M = 19, 123, 171 in one handle (1, 2 and 3 row slots and their shrinking panels)
     sds = [dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5, walkers=5),
@@ -675,16 +698,31 @@ def test_column_split_panel_matches_row_panel(monkeypatch):
     # M = 123 with both derivative modes (the doubled system has 246 rows: 4 slots)
     cases.append(([dict(n_elec=38, rs=2.0, theta=0.25, nmax2=9, dtau=0.05, stab_every=10, walkers=3,
                         flags=F.FTAFQMC_CHECKPOINT)], None, True))
-    for k, (systems, n_slices, bwd) in enumerate(cases):
-        fields = []
-        for j, sd in enumerate(systems):
-            s = oracle_system(sd)
-            fields.append(si.fields(700 + 10 * k + j, sd["walkers"], s.n_slices, s.NQ))
-        print("panel case", k, [oracle_system(sd).M for sd in systems], flush=True)
-        split = _panel_case_outputs(F, systems, fields, n_slices, bwd)
-        monkeypatch.setenv("FTAFQMC_GJ_ROW_PANEL", "1")
-        row = _panel_case_outputs(F, systems, fields, n_slices, bwd)
-        monkeypatch.delenv("FTAFQMC_GJ_ROW_PANEL")
-        assert len(split) == len(row)
-        for i, (a, b) in enumerate(zip(split, row)):
-            assert np.array_equal(a, b, equal_nan=True), (k, i, np.nanmax(np.abs(a - b)))
+    # M = 57: one 64-column step narrower than the panel (57 columns)
+    cases.append(([dict(n_elec=38, rs=1.0, theta=0.25, nmax2=5, dtau=0.05, stab_every=4, walkers=4)], None, False))
+    return cases
+
+
+def test_64_column_steps_match_32_column_steps(monkeypatch):
+    """The solve takes 64-column Gauss-Jordan steps (one 64-column panel, one K = 64 update) where
+    at most 256 rows are left, 32-column steps elsewhere (FTAFQMC_GJ_PANEL64=0: everywhere).  The
+    two orders of the same elimination agree to rounding on every shape: M = 19/123/171 in one
+    handle, M = 257 and 485 (64-column steps after two-half steps), the doubled 2M = 246 system
+    of both derivative modes, and M = 57 (a single step narrower than the panel)."""
+    F = _F()
+    for k, (systems, n_slices, bwd) in enumerate(_panel_cases(F)):
+        fields = _panel_case_fields(k, systems)
+        print("64-column case", k, [oracle_system(sd).M for sd in systems], flush=True)
+        wide = _panel_case_outputs(F, systems, fields, n_slices, bwd)
+        monkeypatch.setenv("FTAFQMC_GJ_PANEL64", "0")
+        narrow = _panel_case_outputs(F, systems, fields, n_slices, bwd)
+        monkeypatch.delenv("FTAFQMC_GJ_PANEL64")
+        assert len(wide) == len(narrow)
+        # FP64 paths to rounding; a mixed path carries the FP64 rounding into its FP32 chain
+        tol = 1e-5 if any(sd.get("precision", 0) == 1 for sd in systems) else 1e-10
+        for i, (a, b) in enumerate(zip(wide, narrow)):
+            fin = np.isfinite(b)
+            assert np.array_equal(np.isfinite(a), fin), (k, i)
+            scale = max(np.abs(b[fin]).max(), 1.0) if fin.any() else 1.0
+            err = np.abs(a[fin] - b[fin]).max() / scale if fin.any() else 0.0
+            assert err < tol, (k, i, err)
