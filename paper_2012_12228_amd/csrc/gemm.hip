@@ -74,7 +74,8 @@ __global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 1
   if (!xcd_walker_tile(blockIdx.x, p.W, p.tiles_m * p.tiles_n, &w, &tile)) return;
   const int tm = tile / p.tiles_n, tn = tile - tm * p.tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
-  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  // the wave index is scalar, so that the per-block tests below are scalar branches
+  const int t = threadIdx.x, lane = t & 63, wid = __builtin_amdgcn_readfirstlane(t >> 6);
   const int wr = wid / TL::WGN, wc = wid % TL::WGN;
   const int Mr = p.m, Nc = p.n, Kd = p.k;
 
