@@ -74,6 +74,10 @@ __global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 1
   if (!xcd_walker_tile(blockIdx.x, p.W, p.tiles_m * p.tiles_n, &w, &tile)) return;
   const int tm = tile / p.tiles_n, tn = tile - tm * p.tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
+  // Hermitian result: the tiles above the diagonal are written by their mirror images
+  constexpr bool SQUARE = BM == BN;
+  const bool herm = ROLE == 1 && SQUARE && p.herm;
+  if (herm && tn > tm) return;   // uniform over the workgroup, before any barrier
   // the wave index is scalar, so that the per-block tests below are scalar branches
   const int t = threadIdx.x, lane = t & 63, wid = __builtin_amdgcn_readfirstlane(t >> 6);
   const int wr = wid / TL::WGN, wc = wid % TL::WGN;
@@ -217,10 +221,14 @@ __global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 1
     if constexpr (UNCOND) load_tile(kt);
     else load_tile_la(kt);
   };
-  load(0);
-  store_tile(0);
+  // upper-triangular A: the k-tiles left of this row tile hold only zeros of A
+  const int kt0 = (ROLE == 1 && p.tri_a) ? (m0 / BK < nk ? m0 / BK : nk) : 0;
+  if (kt0 < nk) {
+    load(kt0);
+    store_tile(kt0 & 1);
+  }
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
+  for (int kt = kt0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) load(kt + 1);
     if (kt + 1 == nk && PRE) {
@@ -365,6 +373,7 @@ __global__ __launch_bounds__(TL::NT, (ROLE == 0 && TL::NT >= 1024 && TL::WM == 1
             if (p.cs) out = cscale(out, p.cs[gj]);
           }
           store_c(C + off, out);
+          if (herm && tn < tm && gj < p.mpad && gi < p.npad) store_c(C + (long long)gj * p.ldc + gi, cconj(out));
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             if (e >= p.nextra) break;

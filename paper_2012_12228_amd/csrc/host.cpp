@@ -677,7 +677,7 @@ int stabilise(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st) {
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_perm(d, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_gather(d, st); }));
   GemmParams g = gp_base(s, d);
-  g.A = d.E0; g.B = d.E0; g.C = d.aug; g.opA = 1; g.role = 1;
+  g.A = d.E0; g.B = d.E0; g.C = d.aug; g.opA = 1; g.role = 1; g.herm = 1;
   g.sC = d.aug_stride; g.ldc = 2 * s.ld;
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_zgemm(g, GEMM_Z64, st); }));  // S = E0^H E0 into the left block
   ElimParams e;
@@ -943,7 +943,7 @@ int doubled_push(ftafqmc_ctx* h, HostSys& s, hipStream_t st, bool with_inverse) 
   HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_stab_perm(dd, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_stab_gather(dd, st); }));
   GemmParams gs = gp_dd(s);
-  gs.A = dd.E0; gs.B = dd.E0; gs.C = dd.aug; gs.opA = 1;
+  gs.A = dd.E0; gs.B = dd.E0; gs.C = dd.aug; gs.opA = 1; gs.herm = 1;
   gs.sC = dd.aug_stride; gs.ldc = 2 * s.ld2;
   HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(gs, GEMM_Z64, st); }));
   const ElimParams e = ep_dd(s, 0, 0);
@@ -958,7 +958,7 @@ int doubled_push(ftafqmc_ctx* h, HostSys& s, hipStream_t st, bool with_inverse) 
   }
   HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_permute_rows(t, st); }));
   GemmParams gt = gp_dd(s);
-  gt.A = dd.E1; gt.B = dd.E0; gt.C = t.Td;
+  gt.A = dd.E1; gt.B = dd.E0; gt.C = t.Td; gt.tri_a = 1;   // Ru is upper triangular
   HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_zgemm(gt, GEMM_Z64, st); }));
   return FTAFQMC_OK;
 }

@@ -23,6 +23,9 @@ struct GemmParams {
   int tile;                  // tile shape index (0 .. gemm_tile_count()-1) for role 0
   int tiles_m, tiles_n;      // set by the launcher
   int skip0, skip1;          // role 1: rows [skip0, skip1) of C are not written
+  int tri_a;                 // role 1: A is upper triangular (zero below the diagonal): k starts at the row tile
+  int herm;                  // role 1: C is Hermitian (A^H A): only the tiles on and below the diagonal are
+                             // computed, each one below also stored conjugate-transposed above
 };
 hipError_t launch_zgemm(const GemmParams& p, int prec, hipStream_t s);
 // The mixed propagator's products on the BF16 matrix cores with three-way split operands
