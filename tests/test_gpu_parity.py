@@ -370,9 +370,13 @@ def test_greens_complex64_copy_and_dtype_checks():
             F.ftafqmc_greens(ctx.handle, 0, bad, ctx.device)
 
 
-def test_nan_fields_flag_only_that_walker():
+@pytest.mark.parametrize("nmax2,n_elec", [(2, 14), (5, 38), (9, 38)], ids=["m19", "m57", "m123"])
+def test_nan_fields_flag_only_that_walker(nmax2, n_elec):
+    """A NaN field marks its walker failed (status 2) and leaves the others bit-identical: with
+    32-column steps (M=19) and with 64-column steps (M=57: one step narrower than the panel;
+    M=123: two row slots), where the failed walker's pivot searches find no usable pivot."""
     F = _F()
-    sd = dict(n_elec=14, rs=1.0, theta=0.5, nmax2=2, dtau=0.05, stab_every=5, walkers=4)
+    sd = dict(n_elec=n_elec, rs=1.0, theta=0.5, nmax2=nmax2, dtau=0.05, stab_every=5, walkers=4)
     s = oracle_system(sd)
     flds = si.fields(21, 4, s.n_slices, s.NQ)
     bad = flds.copy()
