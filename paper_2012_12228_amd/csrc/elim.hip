@@ -6,14 +6,17 @@
 //   * the Cholesky factor of S = Y^H Y in the QR stabilisation: no pivoting, forward
 //     only; the left block becomes U = D L^H (S = L D L^H) and R becomes L^{-1} R;
 //   * the update of T^{-1} by a unit triangular factor (again forward only).
-// NB = 32 columns per panel, one kernel sequence for all walkers:
-//   panel   one workgroup per walker, one row per thread (pivot search = workgroup reduction,
-//           row exchange = relabelling, updates = register operations with LDS broadcasts of
-//           the pivot row).  Forward elimination: LU of the panel, then L11^{-1}.  Gauss-Jordan:
-//           in-place Gauss-Jordan inversion of the pivot block inside the column loop (a
-//           runtime loop over columns with the row rotated in registers, so the loop body is
-//           small and stays in the instruction cache);
-//   swap    the panel's row exchanges composed into one permutation of at most 2 NB rows;
+// NB = 32 columns per panel (64 for the Gauss-Jordan steps where at most 256 rows are left),
+// one kernel sequence for all walkers:
+//   panel   one workgroup per walker.  Forward elimination: one row per thread, LU of the panel
+//           with LDS broadcasts of the pivot row, then L11^{-1}.  Gauss-Jordan: in-place
+//           Gauss-Jordan inversion of the pivot block inside the column loop, either with one
+//           row per thread (the row rotated in registers so the runtime column loop stays
+//           small) or, by default, column-split: each wave owns 8 columns of every row, the
+//           owning wave searches a column's pivot alone and passes the multipliers through
+//           LDS (row exchange = relabelling in both);
+//   swap    the panel's row exchanges composed into one permutation of at most 2 x the panel
+//           width rows;
 // Forward elimination (LU, right-looking):
 //   trsm    U12 = L11^{-1} A12 as a small in-place MFMA GEMM (each workgroup owns whole
 //           columns and reads them completely before it writes);
