@@ -741,6 +741,29 @@ GemmParams update_params(const ElimParams& e, int row0, int nrows, int k0, int k
   return g;
 }
 
+// Rows the FP64 update GEMM computes for `rows` rows of C: a 32-row tile up to 32 rows, 64-row
+// tiles above.
+int update_row_work(int rows) { return rows <= 0 ? 0 : rows <= 32 ? 32 : 64 * ((rows + 63) / 64); }
+
+// aug[r, c0..c0+ncols) -= aug[r, j0..j0+kb) aug[j0..j0+kb, c0..c0+ncols) for every row r but
+// the pivot rows [j0, j0 + kb): two GEMMs over the rows above and below the pivot rows where
+// they cover fewer tile rows than one GEMM over all M rows whose epilogue skips the pivot rows
+// (a 64-column step at j0 = 64 c computes two tile rows of three at M = 171).  Every entry takes
+// the same k-ordered sum either way.
+hipError_t update_except(const ElimParams& e, int j0, int kb, int c0, int ncols, hipStream_t s) {
+  const int M = e.M, below = M - j0 - kb;
+  hipError_t err;
+  if (update_row_work(j0) + update_row_work(below) < update_row_work(M)) {
+    if (j0 > 0 && (err = launch_zgemm(update_params(e, 0, j0, j0, kb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
+      return err;
+    return below > 0 ? launch_zgemm(update_params(e, j0 + kb, below, j0, kb, c0, ncols), GEMM_Z64, s) : hipSuccess;
+  }
+  GemmParams g = update_params(e, 0, M, j0, kb, c0, ncols);
+  g.skip0 = j0;
+  g.skip1 = j0 + kb;
+  return launch_zgemm(g, GEMM_Z64, s);
+}
+
 // aug[row0..row0+kb, col0..] <- T aug[row0..row0+kb, col0..] with a per-walker kb x kb T (in place)
 GemmParams tri_params(const ElimParams& e, const double2* T, int ldT, int row0, int kb, int col0, int ncols) {
   GemmParams g = aug_params(e);
@@ -833,10 +856,7 @@ hipError_t launch_gj(const ElimParams& e, PanelParams p, int cend, bool wide, hi
       if ((err = swap_rows(p, e.W, j0, cend, s)) != hipSuccess) return err;
       if (ncols > 0) {
         if ((err = launch_zgemm(tri_params(e, e.tri + TRI_TL, 2 * NB, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess) return err;
-        GemmParams g = update_params(e, 0, M, j0, jb, c0, ncols);
-        g.skip0 = j0;
-        g.skip1 = j0 + jb;
-        if ((err = launch_zgemm(g, GEMM_Z64, s)) != hipSuccess) return err;
+        if ((err = update_except(e, j0, jb, c0, ncols, s)) != hipSuccess) return err;
       }
       j0 += jb;
       continue;
@@ -848,10 +868,7 @@ hipError_t launch_gj(const ElimParams& e, PanelParams p, int cend, bool wide, hi
       if ((err = swap_rows(p, e.W, j0, cend, s)) != hipSuccess) return err;   // panel columns too
       if (ncols > 0) {
         if ((err = launch_zgemm(tri_params(e, e.tri + TRI_T1, NB, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess) return err;
-        GemmParams g = update_params(e, 0, M, j0, jb, c0, ncols);   // every row but the pivot rows
-        g.skip0 = j0;
-        g.skip1 = j0 + jb;
-        if ((err = launch_zgemm(g, GEMM_Z64, s)) != hipSuccess) return err;
+        if ((err = update_except(e, j0, jb, c0, ncols, s)) != hipSuccess) return err;
       }
       j0 += jb;
       continue;
@@ -863,12 +880,7 @@ hipError_t launch_gj(const ElimParams& e, PanelParams p, int cend, bool wide, hi
     if ((err = gj_panel(p, M, e.W, row_panel, s)) != hipSuccess) return err;
     if ((err = swap_rows(p, e.W, j0, cend, s)) != hipSuccess) return err;
     if ((err = launch_zgemm(tri_params(e, e.tri + TRI_T1, NB, j0, NB, c2, jb2), GEMM_Z64, s)) != hipSuccess) return err;
-    {
-      GemmParams g = update_params(e, 0, M, j0, NB, c2, jb2);
-      g.skip0 = j0;
-      g.skip1 = j0 + NB;
-      if ((err = launch_zgemm(g, GEMM_Z64, s)) != hipSuccess) return err;
-    }
+    if ((err = update_except(e, j0, NB, c2, jb2, s)) != hipSuccess) return err;
     // second half: pivots among rows [c2, M), T2; its exchanges cover the first half's columns
     p.j0 = c2; p.jb = jb2; p.tri = e.tri + TRI_T2;
     if ((err = gj_panel(p, M, e.W, row_panel, s)) != hipSuccess) return err;
@@ -881,10 +893,7 @@ hipError_t launch_gj(const ElimParams& e, PanelParams p, int cend, bool wide, hi
     const int c0 = j0 + kb, ncols = cend - c0;
     if (ncols > 0) {
       if ((err = launch_zgemm(tri_params(e, e.tri + TRI_TL, 2 * NB, j0, kb, c0, ncols), GEMM_Z64, s)) != hipSuccess) return err;
-      GemmParams g = update_params(e, 0, M, j0, kb, c0, ncols);
-      g.skip0 = j0;
-      g.skip1 = j0 + kb;
-      if ((err = launch_zgemm(g, GEMM_Z64, s)) != hipSuccess) return err;
+      if ((err = update_except(e, j0, kb, c0, ncols, s)) != hipSuccess) return err;
       // first half's rows: X1 - P1 X2 (P1 in their second-half columns, X2 in the second half's rows)
       if ((err = launch_zgemm(update_params(e, j0, NB, c2, jb2, c0, ncols), GEMM_Z64, s)) != hipSuccess) return err;
     }
