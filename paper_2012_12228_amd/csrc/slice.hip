@@ -647,14 +647,18 @@ __global__ __launch_bounds__(NT) void stab_finish_b_kernel(SysDev s) {
 // Exchange: sum_Q v_Q Lambda_Q = sum_{a != d} v(K_a - K_d) sum_b P_ab P_cd with
 // K_c = K_b - (K_a - K_d), P = I - G^T.  One workgroup per (walker, a), the d shared over the
 // waves, b over the lanes; the lookup tables sit in LDS and each lane's (at most 8) gathers
-// of row d are issued together.
+// of row d are issued together.  P_cd = delta_cd - G_dc, and c = d only for b = a, so the sum
+// over b is P_aa - sum_b P_ab G_dc: the delta term leaves the loop as P_aa sum_{d != a} v(K_a - K_d).
+// The wave index is scalar, so row d's address is scalar and each gather is one offset; the row
+// v(K_a - K_d) over d sits in LDS with the tables.
 // With X: the sum over b for every pair (a, d) also goes to X[w][a][d] (for <rho(Q) rho(-Q)>).
 template <int EX_B, bool WITHX>                     // b per lane: M <= 64 EX_B
 __global__ __launch_bounds__(NT) void exchange_kernel(SysDev s, double2* X) {
   extern __shared__ char dyn[];
   const int M = s.M, ld = s.ld;
   double2* pcol = (double2*)dyn;                    // [M]: P_ab = delta_ab - G_ba
-  int* flat = (int*)(pcol + M);                     // [M]
+  double* vrow = (double*)(pcol + M);               // [M]: v(K_a - K_d), 0 at d = a
+  int* flat = (int*)(vrow + M);                     // [M]
   short* grid = (short*)(flat + M);                 // [grid_dim^3]
   __shared__ double red[8];
   int w, a;
@@ -667,9 +671,10 @@ __global__ __launch_bounds__(NT) void exchange_kernel(SysDev s, double2* X) {
     if (b == a) v.x += 1.0;
     pcol[b] = v;
     flat[b] = s.flat[b];
+    vrow[b] = b == a ? 0.0 : s.vq[s.idx[a * M + b]];
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // this lane's b and their grid offsets do not depend on d
   int fb[EX_B];
   double2 pb[EX_B];
@@ -679,10 +684,12 @@ __global__ __launch_bounds__(NT) void exchange_kernel(SysDev s, double2* X) {
     fb[k] = b < M ? flat[b] - flat[a] + s.grid_c0 : -1;
     pb[k] = b < M ? pcol[b] : zero2();
   }
+  const double2 paa = pcol[a];
   double2 acc = zero2();
+  double vsum = 0.0;                                // sum of v(K_a - K_d) over this wave's d
   for (int d = wid; d < M; d += NT / 64) {
     if (d == a) continue;
-    const double v = s.vq[s.idx[a * M + d]];
+    const double v = vrow[d];
     const double2* Gd = G + (long long)d * ld;
     const int fd = flat[d];
     int c[EX_B];
@@ -691,23 +698,25 @@ __global__ __launch_bounds__(NT) void exchange_kernel(SysDev s, double2* X) {
     for (int k = 0; k < EX_B; ++k) c[k] = fb[k] >= 0 ? grid[fb[k] + fd] : -1;   // K_b - K_a + K_d
 #pragma unroll
     for (int k = 0; k < EX_B; ++k) g[k] = c[k] >= 0 ? Gd[c[k]] : zero2();
-    double2 part = zero2();
+    double2 part = zero2();                         // sum_b P_ab G_dc
 #pragma unroll
     for (int k = 0; k < EX_B; ++k) {
-      if (c[k] >= 0) {
-        double2 pcd = cscale(g[k], -1.0);           // P_cd = delta_cd - G_dc
-        if (c[k] == d) pcd.x += 1.0;
-        const double2 pr = cmul(pb[k], pcd);
-        part.x += pr.x;
-        part.y += pr.y;
-      }
+      part.x = fma(pb[k].x, g[k].x, part.x);
+      part.x = fma(-pb[k].y, g[k].y, part.x);
+      part.y = fma(pb[k].x, g[k].y, part.y);
+      part.y = fma(pb[k].y, g[k].x, part.y);
     }
-    acc.x += v * part.x;
-    acc.y += v * part.y;
+    acc.x -= v * part.x;
+    acc.y -= v * part.y;
+    vsum += v;
     if constexpr (WITHX) {
       const double px = wave_sum(part.x), py = wave_sum(part.y);
-      if (lane == 0) X[(long long)w * s.mat_stride + (long long)a * ld + d] = make_double2(px, py);
+      if (lane == 0) X[(long long)w * s.mat_stride + (long long)a * ld + d] = make_double2(paa.x - px, paa.y - py);
     }
+  }
+  if (lane == 0) {                                  // the delta term
+    acc.x += paa.x * vsum;
+    acc.y += paa.y * vsum;
   }
   acc = block_csum_256(acc, red);
   if (threadIdx.x == 0) s.exch[(long long)w * ld + a] = acc;
@@ -936,7 +945,7 @@ hipError_t launch_stab_finish_b(const SysDev& s, hipStream_t st) {
   return hipGetLastError();
 }
 template <bool WITHX> hipError_t launch_exchange(const SysDev& s, double2* X, hipStream_t st) {
-  const size_t shm = (size_t)s.M * (sizeof(double2) + sizeof(int)) +
+  const size_t shm = (size_t)s.M * (sizeof(double2) + sizeof(double) + sizeof(int)) +
                      (size_t)s.grid_dim * s.grid_dim * s.grid_dim * sizeof(short) + 16;
   if (s.M <= 64 * 2) exchange_kernel<2, WITHX><<<tiles_blocks(s, s.M), NT, shm, st>>>(s, X);
   else if (s.M <= 64 * 4) exchange_kernel<4, WITHX><<<tiles_blocks(s, s.M), NT, shm, st>>>(s, X);
