@@ -3,7 +3,8 @@
 Calls only oracle/ and the seeded input generator.  For each workload and each
 sampled walker it runs the FP64 oracle over the whole path and keeps, at every
 energy record (each stabilisation boundary and the last slice): E_1, E_2, E, N,
-ln w and the status; plus the final Green's function's diagonal and first rows.
+ln w and the status; plus the final Green's function's diagonal, first rows and 256 entries at
+seeded positions (for element-by-element checks).
 For the derivative workload it also keeps each sampled walker's frozen-path
 derivatives (d ln w, dE, dN in mu and in lambda) from oracle.tangent, and (mode pathwise)
 their pathwise derivatives with the raw fields held fixed.  Mode lowrank keeps the same
@@ -28,12 +29,19 @@ from oracle import ueg, path, energy, tangent, lowrank  # noqa: E402
 import synthinputs as si  # noqa: E402
 
 SAMPLES = {
-    "ueg_n66_m171": {0: [0, 255]},
-    "ueg_n38_m123": {0: [0, 127]},
+    "ueg_n66_m171": {0: [0, 85, 170, 255]},
+    "ueg_n38_m123": {0: [0, 42, 85, 127]},
     "ueg_uneven4": {0: [0, 170], 1: [0, 170], 2: [0, 84], 3: [0, 84]},
-    "ueg_n114_m485": {0: [0, 511]},
+    "ueg_n114_m485": {0: [0, 170, 341, 511]},
 }
 G_ROWS = 8
+G_SAMPLES = 256
+
+
+def g_sample_positions(M, sidx, w):
+    """Seeded entry positions (i, j) of a walker's final G, the same for the oracle and the tests."""
+    rng = np.random.default_rng(1000003 * (sidx + 1) + w)
+    return rng.integers(0, M, G_SAMPLES), rng.integers(0, M, G_SAMPLES)
 LOWRANK_SAMPLES = {"ueg_n114_m485": {0: [0, 511]}}
 TANGENT_SAMPLES = {"ueg_n38_m123": [0, 63, 127]}
 
@@ -53,6 +61,9 @@ def one(args):
             out = path.run_walker(s, z, energy_fn=energy.local_energy)
     recs = out["records"]
     extra = dict(ranks=out["ranks"]) if low_rank else {}
+    gi, gj = g_sample_positions(s.M, sidx, w)
+    if not low_rank:
+        extra.update(G_samp_i=gi, G_samp_j=gj, G_samp=out["G"][gi, gj].copy())
     return dict(**extra,
         system=sidx, walker=w,
         slices=np.array([r["slice"] for r in recs]),
