@@ -904,18 +904,12 @@ hipError_t launch_gj(const ElimParams& e, PanelParams p, int cend, bool wide, hi
 
 }  // namespace
 
-hipError_t launch_elim(const ElimParams& e, hipStream_t s) {
-  if (e.W <= 0 || e.M <= 0) return hipSuccess;
-  if (e.M > 512 || !e.tri) return hipErrorInvalidValue;
-  if ((e.pivot != 0) != (e.backsub != 0)) return hipErrorInvalidValue;   // the two modes built
-  const int M = e.M;
-  const int cend = e.rhs_off + e.nrhs;   // trailing columns run up to the end of the right-hand sides
-  PanelParams p;
-  p.aug = e.aug; p.stride = e.stride; p.lda = e.lda; p.M = M; p.W = e.W; p.pivot = e.pivot;
-  p.piv = e.piv; p.ld = e.ld; p.lndet = e.lndet; p.status = e.status; p.gj = e.backsub != 0 ? 1 : 0;
-  p.tri = e.tri;
-  p.tri_stride = TRI_ELEMS;
-  if (e.backsub) return launch_gj(e, p, cend, M > gj_wide_min_m(), s);   // a solve: Gauss-Jordan
+namespace {
+// Forward elimination without pivoting; with `lower_left` the left block is lower triangular, so
+// the pivot rows' entries right of the panel inside the left block are zeros and so is every
+// left-block product: the pivot-block products and trailing updates cover the right-hand block only.
+hipError_t launch_forward(const ElimParams& e, PanelParams p, bool lower_left, hipStream_t s) {
+  const int M = e.M, cend = e.rhs_off + e.nrhs;
   hipError_t err;
   for (int j0 = 0; j0 < M; j0 += NB) {
     const int jb = M - j0 < NB ? M - j0 : NB;
@@ -923,13 +917,39 @@ hipError_t launch_elim(const ElimParams& e, hipStream_t s) {
     if ((err = launch_panel(M - j0, e.W, p, s, panel_kernel<64>, panel_kernel<128>, panel_kernel<256>,
                             panel_kernel<512>)) != hipSuccess)
       return err;
-    const int c0 = j0 + jb;
-    const int ncols = cend - c0;
+    const int c0 = lower_left ? e.rhs_off : j0 + jb, ncols = cend - c0;
     if (ncols <= 0) continue;
     if ((err = launch_zgemm(tri_params(e, e.tri + TRI_T1, NB, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
       return err;
-    if (M - c0 > 0 && (err = launch_zgemm(update_params(e, c0, M - c0, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
+    if (M - j0 - jb > 0 &&
+        (err = launch_zgemm(update_params(e, j0 + jb, M - j0 - jb, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
       return err;
   }
   return hipSuccess;
+}
+
+PanelParams panel_params(const ElimParams& e) {
+  PanelParams p;
+  p.aug = e.aug; p.stride = e.stride; p.lda = e.lda; p.M = e.M; p.W = e.W; p.pivot = e.pivot;
+  p.piv = e.piv; p.ld = e.ld; p.lndet = e.lndet; p.status = e.status; p.gj = e.backsub != 0 ? 1 : 0;
+  p.tri = e.tri;
+  p.tri_stride = TRI_ELEMS;
+  return p;
+}
+}  // namespace
+
+hipError_t launch_elim_lower(const ElimParams& e, hipStream_t s) {
+  if (e.W <= 0 || e.M <= 0) return hipSuccess;
+  if (e.M > 512 || !e.tri || e.pivot || e.backsub || e.rhs_off < e.M) return hipErrorInvalidValue;
+  return launch_forward(e, panel_params(e), true, s);
+}
+
+hipError_t launch_elim(const ElimParams& e, hipStream_t s) {
+  if (e.W <= 0 || e.M <= 0) return hipSuccess;
+  if (e.M > 512 || !e.tri) return hipErrorInvalidValue;
+  if ((e.pivot != 0) != (e.backsub != 0)) return hipErrorInvalidValue;   // the two modes built
+  const int cend = e.rhs_off + e.nrhs;   // trailing columns run up to the end of the right-hand sides
+  const PanelParams p = panel_params(e);
+  if (e.backsub) return launch_gj(e, p, cend, e.M > gj_wide_min_m(), s);   // a solve: Gauss-Jordan
+  return launch_forward(e, p, false, s);
 }

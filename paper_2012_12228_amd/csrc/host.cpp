@@ -687,7 +687,7 @@ int stabilise(ftafqmc_ctx* h, HostSys& s, SysDev& d, hipStream_t st) {
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_elim(e, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_finish_a(d, st); }));
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_build_ti(d, st); }));
-  HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_elim(e, st); }));
+  HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_elim_lower(e, st); }));   // Ru^T is lower triangular
   HIPCHK(timed(h, FTAFQMC_PROF_STAB, st, [&] { return launch_stab_finish_b(d, st); }));
   return FTAFQMC_OK;
 }
@@ -953,7 +953,7 @@ int doubled_push(ftafqmc_ctx* h, HostSys& s, hipStream_t st, bool with_inverse) 
     SysDev pv = dd;
     pv.Ti = t.Tid;
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_stab_build_ti(pv, st); }));
-    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_elim(e, st); }));
+    HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_elim_lower(e, st); }));   // Ru^T lower triangular
     HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_stab_finish_b(pv, st); }));
   }
   HIPCHK(timed(h, FTAFQMC_PROF_BACKWARD, st, [&] { return launch_permute_rows(t, st); }));

@@ -49,6 +49,9 @@ struct ElimParams {
   double2* tri;    // [W][elim_tri_elems(M)] inverse of the current pivot block (workspace)
 };
 hipError_t launch_elim(const ElimParams& p, hipStream_t s);
+// Forward elimination (no pivoting, no back-substitution) of [L | R] with L lower triangular:
+// the same result as launch_elim, the products over L's zero upper part skipped.
+hipError_t launch_elim_lower(const ElimParams& p, hipStream_t s);
 size_t elim_tri_elems(int M);
 
 // Per-system constant tables and per-walker state, as device pointers.
