@@ -948,7 +948,9 @@ template <bool WITHX> hipError_t launch_exchange(const SysDev& s, double2* X, hi
   const size_t shm = (size_t)s.M * (sizeof(double2) + sizeof(double) + sizeof(int)) +
                      (size_t)s.grid_dim * s.grid_dim * s.grid_dim * sizeof(short) + 16;
   if (s.M <= 64 * 2) exchange_kernel<2, WITHX><<<tiles_blocks(s, s.M), NT, shm, st>>>(s, X);
+  else if (s.M <= 64 * 3) exchange_kernel<3, WITHX><<<tiles_blocks(s, s.M), NT, shm, st>>>(s, X);
   else if (s.M <= 64 * 4) exchange_kernel<4, WITHX><<<tiles_blocks(s, s.M), NT, shm, st>>>(s, X);
+  else if (s.M <= 64 * 6) exchange_kernel<6, WITHX><<<tiles_blocks(s, s.M), NT, shm, st>>>(s, X);
   else if (s.M <= 64 * 8) exchange_kernel<8, WITHX><<<tiles_blocks(s, s.M), NT, shm, st>>>(s, X);
   else return hipErrorInvalidValue;
   return hipGetLastError();
