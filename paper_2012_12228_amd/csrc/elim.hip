@@ -905,25 +905,59 @@ hipError_t launch_gj(const ElimParams& e, PanelParams p, int cend, bool wide, hi
 }  // namespace
 
 namespace {
+hipError_t forward_panel(const ElimParams& e, PanelParams p, int j0, int jb, double2* tri, hipStream_t s) {
+  p.j0 = j0; p.jb = jb; p.tri = tri;
+  return launch_panel(e.M - j0, e.W, p, s, panel_kernel<64>, panel_kernel<128>, panel_kernel<256>,
+                      panel_kernel<512>);
+}
+
 // Forward elimination without pivoting; with `lower_left` the left block is lower triangular, so
 // the pivot rows' entries right of the panel inside the left block are zeros and so is every
 // left-block product: the pivot-block products and trailing updates cover the right-hand block only.
+// Above GJ_WIDE_MIN_M rows (as for the solve) two 32-column panels make one step with a K = 64
+// trailing update: the first panel's step reaches the second half's columns only, and the
+// combined inverse of the 64-column unit lower block, [[T1, 0], [-T2 L21 T1, T2]], comes from the
+// combine kernel (L21 being the first panel's multipliers in the second half's rows).
 hipError_t launch_forward(const ElimParams& e, PanelParams p, bool lower_left, hipStream_t s) {
   const int M = e.M, cend = e.rhs_off + e.nrhs;
+  const bool wide = M > gj_wide_min_m();
   hipError_t err;
-  for (int j0 = 0; j0 < M; j0 += NB) {
+  for (int j0 = 0; j0 < M;) {
+    if (wide && M - j0 > NB) {
+      const int jb2 = M - j0 - NB < NB ? M - j0 - NB : NB, kb = NB + jb2, c2 = j0 + NB;
+      if ((err = forward_panel(e, p, j0, NB, e.tri + TRI_T1, s)) != hipSuccess) return err;
+      if (!lower_left) {                   // (lower triangular: those columns of the pivot rows are zero)
+        if ((err = launch_zgemm(tri_params(e, e.tri + TRI_T1, NB, j0, NB, c2, jb2), GEMM_Z64, s)) != hipSuccess) return err;
+        if ((err = launch_zgemm(update_params(e, c2, M - c2, j0, NB, c2, jb2), GEMM_Z64, s)) != hipSuccess) return err;
+      }
+      if ((err = forward_panel(e, p, c2, jb2, e.tri + TRI_T2, s)) != hipSuccess) return err;
+      CombineParams cp;
+      cp.aug = e.aug; cp.stride = e.stride; cp.lda = e.lda; cp.tri = e.tri; cp.tri_stride = TRI_ELEMS;
+      cp.j0 = j0; cp.jb2 = jb2; cp.W = e.W;
+      gj_combine_kernel<<<e.W, 256, 0, s>>>(cp);
+      if ((err = hipGetLastError()) != hipSuccess) return err;
+      const int c0 = lower_left ? e.rhs_off : j0 + kb, ncols = cend - c0;
+      if (ncols > 0) {
+        if ((err = launch_zgemm(tri_params(e, e.tri + TRI_TL, 2 * NB, j0, kb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
+          return err;
+        if (M - j0 - kb > 0 &&
+            (err = launch_zgemm(update_params(e, j0 + kb, M - j0 - kb, j0, kb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
+          return err;
+      }
+      j0 += kb;
+      continue;
+    }
     const int jb = M - j0 < NB ? M - j0 : NB;
-    p.j0 = j0; p.jb = jb;
-    if ((err = launch_panel(M - j0, e.W, p, s, panel_kernel<64>, panel_kernel<128>, panel_kernel<256>,
-                            panel_kernel<512>)) != hipSuccess)
-      return err;
+    if ((err = forward_panel(e, p, j0, jb, e.tri + TRI_T1, s)) != hipSuccess) return err;
     const int c0 = lower_left ? e.rhs_off : j0 + jb, ncols = cend - c0;
-    if (ncols <= 0) continue;
-    if ((err = launch_zgemm(tri_params(e, e.tri + TRI_T1, NB, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
-      return err;
-    if (M - j0 - jb > 0 &&
-        (err = launch_zgemm(update_params(e, j0 + jb, M - j0 - jb, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
-      return err;
+    if (ncols > 0) {
+      if ((err = launch_zgemm(tri_params(e, e.tri + TRI_T1, NB, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
+        return err;
+      if (M - j0 - jb > 0 &&
+          (err = launch_zgemm(update_params(e, j0 + jb, M - j0 - jb, j0, jb, c0, ncols), GEMM_Z64, s)) != hipSuccess)
+        return err;
+    }
+    j0 += jb;
   }
   return hipSuccess;
 }
