@@ -22,6 +22,9 @@
 //           columns and reads them completely before it writes);
 //   update  A22 -= L21 U12 as a batched MFMA GEMM over the contiguous column range
 //           [j0+NB, rhs_off+nrhs) (the zero padding between the two blocks stays zero).
+//   Above 256 rows two panels make one step with K = 64 (the combined inverse of the 64-column
+//   unit lower block from the combine kernel); with a lower-triangular left block (the T^{-1}
+//   update) the products cover the right-hand block only.
 // Gauss-Jordan (the solve with right-hand sides): the panel kernel leaves the panel columns
 // untouched and returns A11^{-1} of the pivot block; the row exchanges run
 // over the panel columns too, the pivot rows become P = A11^{-1} [A12 | R1] in place, and every
